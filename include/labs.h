@@ -1,0 +1,188 @@
+/*
+ * labs.h -- C ABI of the MI355X (gfx950) LABS dual-step library, liblabs.so.
+ *
+ * The operations follow the problem statement of Psenicnik, Mlinaric, Brest and
+ * Boskovic, "Dual-Step Optimization for Binary Sequences with High Merit
+ * Factors" (arXiv 2409.07222):
+ *   Sec. 1    S = (s_1..s_L), s_i in {+1,-1}; C_k(S) = sum_{i=1}^{L-k} s_i s_{i+k};
+ *             E(S) = sum_{k=1}^{L-1} C_k^2; Eq. (1) F = L^2 / (2E).
+ *   Eq. (2)   skew-symmetry for L = 2k+1: s_{k+1+i} = (-1)^i s_{k+1-i}, i = 1..k.
+ *   Eq. (3)   restriction classes: s_1..s_p fixed, s_{p+1}..s_{k+1} free, the
+ *             last k elements set by Eq. (2).
+ *   Alg. 1    first step: walks over skew neighbours (one free element and its
+ *             Eq. (2) partner flipped), best neighbour each step, sieve by energy.
+ *   Alg. 2    second step: best-first search over all L single flips, driven by
+ *             a priority queue keyed by E.
+ *
+ * Conventions shared by every entry point
+ *   Packed sequences: W = labs_words(L) = ceil(L/32) uint32 words per sequence;
+ *     s_i is bit 31 - ((i-1) mod 32) of word (i-1)/32, set for +1, clear for -1;
+ *     the unused low bits of the last word must be zero.  Sequence j of a batch
+ *     starts at word j*W.  Read MSB first the words spell s_1, s_2, ... -- the
+ *     digit order of the paper's hexadecimal coding (Sec. 4).
+ *   Order of sequences ("key order"): ascending (E, key) where key is the packed
+ *     words compared as unsigned integers, word 0 first.
+ *   Pointers: every array argument is DEVICE memory unless marked "host".  The
+ *     caller owns all memory; the library allocates nothing except where an entry
+ *     point says so.
+ *   Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Calls enqueue work and return; results are valid once the stream has
+ *     synchronised, except where an entry point says it synchronises.
+ *   Errors: arguments are validated before anything is enqueued; on
+ *     LABS_E_INVALID nothing was written.  HIP failures return LABS_E_DEVICE.
+ *     labs_last_error() returns a description of the last failure on the
+ *     calling thread.  No C++ exception crosses this interface.
+ *   Limits: odd L for skew operations; 1 <= L <= 1023 for energies and deltas;
+ *     first-step walks need 5 <= L <= 639 (at most 10 words of even lags);
+ *     |C_k| <= L-1 and E < 2^31 for every L accepted.
+ */
+#ifndef LABS_H
+#define LABS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LABS_ABI_VERSION 1
+
+typedef int32_t labs_status;
+enum {
+    LABS_OK = 0,
+    LABS_E_INVALID = -1,     /* bad argument; nothing enqueued */
+    LABS_E_DEVICE = -2,      /* HIP runtime or launch failure */
+    LABS_E_NOMEM = -3,       /* workspace too small */
+    LABS_E_UNSUPPORTED = -4  /* valid request outside what this build implements */
+};
+
+int32_t labs_abi_version(void);
+const char* labs_status_str(labs_status s);
+/* Text of the last failure on this thread ("" when none).  The pointer stays
+ * valid until the next library call on the same thread. */
+const char* labs_last_error(void);
+/* ceil(L/32): words per packed sequence. */
+int32_t labs_words(int32_t L);
+
+/* ----------------------------------------------------------------------------
+ * labs_energy -- Sec. 1 definitions: E(S) and optionally every C_k(S).
+ *   L       sequence length, 1..1023
+ *   n       number of sequences (0 allowed: nothing is done)
+ *   seqs    [n*W] packed sequences (device, read)
+ *   E       [n] int32 energies (device, written)
+ *   C       [n*(L-1)] int32, C_1..C_{L-1} of sequence j at j*(L-1) (device,
+ *           written; may be NULL)
+ */
+labs_status labs_energy(int32_t L, int64_t n, const uint32_t* seqs, int32_t* E, int32_t* C,
+                        void* stream);
+
+/* ----------------------------------------------------------------------------
+ * labs_flip_deltas -- exact energy change of every neighbour, E(S') - E(S).
+ *   skew = 0: the L single flips of Alg. 2's neighbourhood; dE is [n*L], entry
+ *             j*L + (i-1) for the flip of s_i.  p is ignored.
+ *   skew = 1: the skew neighbours of Alg. 1 over the free positions of Eq. (3):
+ *             a = p+1..k+1 (k = (L-1)/2, L odd), flipping s_a together with its
+ *             Eq. (2) partner s_{L+1-a} (the centre a = k+1 alone); dE is
+ *             [n*(k+1-p)], entry j*(k+1-p) + (a-p-1).  The change is exact for
+ *             any input sequence, skew-symmetric or not.
+ */
+labs_status labs_flip_deltas(int32_t L, int32_t p, int32_t skew, int64_t n,
+                             const uint32_t* seqs, int32_t* dE, void* stream);
+
+/* ----------------------------------------------------------------------------
+ * First step (Alg. 1 with a tabu tenure in place of the Bloom filter).
+ *
+ * Walker w (global id walker_begin + j, j = 0..n_walkers-1) starts from a
+ * seeded skew-symmetric sequence in a seeded restriction class: it reads the
+ * SplitMix64 stream (Steele, Lea, Flood 2014) whose state starts at
+ *   key = mix(seed ^ mix((L << 32) ^ (w + 1))),  mix = SplitMix64's finaliser,
+ * output i (i = 0, 1, ...) being mix(key + (i+1) * 0x9E3779B97F4A7C15).
+ * Output i-1 sets s_i (+1 when its top bit is set) for i = 1..k+1, except that
+ * s_1 = +1 when p >= 1; output k+1 draws the tenure
+ * tenure_lo + (output mod (tenure_hi - tenure_lo + 1)).  Eq. (2) sets the rest.
+ * Then, for t = 1..steps: every free position a = p+1..k+1 is evaluated
+ * (dE_a = E(flip_skew_a S) - E(S)); the admissible ones are those with
+ * tabu_until[a] < t (initially 0); the walker takes the admissible a with the
+ * lowest (dE_a, a), even uphill, sets tabu_until[a] = t + tenure and E += dE_a.
+ * With no admissible position the walk stops; its remaining trajectory is -1.
+ * Sieve: after each move, a sequence with E <= e_max is offered to the pool.
+ * Results depend only on (seed, L, p, tenures, steps, walker id): any split of
+ * the walker range gives the same per-walker results.
+ */
+typedef struct {
+    int32_t L;            /* odd, 5..639 */
+    int32_t p;            /* restriction prefix length, 0..k-1 (at least 2 free positions) */
+    int32_t steps;        /* steps per walker; 0 = the paper's default 4(L+1) */
+    int32_t tenure_lo;    /* tabu tenure range, 0 <= lo <= hi < k+1-p */
+    int32_t tenure_hi;
+    int32_t e_max;        /* sieve threshold (E <= e_max enters the pool); < 0: no pool */
+    int64_t walker_begin; /* first global walker id, >= 0 */
+    int64_t n_walkers;    /* >= 1; walker ids must stay below 2^31 */
+    uint64_t seed;
+    uint32_t flags;       /* bit 0 LABS_POOL_WALKER_BEST: also offer each walker's best
+                             sequence (the first step reaching its lowest energy, the
+                             initial sequence counted as step 0) to the pool at the end */
+    int32_t reserved;     /* must be 0 */
+} labs_step1_cfg;
+
+#define LABS_POOL_WALKER_BEST 1u
+
+/* Candidate pool (caller-allocated, device).  On return from a call that fills
+ * it, the pool holds the min(capacity, D) smallest, in key order, of the D
+ * distinct sequences in (its previous contents) U (this call's offers), sorted
+ * ascending; `walker`/`step` of an entry are those of its earliest offer in
+ * (walker, step) order.  Overflow is not an error: *dropped grows by the number
+ * of distinct sequences cut by the capacity. */
+typedef struct {
+    uint32_t* seqs;     /* [capacity*W] */
+    int32_t* E;         /* [capacity] */
+    int64_t* walker;    /* [capacity], may be NULL */
+    int32_t* step;      /* [capacity], may be NULL */
+    int64_t capacity;   /* >= 1 */
+    int64_t* count;     /* device int64: entries held (read on entry, written) */
+    int64_t* dropped;   /* device int64: incremented */
+} labs_pool;
+
+typedef struct {
+    uint32_t* final_seqs;  /* [n*W] sequence after the last step */
+    int32_t* final_E;      /* [n] */
+    uint32_t* best_seqs;   /* [n*W] first sequence of least energy (may be NULL) */
+    int32_t* best_E;       /* [n] (may be NULL) */
+    int32_t* best_step;    /* [n] step of best (0 = initial), may be NULL */
+    int32_t* traj_E;       /* [n*steps] energy after step t at j*steps + t-1, may be NULL */
+    int64_t* flip_evals;   /* device int64, incremented by (steps taken)*(k+1-p) per walker;
+                              may be NULL */
+} labs_step1_out;
+
+/* Workspace bytes for labs_walk_step1 with these configurations and pools of at
+ * most pool_capacity entries (ignored when no cfg has e_max >= 0).  Host call. */
+labs_status labs_walk_step1_workspace(const labs_step1_cfg* cfg, int32_t n_cfg,
+                                      int64_t pool_capacity, size_t* bytes);
+
+/* Run the first step.  cfg, pools and outs are HOST arrays of n_cfg structs
+ * (n_cfg = 1 in this build); pools may be NULL when every cfg has e_max < 0.
+ * prop must be NULL (plain walker).  When a pool is used the call synchronises
+ * `stream` between walk segments and returns after the pool is final. */
+labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void* prop,
+                            labs_pool* pools, labs_step1_out* outs, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* ----------------------------------------------------------------------------
+ * labs_pool_topk -- the k smallest distinct sequences of a pool in key order.
+ *   pool     as above; reads pool->count (entries 0..count-1, any order, duplicates
+ *            allowed)
+ *   out_seqs [k*W], out_E [k] (device, written), out_n (device int64: number written,
+ *            min(k, distinct))
+ *   ws       workspace of labs_pool_topk_workspace(pool->capacity, L) bytes
+ * Synchronises `stream` (it reads pool->count).
+ */
+labs_status labs_pool_topk_workspace(int64_t capacity, int32_t L, size_t* bytes);
+labs_status labs_pool_topk(const labs_pool* pool, int32_t L, int32_t k, uint32_t* out_seqs,
+                           int32_t* out_E, int64_t* out_n, void* ws, size_t ws_bytes,
+                           void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LABS_H */

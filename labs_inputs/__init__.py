@@ -114,7 +114,7 @@ def unpack(packed: np.ndarray, L: int) -> np.ndarray:
     if one:
         w = w[None, :]
     shifts = (31 - np.arange(32, dtype=np.uint32))[None, None, :]
-    bits = ((w[:, :, None] >> shifts) & 1).reshape(w.shape[0], -1)[:, :L]
+    bits = ((w[:, :, None] >> shifts) & 1).reshape(w.shape[0], w.shape[1] * 32)[:, :L]
     out = (bits.astype(np.int8) * 2 - 1).astype(np.int8)
     return out[0] if one else out
 

@@ -212,7 +212,12 @@ int64_t or_walk_one(int32_t L, int32_t p, int32_t steps, int32_t tenure_lo, int3
 
     int32_t t = 1;
     for (; t <= steps; ++t) {
-        for (int32_t a = p + 1; a <= k + 1; ++a) delta[a - p - 1] = or_delta_skew(L, s, a);
+        int64_t e_here = or_energy(L, s, NULL);
+        for (int32_t a = p + 1; a <= k + 1; ++a) {
+            or_flip_skew(L, s, a);
+            delta[a - p - 1] = or_energy(L, s, NULL) - e_here;
+            or_flip_skew(L, s, a);
+        }
         int32_t best_a = -1;
         for (int32_t a = p + 1; a <= k + 1; ++a) {
             if (tabu_until[a - p - 1] >= t) continue;

@@ -1,0 +1,392 @@
+// Host side of the C ABI (include/labs.h): validation, workspace layout and
+// orchestration.  Every computation is enqueued on the caller's stream.
+#include "labs_internal.h"
+
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+namespace labsdev {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+void clear_error() { g_err.clear(); }
+labs_status invalid(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return LABS_E_INVALID;
+}
+labs_status device_error(hipError_t e, const char* what) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return LABS_E_DEVICE;
+}
+const char* last_error() { return g_err.c_str(); }
+
+}  // namespace labsdev
+
+using namespace labsdev;
+
+namespace {
+
+constexpr int kSegMax = 4096;    // walk steps per launch without a pool
+constexpr int kSegPool0 = 256;   // first segment length with a pool
+
+hipStream_t S(void* s) { return (hipStream_t)s; }
+
+labs_status check_step1_cfg(const labs_step1_cfg& c) {
+    if (c.L < 5 || c.L > 639 || (c.L & 1) == 0)
+        return invalid("first-step L must be odd in [5, 639], got %d", c.L);
+    const int k = (c.L - 1) / 2;
+    if (c.p < 0 || c.p > k - 1) return invalid("p must be in [0, k-1] = [0, %d], got %d", k - 1, c.p);
+    const int nf = k + 1 - c.p;
+    if (c.steps < 0) return invalid("steps must be >= 0");
+    if (c.tenure_lo < 0 || c.tenure_hi < c.tenure_lo || c.tenure_hi >= nf)
+        return invalid("tenure range must satisfy 0 <= lo <= hi < %d (free positions)", nf);
+    if (c.walker_begin < 0 || c.n_walkers < 1 || c.walker_begin + c.n_walkers > (int64_t)INT32_MAX)
+        return invalid("walker range must be non-empty, non-negative and below 2^31");
+    if (c.flags & ~LABS_POOL_WALKER_BEST) return invalid("unknown flags 0x%x", c.flags);
+    if (c.reserved != 0) return invalid("reserved must be 0");
+    if (!walk_shape_supported(c.L, c.p)) return invalid("no walker kernel for L=%d p=%d", c.L, c.p);
+    return LABS_OK;
+}
+
+int64_t staging_cap(const labs_step1_cfg& c) {
+    int64_t s = 64 * c.n_walkers;
+    if (s < (1 << 16)) s = 1 << 16;
+    if (s > (1 << 22)) s = 1 << 22;
+    return s;
+}
+
+bool uses_pool(const labs_step1_cfg& c) {
+    return c.e_max >= 0 || (c.flags & LABS_POOL_WALKER_BEST);
+}
+
+struct WalkLayout {
+    size_t state_bytes = 0;   // one contiguous block, checkpointed as a unit
+    size_t off_seq = 0, off_E = 0, off_ten = 0, off_halt = 0, off_tabu = 0, off_bE = 0, off_bT = 0,
+           off_bS = 0;
+    int64_t S = 0, cap = 0;
+    int32_t KW = 0;
+    size_t total = 0;
+};
+
+WalkLayout walk_layout(const labs_step1_cfg& c, int64_t pool_cap, bool pool) {
+    WalkLayout lo;
+    const int64_t n = c.n_walkers;
+    const int W = words_of(c.L);
+    const int k = (c.L - 1) / 2;
+    const int nf = k + 1 - c.p;
+    size_t o = 0;
+    auto put = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes, 256);
+        return at;
+    };
+    lo.off_seq = put(sizeof(uint32_t) * n * W);
+    lo.off_E = put(sizeof(int32_t) * n);
+    lo.off_ten = put(sizeof(int32_t) * n);
+    lo.off_halt = put(sizeof(int32_t) * n);
+    lo.off_tabu = put(sizeof(int32_t) * n * nf);
+    lo.off_bE = put(sizeof(int32_t) * n);
+    lo.off_bT = put(sizeof(int32_t) * n);
+    lo.off_bS = put(sizeof(uint32_t) * n * W);
+    lo.state_bytes = o;
+    size_t total = o;
+    if (pool) {
+        lo.S = staging_cap(c);
+        if (lo.S < n) lo.S = n;   // room for one offer per walker
+        lo.cap = pool_cap;
+        lo.KW = W + 3;
+        total += o;                                                           // checkpoint
+        total += align_up(sizeof(uint32_t) * lo.KW * (lo.S + lo.cap), 256);   // records
+        total += 512;                                                         // counters
+        total += compact_workspace_bytes(lo.S + lo.cap, lo.KW);
+    }
+    lo.total = total + 4096;
+    return lo;
+}
+
+labs_status check_pool(const labs_pool* pl) {
+    if (!pl) return invalid("a pool is required when e_max >= 0 or LABS_POOL_WALKER_BEST is set");
+    if (pl->capacity < 1 || pl->capacity > (int64_t)INT32_MAX)
+        return invalid("pool capacity must be in [1, 2^31)");
+    if (!pl->seqs || !pl->E || !pl->count || !pl->dropped)
+        return invalid("pool seqs, E, count and dropped must not be NULL");
+    return LABS_OK;
+}
+
+// Host scalars read back between segments.
+struct HostPair {
+    uint32_t st_count;
+    int64_t pool_count;
+};
+
+}  // namespace
+
+extern "C" {
+
+int32_t labs_abi_version(void) { return LABS_ABI_VERSION; }
+
+const char* labs_status_str(labs_status s) {
+    switch (s) {
+        case LABS_OK: return "ok";
+        case LABS_E_INVALID: return "invalid argument";
+        case LABS_E_DEVICE: return "device error";
+        case LABS_E_NOMEM: return "workspace too small";
+        case LABS_E_UNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+const char* labs_last_error(void) { return last_error(); }
+
+int32_t labs_words(int32_t L) { return L <= 0 ? 0 : words_of(L); }
+
+labs_status labs_energy(int32_t L, int64_t n, const uint32_t* seqs, int32_t* E, int32_t* C,
+                        void* stream) {
+    clear_error();
+    if (L < 1 || L > 1023) return invalid("L must be in [1, 1023], got %d", L);
+    if (n < 0 || n > (int64_t)INT32_MAX) return invalid("n must be in [0, 2^31)");
+    if (n > 0 && (!seqs || !E)) return invalid("seqs and E must not be NULL");
+    return launch_energy(L, n, seqs, E, L > 1 ? C : nullptr, S(stream));
+}
+
+labs_status labs_flip_deltas(int32_t L, int32_t p, int32_t skew, int64_t n, const uint32_t* seqs,
+                             int32_t* dE, void* stream) {
+    clear_error();
+    if (L < 1 || L > 1023) return invalid("L must be in [1, 1023], got %d", L);
+    if (skew != 0 && skew != 1) return invalid("skew must be 0 or 1");
+    if (skew) {
+        if ((L & 1) == 0 || L < 3) return invalid("skew flips need odd L >= 3");
+        const int k = (L - 1) / 2;
+        if (p < 0 || p > k) return invalid("p must be in [0, k]");
+    }
+    if (n < 0 || n > (int64_t)INT32_MAX) return invalid("n must be in [0, 2^31)");
+    if (n > 0 && (!seqs || !dE)) return invalid("seqs and dE must not be NULL");
+    return launch_flip_deltas(L, p, skew, n, seqs, dE, S(stream));
+}
+
+labs_status labs_walk_step1_workspace(const labs_step1_cfg* cfg, int32_t n_cfg, int64_t pool_capacity,
+                                      size_t* bytes) {
+    clear_error();
+    if (!cfg || !bytes) return invalid("cfg and bytes must not be NULL");
+    if (n_cfg != 1) return invalid("this build runs one configuration per call (n_cfg = 1)");
+    labs_status s = check_step1_cfg(cfg[0]);
+    if (s != LABS_OK) return s;
+    const bool pool = uses_pool(cfg[0]);
+    if (pool && (pool_capacity < 1 || pool_capacity > (int64_t)INT32_MAX))
+        return invalid("pool capacity must be in [1, 2^31)");
+    *bytes = walk_layout(cfg[0], pool ? pool_capacity : 0, pool).total;
+    return LABS_OK;
+}
+
+labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void* prop,
+                            labs_pool* pools, labs_step1_out* outs, void* ws, size_t ws_bytes,
+                            void* stream) {
+    clear_error();
+    if (!cfg || !outs) return invalid("cfg and outs must not be NULL");
+    if (n_cfg != 1) return invalid("this build runs one configuration per call (n_cfg = 1)");
+    if (prop) return invalid("prop must be NULL for the plain walker");
+    const labs_step1_cfg c = cfg[0];
+    labs_status s = check_step1_cfg(c);
+    if (s != LABS_OK) return s;
+    const labs_step1_out o = outs[0];
+    if (!o.final_seqs || !o.final_E) return invalid("final_seqs and final_E must not be NULL");
+    const bool pool = uses_pool(c);
+    labs_pool pl{};
+    if (pool) {
+        if ((s = check_pool(pools)) != LABS_OK) return s;
+        pl = pools[0];
+    }
+    if (!ws) return invalid("workspace must not be NULL");
+    const WalkLayout lo = walk_layout(c, pool ? pl.capacity : 0, pool);
+    if (ws_bytes < lo.total) {
+        set_error("workspace needs %zu bytes, got %zu", lo.total, ws_bytes);
+        return LABS_E_NOMEM;
+    }
+    hipStream_t st = S(stream);
+    const int L = c.L, k = (L - 1) / 2, W = words_of(L);
+    const int steps = c.steps ? c.steps : 4 * (L + 1);
+    char* base = (char*)ws;
+    WalkArgs A{};
+    A.L = L;
+    A.p = c.p;
+    A.k = k;
+    A.nf = k + 1 - c.p;
+    A.W = W;
+    A.steps_total = steps;
+    A.n = c.n_walkers;
+    A.walker_begin = c.walker_begin;
+    A.seed = c.seed;
+    A.tenure_lo = c.tenure_lo;
+    A.tenure_hi = c.tenure_hi;
+    A.seq = (uint32_t*)(base + lo.off_seq);
+    A.E = (int32_t*)(base + lo.off_E);
+    A.tenure = (int32_t*)(base + lo.off_ten);
+    A.halted = (int32_t*)(base + lo.off_halt);
+    A.tabu = (int32_t*)(base + lo.off_tabu);
+    A.bestE = (int32_t*)(base + lo.off_bE);
+    A.bestT = (int32_t*)(base + lo.off_bT);
+    A.bestSeq = (uint32_t*)(base + lo.off_bS);
+    A.traj = o.traj_E;
+    A.e_max = c.e_max;
+    A.thr = nullptr;
+
+    if ((s = launch_walker_init(A, st)) != LABS_OK) return s;
+
+    if (!pool) {
+        for (int t = 0; t < steps; t += kSegMax) {
+            A.t0 = t;
+            A.t1 = t + kSegMax < steps ? t + kSegMax : steps;
+            if ((s = launch_walk(A, st)) != LABS_OK) return s;
+        }
+        A.t1 = steps;
+        return launch_walk_outputs(A, o, st);
+    }
+
+    // ---- pool mode: segments, compaction after each, exact retry on overflow
+    Carve cv(base + lo.state_bytes, ws_bytes - lo.state_bytes);
+    char* ckpt = cv.take<char>(lo.state_bytes);
+    RecBuf rb;
+    rb.KW = lo.KW;
+    rb.stride = lo.S + lo.cap;
+    rb.rec = cv.take<uint32_t>((size_t)rb.KW * rb.stride);
+    uint32_t* st_count = cv.take<uint32_t>(16);
+    int32_t* thr = (int32_t*)(st_count + 8);
+    const size_t cws_bytes = compact_workspace_bytes(lo.S + lo.cap, lo.KW);
+    void* cws = cv.take<char>(cws_bytes);
+    if (!cv.ok()) return invalid("workspace layout overflow");
+    A.thr = thr;
+    A.rec = rb.rec;
+    A.rec_stride = rb.stride;
+    A.st_count = st_count;
+    A.st_cap = (uint32_t)lo.S;
+    const int32_t e_max_eff = c.e_max >= 0 ? c.e_max : INT32_MAX;
+
+    HostPair hp{};
+    auto read_counts = [&]() -> labs_status {
+        LABS_HIP(hipMemcpyAsync(&hp.st_count, st_count, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        LABS_HIP(hipMemcpyAsync(&hp.pool_count, pl.count, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        LABS_HIP(hipStreamSynchronize(st));
+        return LABS_OK;
+    };
+    // initial compaction: normalise the pool's previous contents, set the threshold
+    LABS_HIP(hipMemsetAsync(st_count, 0, 64, st));
+    if ((s = read_counts()) != LABS_OK) return s;
+    if (hp.pool_count < 0 || hp.pool_count > pl.capacity) return invalid("pool count out of range");
+    if ((s = pool_to_rec(pl, hp.pool_count, W, rb, 0, st)) != LABS_OK) return s;
+    if ((s = compact_records(rb, W, hp.pool_count, pl.capacity, pl.seqs, pl.E, pl.walker, pl.step,
+                             pl.count, pl.dropped, nullptr, thr, e_max_eff, cws, cws_bytes, st)) != LABS_OK)
+        return s;
+
+    int seg = kSegPool0;
+    int t = 0;
+    while (c.e_max >= 0 && t < steps) {
+        const int len = seg < steps - t ? seg : steps - t;
+        LABS_HIP(hipMemcpyAsync(ckpt, base, lo.state_bytes, hipMemcpyDeviceToDevice, st));
+        LABS_HIP(hipMemsetAsync(st_count, 0, sizeof(uint32_t), st));
+        A.t0 = t;
+        A.t1 = t + len;
+        if ((s = launch_walk(A, st)) != LABS_OK) return s;
+        if ((s = read_counts()) != LABS_OK) return s;
+        if (hp.st_count > (uint32_t)lo.S) {
+            // staging overflowed: restore and redo the segment in halves
+            LABS_HIP(hipMemcpyAsync(base, ckpt, lo.state_bytes, hipMemcpyDeviceToDevice, st));
+            if (len == 1) return invalid("staging too small for one step of offers");
+            seg = len / 2;
+            continue;
+        }
+        const int64_t nst = hp.st_count;
+        if ((s = pool_to_rec(pl, hp.pool_count, W, rb, nst, st)) != LABS_OK) return s;
+        if ((s = compact_records(rb, W, nst + hp.pool_count, pl.capacity, pl.seqs, pl.E, pl.walker,
+                                 pl.step, pl.count, pl.dropped, nullptr, thr, e_max_eff, cws, cws_bytes,
+                                 st)) != LABS_OK)
+            return s;
+        t += len;
+        if ((int64_t)nst < lo.S / 8 && seg < kSegMax) seg *= 2;
+    }
+    if (c.e_max < 0) {
+        for (int tt = 0; tt < steps; tt += kSegMax) {
+            A.t0 = tt;
+            A.t1 = tt + kSegMax < steps ? tt + kSegMax : steps;
+            if ((s = launch_walk(A, st)) != LABS_OK) return s;
+        }
+    }
+    if (c.flags & LABS_POOL_WALKER_BEST) {
+        LABS_HIP(hipMemsetAsync(st_count, 0, sizeof(uint32_t), st));
+        if ((s = launch_offer_best(A, st)) != LABS_OK) return s;
+        if ((s = read_counts()) != LABS_OK) return s;
+        const int64_t nst = hp.st_count;
+        if ((s = pool_to_rec(pl, hp.pool_count, W, rb, nst, st)) != LABS_OK) return s;
+        if ((s = compact_records(rb, W, nst + hp.pool_count, pl.capacity, pl.seqs, pl.E, pl.walker,
+                                 pl.step, pl.count, pl.dropped, nullptr, thr, e_max_eff, cws, cws_bytes,
+                                 st)) != LABS_OK)
+            return s;
+    }
+    A.t1 = steps;
+    return launch_walk_outputs(A, o, st);
+}
+
+labs_status labs_pool_topk_workspace(int64_t capacity, int32_t L, size_t* bytes) {
+    clear_error();
+    if (!bytes) return invalid("bytes must not be NULL");
+    if (capacity < 0 || capacity > (int64_t)INT32_MAX) return invalid("capacity out of range");
+    if (L < 1 || L > 1023) return invalid("L must be in [1, 1023]");
+    const int32_t KW = words_of(L) + 3;
+    const int64_t n = capacity > 0 ? capacity : 1;
+    *bytes = align_up(sizeof(uint32_t) * KW * n, 256) + compact_workspace_bytes(n, KW) + 4096;
+    return LABS_OK;
+}
+
+labs_status labs_pool_topk(const labs_pool* pool, int32_t L, int32_t k, uint32_t* out_seqs, int32_t* out_E,
+                           int64_t* out_n, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (!pool || !pool->count) return invalid("pool and pool->count must not be NULL");
+    if (L < 1 || L > 1023) return invalid("L must be in [1, 1023]");
+    if (k < 1) return invalid("k must be >= 1");
+    if (!out_seqs || !out_E || !out_n) return invalid("outputs must not be NULL");
+    if (pool->capacity < 0 || pool->capacity > (int64_t)INT32_MAX) return invalid("capacity out of range");
+    size_t need = 0;
+    labs_status s = labs_pool_topk_workspace(pool->capacity, L, &need);
+    if (s != LABS_OK) return s;
+    if (!ws || ws_bytes < need) {
+        set_error("workspace needs %zu bytes, got %zu", need, ws_bytes);
+        return LABS_E_NOMEM;
+    }
+    hipStream_t st = S(stream);
+    int64_t n = 0;
+    LABS_HIP(hipMemcpyAsync(&n, pool->count, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    LABS_HIP(hipStreamSynchronize(st));
+    if (n < 0 || n > pool->capacity) return invalid("pool count %lld out of range", (long long)n);
+    if (n > 0 && (!pool->seqs || !pool->E)) return invalid("pool seqs and E must not be NULL");
+    const int32_t W = words_of(L);
+    Carve cv(ws, ws_bytes);
+    RecBuf rb;
+    rb.KW = W + 3;
+    rb.stride = n > 0 ? n : 1;
+    rb.rec = cv.take<uint32_t>((size_t)rb.KW * rb.stride);
+    const size_t cws_bytes = compact_workspace_bytes(rb.stride, rb.KW);
+    void* cws = cv.take<char>(cws_bytes);
+    if (!cv.ok()) return invalid("workspace layout overflow");
+    if ((s = pool_to_rec(*pool, n, W, rb, 0, st)) != LABS_OK) return s;
+    return compact_records(rb, W, n, k, out_seqs, out_E, nullptr, nullptr, nullptr, nullptr, out_n, nullptr,
+                           INT32_MAX, cws, cws_bytes, st);
+}
+
+}  // extern "C"

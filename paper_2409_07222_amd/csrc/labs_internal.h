@@ -1,0 +1,130 @@
+// Internal declarations of liblabs.so (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/labs.h"
+
+namespace labsdev {
+
+// ---------------------------------------------------------------- host errors
+void set_error(const char* fmt, ...);
+void clear_error();
+labs_status invalid(const char* fmt, ...);   // sets the message, returns LABS_E_INVALID
+labs_status device_error(hipError_t e, const char* what);
+const char* last_error();
+
+#define LABS_HIP(call)                                                      \
+    do {                                                                    \
+        hipError_t _e = (call);                                             \
+        if (_e != hipSuccess) return ::labsdev::device_error(_e, #call);       \
+    } while (0)
+
+#define LABS_LAUNCHED(what)                                                 \
+    do {                                                                    \
+        hipError_t _e = hipGetLastError();                                  \
+        if (_e != hipSuccess) return ::labsdev::device_error(_e, what);        \
+    } while (0)
+
+inline int32_t words_of(int32_t L) { return (L + 31) / 32; }
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over a caller workspace (256-byte aligned slices).
+struct Carve {
+    char* base;
+    size_t size, used;
+    explicit Carve(void* b, size_t s) : base((char*)b), size(s), used(0) {}
+    template <class T> T* take(size_t count) {
+        size_t off = align_up(used, 256);
+        used = off + count * sizeof(T);
+        return (base && used <= size) ? (T*)(base + off) : nullptr;
+    }
+    bool ok() const { return used <= size; }
+};
+
+// ---------------------------------------------------------------- device helpers
+extern "C" __device__ int __ockl_wfred_min_i32(int);
+extern "C" __device__ unsigned int __ockl_wfred_or_u32(unsigned int);
+extern "C" __device__ int __ockl_wfred_add_i32(int);
+extern "C" __device__ unsigned int __ockl_wfred_max_u32(unsigned int);
+
+// SplitMix64 (Steele, Lea, Flood 2014): finaliser and the counter form of its
+// stream, output i of the stream started at `key` is mix(key + (i+1)*gamma).
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t sm64_at(uint64_t key, uint64_t i) {
+    return sm64_mix(key + (i + 1ull) * 0x9E3779B97F4A7C15ull);
+}
+__device__ __forceinline__ uint64_t walker_key(uint64_t seed, int32_t L, int64_t w) {
+    uint64_t lw = ((uint64_t)(uint32_t)L << 32) ^ (uint64_t)(w + 1);
+    return sm64_mix(seed ^ sm64_mix(lw));
+}
+
+// Packed wire format: s_i (1-based) is bit 31-((i-1)&31) of word (i-1)>>5.
+__device__ __forceinline__ int packed_bit(const uint32_t* w, int i) {
+    return (w[(i - 1) >> 5] >> (31 - ((i - 1) & 31))) & 1;
+}
+
+// ---------------------------------------------------------------- launchers
+labs_status launch_energy(int32_t L, int64_t n, const uint32_t* seqs, int32_t* E, int32_t* C,
+                          hipStream_t st);
+labs_status launch_flip_deltas(int32_t L, int32_t p, int32_t skew, int64_t n,
+                               const uint32_t* seqs, int32_t* dE, hipStream_t st);
+
+// Records for sorting/pooling: KW = W + 3 uint32 key words per record, stored
+// word-major: key word q of record i at rec[q*stride + i]. Word 0 is E, words
+// 1..W the packed sequence, word W+1 the walker id, word W+2 the step.
+struct RecBuf {
+    uint32_t* rec;
+    int64_t stride;
+    int32_t KW;
+};
+
+size_t sort_workspace_bytes(int64_t nmax, int32_t KW);
+size_t compact_workspace_bytes(int64_t nmax, int32_t KW);
+labs_status compact_records(const RecBuf& rb, int32_t W, int64_t n, int64_t cap, uint32_t* out_seqs,
+                            int32_t* out_E, int64_t* out_walker, int32_t* out_step, int64_t* count,
+                            int64_t* dropped, int64_t* out_n, int32_t* thr, int32_t e_max, void* ws,
+                            size_t ws_bytes, hipStream_t st);
+labs_status pool_to_rec(const labs_pool& pool, int64_t n, int32_t W, const RecBuf& rb, int64_t off,
+                        hipStream_t st);
+
+// First-step walker state and launch arguments (walk.hip).
+struct WalkArgs {
+    int32_t L, p, k, nf, W;
+    int32_t t0, t1, steps_total;
+    int64_t n, walker_begin;
+    uint64_t seed;
+    int32_t tenure_lo, tenure_hi;
+    uint32_t* seq;      // [n*W] packed current sequence
+    int32_t* E;         // [n]
+    int32_t* tenure;    // [n]
+    int32_t* halted;    // [n] 0 = running, else the step that found no admissible move
+    int32_t* tabu;      // [n*nf] tabu_until per free position
+    int32_t* bestE;     // [n]
+    int32_t* bestT;     // [n]
+    uint32_t* bestSeq;  // [n*W]
+    int32_t* traj;      // [n*steps_total] or null
+    int32_t e_max;      // < 0: sieve off
+    const int32_t* thr; // device scalar: current pool threshold (E <= thr may enter)
+    uint32_t* rec;      // staging records, word-major
+    int64_t rec_stride;
+    uint32_t* st_count;
+    uint32_t st_cap;
+};
+bool walk_shape_supported(int L, int p);
+labs_status launch_walker_init(const WalkArgs& A, hipStream_t st);
+labs_status launch_walk(const WalkArgs& A, hipStream_t st);
+labs_status launch_offer_best(const WalkArgs& A, hipStream_t st);
+labs_status launch_walk_outputs(const WalkArgs& A, const labs_step1_out& o, hipStream_t st);
+// Sorts records [0, n) of `rb` by key words 0..nkeys-1 (word 0 most significant),
+// leaving the permutation in *perm_out (device array of n uint32, inside ws).
+labs_status radix_sort_records(const RecBuf& rb, int64_t n, int32_t nkeys, void* ws,
+                               size_t ws_bytes, uint32_t** perm_out, hipStream_t st);
+
+}  // namespace labsdev
