@@ -1,0 +1,155 @@
+#!/usr/bin/env python3
+"""Benchmark of the dual-step hot path at L = 501 on one MI355X.
+
+One benchmark step = one pass of the implemented hot path over a fresh seeded
+batch: walker init, the first-step walk of 16,384 skew-symmetric walkers
+(p = 16, tabu tenure in [L/10, L/5]) for 50,000 steps each, the F >= 8 sieve
+into a 2^20-entry pool (each walker's best offered too), and the pool's
+top 1024.  The headline value is flip-evaluations per second over the whole
+step.  A separate instrumented pass times the walk kernel alone for the
+roofline; the oracle timed on the host cores gives the CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+L = 501
+P = 16
+TAU_NUM, TAU_DEN = 8, 1
+METRIC = "flip-evals/sec and time-to-F>=tau at L=501, learned vs plain walker"
+# Nominal integer cost of one skew flip-evaluation: 4 ops per even lag, k lags.
+W_OPS = 2 * (L - 1)
+# gfx950 integer VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--walkers", type=int, default=16384)
+    ap.add_argument("--walk-steps", type=int, default=50000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline-pass", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(budget_s: float):
+    """The oracle's first-step walker (definitional energies), single thread,
+    on a bounded sample of the same walk: one walker at L = 501, p = 16."""
+    import oracle
+    oracle.lib()
+    k = (L - 1) // 2
+    nf = k + 1 - P
+    lo, hi = L // 10, L // 5
+    t0 = time.perf_counter()
+    oracle.walk(L, P, 4, lo, hi, 4, [0], want_traj=False)
+    per_step = (time.perf_counter() - t0) / 4
+    steps = max(4, int(budget_s / max(per_step, 1e-6)))
+    t0 = time.perf_counter()
+    oracle.walk(L, P, steps, lo, hi, 4, [0], want_traj=False)
+    dt = time.perf_counter() - t0
+    return {"value": steps * nf / dt, "unit": "flip-evals/s", "cores": 1, "kind": "oracle",
+            "sample": "1 walker x %d steps of the L=501 p=16 first-step walk (%d flip-evals, "
+                      "%.1f s), definitional energy per neighbour" % (steps, steps * nf, dt)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(walkers shard by id range; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2409_07222_amd import labs
+    import labs_inputs  # noqa: F401  (seeded inputs live in the library's own RNG streams)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    k = (L - 1) // 2
+    nf = k + 1 - P
+    lo, hi = L // 10, L // 5
+    e_max = (L * L * TAU_DEN) // (2 * TAU_NUM)
+    cap, topk = 1 << 20, 1024
+    pool = labs.PoolBuffers.empty(L, cap, device=dev)
+    cfg_ws = None
+
+    def one(seed):
+        nonlocal cfg_ws
+        pool.count.zero_()
+        pool.dropped.zero_()
+        r = labs.walk_step1(L, P, a.walk_steps, lo, hi, seed, a.walkers, e_max=e_max, pool=pool,
+                            pool_walker_best=True, device=dev, workspace=cfg_ws)
+        s, E = labs.pool_topk(pool, topk)
+        return r, E
+
+    # workspace reuse across steps
+    import ctypes
+    cfg = labs.Step1Cfg(L, P, a.walk_steps, lo, hi, e_max, 0, a.walkers, 0, 1, 0)
+    sz = ctypes.c_size_t(0)
+    labs._check(labs.lib().labs_walk_step1_workspace(ctypes.byref(cfg), 1, cap, ctypes.byref(sz)))
+    cfg_ws = torch.empty(int(sz.value), dtype=torch.uint8, device=dev)
+
+    for i in range(a.warmup):
+        one(1000 + i)
+    torch.cuda.synchronize()
+    evals = 0
+    best_E = None
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        r, E = one(4 + i)
+        evals += int(r.flip_evals.item())
+        e = int(E[0].item()) if E.numel() else None
+        if e is not None and (best_E is None or e < best_E):
+            best_E = e
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    roof = None
+    if not a.no_roofline_pass:
+        labs.timing_reset()
+        labs.timing_enable(True)
+        r, _ = one(2000)
+        torch.cuda.synchronize()
+        labs.timing_enable(False)
+        ms, launches = labs.timing_read("walk")
+        ops = int(r.flip_evals.item()) * W_OPS
+        achieved = ops / (ms / 1e3) / 1e12
+        peak = PEAK_INT_OPS / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
+                "frac": achieved / peak, "traffic": None,
+                "kernel": "walk", "launches": launches, "avg_launch_ms": ms / max(launches, 1),
+                "ops_per_flip_eval": W_OPS}
+
+    cpu = None if a.no_cpu_baseline else cpu_baseline(a.cpu_seconds)
+    value = evals / dt
+    line = {
+        "metric": METRIC, "value": value, "unit": "flip-evals/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt * 1e3 / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "first step at L=501 (p=16, tenure [50,100], %d walkers x %d steps, "
+                               "F>=8 sieve into a 2^20 pool with walker bests, top-1024)"
+                               % (a.walkers, a.walk_steps),
+                   "L": L, "p": P, "walkers": a.walkers, "walk_steps": a.walk_steps,
+                   "tau": TAU_NUM / TAU_DEN, "pool_capacity": cap, "topk": topk,
+                   "parallelism": "single GPU"},
+        "best_F": (L * L / (2.0 * best_E)) if best_E else None,
+        "time_to_tau_s": None,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -182,6 +182,17 @@ labs_status labs_pool_topk(const labs_pool* pool, int32_t L, int32_t k, uint32_t
                            int32_t* out_E, int64_t* out_n, void* ws, size_t ws_bytes,
                            void* stream);
 
+/* ----------------------------------------------------------------------------
+ * Launch timing (diagnostics).  While enabled, every launch of a timed kernel
+ * is bracketed by HIP events on the stream it runs on, and the entry point
+ * that launched it synchronises that stream before returning and adds the
+ * elapsed times to a process-wide table.  Timed kernel names: "walk" (the
+ * first-step scan/apply kernel).  total_ms and launches are HOST outputs.
+ */
+labs_status labs_timing_enable(int32_t on);
+labs_status labs_timing_reset(void);
+labs_status labs_timing_read(const char* kernel, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,7 +6,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 namespace labsdev {
 
@@ -43,6 +47,71 @@ const char* last_error() { return g_err.c_str(); }
 using namespace labsdev;
 
 namespace {
+
+// ---------------------------------------------------------------- launch timing
+struct TimingTable {
+    std::mutex mu;
+    bool on = false;
+    std::map<std::string, std::pair<double, int64_t>> acc;
+};
+TimingTable& timing() {
+    static TimingTable t;
+    return t;
+}
+
+// Brackets launches with events on their stream; flush() waits and accumulates.
+class LaunchTimer {
+  public:
+    explicit LaunchTimer(const char* name) : name_(name), on_(false) {
+        std::lock_guard<std::mutex> g(timing().mu);
+        on_ = timing().on;
+    }
+    ~LaunchTimer() {
+        for (auto& e : ev_) {
+            hipEventDestroy(e.first);
+            hipEventDestroy(e.second);
+        }
+    }
+    labs_status begin(hipStream_t st) {
+        if (!on_) return LABS_OK;
+        hipEvent_t a, b;
+        LABS_HIP(hipEventCreate(&a));
+        LABS_HIP(hipEventCreate(&b));
+        ev_.push_back({a, b});
+        LABS_HIP(hipEventRecord(a, st));
+        return LABS_OK;
+    }
+    labs_status end(hipStream_t st) {
+        if (!on_) return LABS_OK;
+        LABS_HIP(hipEventRecord(ev_.back().second, st));
+        return LABS_OK;
+    }
+    labs_status flush() {
+        if (!on_ || ev_.empty()) return LABS_OK;
+        LABS_HIP(hipEventSynchronize(ev_.back().second));
+        double ms = 0;
+        for (auto& e : ev_) {
+            float x = 0;
+            LABS_HIP(hipEventElapsedTime(&x, e.first, e.second));
+            ms += x;
+        }
+        std::lock_guard<std::mutex> g(timing().mu);
+        auto& slot = timing().acc[name_];
+        slot.first += ms;
+        slot.second += (int64_t)ev_.size();
+        for (auto& e : ev_) {
+            hipEventDestroy(e.first);
+            hipEventDestroy(e.second);
+        }
+        ev_.clear();
+        return LABS_OK;
+    }
+
+  private:
+    std::string name_;
+    bool on_;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_;
+};
 
 constexpr int kSegMax = 4096;    // walk steps per launch without a pool
 constexpr int kSegPool0 = 256;   // first segment length with a pool
@@ -249,15 +318,23 @@ labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void
     A.thr = nullptr;
 
     if ((s = launch_walker_init(A, st)) != LABS_OK) return s;
+    LaunchTimer tw("walk");
+    auto walk = [&]() -> labs_status {
+        labs_status r;
+        if ((r = tw.begin(st)) != LABS_OK) return r;
+        if ((r = launch_walk(A, st)) != LABS_OK) return r;
+        return tw.end(st);
+    };
 
     if (!pool) {
         for (int t = 0; t < steps; t += kSegMax) {
             A.t0 = t;
             A.t1 = t + kSegMax < steps ? t + kSegMax : steps;
-            if ((s = launch_walk(A, st)) != LABS_OK) return s;
+            if ((s = walk()) != LABS_OK) return s;
         }
         A.t1 = steps;
-        return launch_walk_outputs(A, o, st);
+        if ((s = launch_walk_outputs(A, o, st)) != LABS_OK) return s;
+        return tw.flush();
     }
 
     // ---- pool mode: segments, compaction after each, exact retry on overflow
@@ -303,7 +380,7 @@ labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void
         LABS_HIP(hipMemsetAsync(st_count, 0, sizeof(uint32_t), st));
         A.t0 = t;
         A.t1 = t + len;
-        if ((s = launch_walk(A, st)) != LABS_OK) return s;
+        if ((s = walk()) != LABS_OK) return s;
         if ((s = read_counts()) != LABS_OK) return s;
         if (hp.st_count > (uint32_t)lo.S) {
             // staging overflowed: restore and redo the segment in halves
@@ -325,7 +402,7 @@ labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void
         for (int tt = 0; tt < steps; tt += kSegMax) {
             A.t0 = tt;
             A.t1 = tt + kSegMax < steps ? tt + kSegMax : steps;
-            if ((s = launch_walk(A, st)) != LABS_OK) return s;
+            if ((s = walk()) != LABS_OK) return s;
         }
     }
     if (c.flags & LABS_POOL_WALKER_BEST) {
@@ -340,7 +417,32 @@ labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void
             return s;
     }
     A.t1 = steps;
-    return launch_walk_outputs(A, o, st);
+    if ((s = launch_walk_outputs(A, o, st)) != LABS_OK) return s;
+    return tw.flush();
+}
+
+labs_status labs_timing_enable(int32_t on) {
+    clear_error();
+    std::lock_guard<std::mutex> g(timing().mu);
+    timing().on = on != 0;
+    return LABS_OK;
+}
+
+labs_status labs_timing_reset(void) {
+    clear_error();
+    std::lock_guard<std::mutex> g(timing().mu);
+    timing().acc.clear();
+    return LABS_OK;
+}
+
+labs_status labs_timing_read(const char* kernel, double* total_ms, int64_t* launches) {
+    clear_error();
+    if (!kernel || !total_ms || !launches) return invalid("arguments must not be NULL");
+    std::lock_guard<std::mutex> g(timing().mu);
+    auto it = timing().acc.find(kernel);
+    *total_ms = it == timing().acc.end() ? 0.0 : it->second.first;
+    *launches = it == timing().acc.end() ? 0 : it->second.second;
+    return LABS_OK;
 }
 
 labs_status labs_pool_topk_workspace(int64_t capacity, int32_t L, size_t* bytes) {

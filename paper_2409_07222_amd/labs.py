@@ -76,6 +76,12 @@ def lib():
             L.labs_pool_topk_workspace.argtypes = [i64, i32, ctypes.POINTER(sz)]
             L.labs_pool_topk.restype = i32
             L.labs_pool_topk.argtypes = [ctypes.POINTER(Pool), i32, i32, vp, vp, vp, vp, sz, vp]
+            L.labs_timing_enable.restype = i32
+            L.labs_timing_enable.argtypes = [i32]
+            L.labs_timing_reset.restype = i32
+            L.labs_timing_read.restype = i32
+            L.labs_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(i64)]
             _lib = L
     return _lib
 
@@ -118,6 +124,23 @@ def words(L: int) -> int:
 
 def abi_version() -> int:
     return int(lib().labs_abi_version())
+
+
+# ---------------------------------------------------------------- timing
+def timing_enable(on: bool = True) -> None:
+    _check(lib().labs_timing_enable(1 if on else 0))
+
+
+def timing_reset() -> None:
+    _check(lib().labs_timing_reset())
+
+
+def timing_read(kernel: str):
+    """(total milliseconds, launches) accumulated for a timed kernel."""
+    ms = ctypes.c_double(0)
+    n = ctypes.c_int64(0)
+    _check(lib().labs_timing_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return float(ms.value), int(n.value)
 
 
 # ---------------------------------------------------------------- energies
