@@ -183,11 +183,66 @@ labs_status labs_pool_topk(const labs_pool* pool, int32_t L, int32_t k, uint32_t
                            void* stream);
 
 /* ----------------------------------------------------------------------------
+ * Second step (Alg. 2) as a batch-synchronous best-first search.
+ *
+ * Open (the priority queue) starts as the distinct candidates, cut to the
+ * pq_capacity smallest in key order; Closed starts empty; best = min(Open).
+ * While Open is non-empty, expansions < max_expansions and u < T_u, a round:
+ *   - pops the min(batch, max_expansions - expansions) smallest Open entries in
+ *     key order into Closed (expansions grows by their number);
+ *   - expands every single flip s_i -> -s_i (i = 1..L) of every popped pivot; a
+ *     neighbour already in Closed, in Open or produced earlier in this round is
+ *     skipped (Alg. 2's PQ.contains test, by exact sequence); the others are
+ *     pushed with their exact energy;
+ *   - if the round's smallest pushed energy is below best's, best becomes the
+ *     smallest pushed entry in key order and u = 0; otherwise u grows by the
+ *     number of pivots (u counts pops since the last strict improvement; with
+ *     batch = 1 this is Alg. 2's dynamic depth exactly);
+ *   - cuts Open to the pq_capacity smallest in key order (evicted sequences
+ *     are forgotten and may be pushed again later).
+ * Results do not depend on scheduling.  The call synchronises `stream`.
+ */
+typedef struct {
+    int32_t L;               /* 2..1023 */
+    int32_t batch;           /* pivots per round, >= 1 */
+    int32_t T_r;             /* rotations; must be 0 in this build */
+    int32_t reserved;        /* must be 0 */
+    int64_t pq_capacity;     /* Q >= 1 */
+    int64_t max_expansions;  /* >= 0 */
+    int64_t T_u;             /* >= 1 */
+} labs_step2_cfg;
+
+typedef struct {
+    int64_t expansions;      /* pivots popped */
+    int64_t pushes;          /* neighbours pushed (new or re-pushed after eviction) */
+    int64_t dup_skips;       /* neighbours skipped as already present */
+    int64_t evictions;       /* entries cut by the capacity */
+    int64_t rounds;
+    int64_t open_count;      /* Open entries at the end */
+    int32_t best_E;
+    int32_t best_round;      /* round of the last improvement, -1 if none */
+} labs_step2_stats;
+
+typedef struct {
+    uint32_t* best_seq;      /* [W] (device) */
+    int32_t* best_E;         /* [1] (device) */
+    labs_step2_stats* stats; /* device */
+    uint32_t* open_seqs;     /* [open_capacity*W] Open at exit, any order (may be NULL) */
+    int32_t* open_E;         /* [open_capacity] (may be NULL) */
+    int64_t open_capacity;   /* entries written: min(open_count, open_capacity) */
+} labs_step2_out;
+
+labs_status labs_refine_step2_workspace(const labs_step2_cfg* cfg, int64_t n_cand, size_t* bytes);
+/* cand_seqs: [n_cand*W] packed candidates (device), n_cand >= 1. */
+labs_status labs_refine_step2(const labs_step2_cfg* cfg, int64_t n_cand, const uint32_t* cand_seqs,
+                              const labs_step2_out* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------------------------
  * Launch timing (diagnostics).  While enabled, every launch of a timed kernel
  * is bracketed by HIP events on the stream it runs on, and the entry point
  * that launched it synchronises that stream before returning and adds the
  * elapsed times to a process-wide table.  Timed kernel names: "walk" (the
- * first-step scan/apply kernel).  total_ms and launches are HOST outputs.
+ * first-step scan/apply kernel), "expand" (the second-step expansion kernel).  total_ms and launches are HOST outputs.
  */
 labs_status labs_timing_enable(int32_t on);
 labs_status labs_timing_reset(void);

@@ -421,6 +421,47 @@ labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void
     return tw.flush();
 }
 
+static labs_status check_step2_cfg(const labs_step2_cfg& c, int64_t n_cand) {
+    if (c.L < 2 || c.L > 1023) return invalid("second-step L must be in [2, 1023], got %d", c.L);
+    if (c.batch < 1 || c.batch > (1 << 20)) return invalid("batch must be in [1, 2^20]");
+    if (c.T_r != 0) return invalid("rotations (T_r > 0) are not part of this build");
+    if (c.reserved != 0) return invalid("reserved must be 0");
+    if (c.pq_capacity < 1 || c.pq_capacity > (int64_t)1 << 28) return invalid("pq_capacity must be in [1, 2^28]");
+    if (c.max_expansions < 0 || c.max_expansions > (int64_t)1 << 30)
+        return invalid("max_expansions must be in [0, 2^30]");
+    if (c.T_u < 1) return invalid("T_u must be >= 1");
+    if (n_cand < 1 || n_cand > (int64_t)1 << 28) return invalid("n_cand must be in [1, 2^28]");
+    return LABS_OK;
+}
+
+labs_status labs_refine_step2_workspace(const labs_step2_cfg* cfg, int64_t n_cand, size_t* bytes) {
+    clear_error();
+    if (!cfg || !bytes) return invalid("cfg and bytes must not be NULL");
+    labs_status s = check_step2_cfg(*cfg, n_cand);
+    if (s != LABS_OK) return s;
+    *bytes = step2_workspace_bytes(*cfg, n_cand);
+    return LABS_OK;
+}
+
+static labs_status timer_begin_cb(void* t, hipStream_t st) { return ((LaunchTimer*)t)->begin(st); }
+static labs_status timer_end_cb(void* t, hipStream_t st) { return ((LaunchTimer*)t)->end(st); }
+
+labs_status labs_refine_step2(const labs_step2_cfg* cfg, int64_t n_cand, const uint32_t* cand_seqs,
+                              const labs_step2_out* out, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (!cfg || !out) return invalid("cfg and out must not be NULL");
+    labs_status s = check_step2_cfg(*cfg, n_cand);
+    if (s != LABS_OK) return s;
+    if (!cand_seqs) return invalid("cand_seqs must not be NULL");
+    if (!out->best_seq || !out->best_E || !out->stats) return invalid("best_seq, best_E and stats must not be NULL");
+    if (out->open_capacity < 0) return invalid("open_capacity must be >= 0");
+    if (!ws) return invalid("workspace must not be NULL");
+    LaunchTimer te("expand");
+    s = step2_run(*cfg, n_cand, cand_seqs, *out, ws, ws_bytes, S(stream), timer_begin_cb, timer_end_cb, &te);
+    if (s != LABS_OK) return s;
+    return te.flush();
+}
+
 labs_status labs_timing_enable(int32_t on) {
     clear_error();
     std::lock_guard<std::mutex> g(timing().mu);

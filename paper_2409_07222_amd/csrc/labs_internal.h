@@ -118,6 +118,11 @@ struct WalkArgs {
     uint32_t st_cap;
 };
 bool walk_shape_supported(int L, int p);
+size_t step2_workspace_bytes(const labs_step2_cfg& c, long long n_cand);
+labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_t* cand_seqs,
+                      const labs_step2_out& out, void* ws, size_t ws_bytes, hipStream_t st,
+                      labs_status (*tb)(void*, hipStream_t), labs_status (*te)(void*, hipStream_t),
+                      void* tctx);
 labs_status launch_walker_init(const WalkArgs& A, hipStream_t st);
 labs_status launch_walk(const WalkArgs& A, hipStream_t st);
 labs_status launch_offer_best(const WalkArgs& A, hipStream_t st);

@@ -47,6 +47,25 @@ class Step1Out(ctypes.Structure):
                 ("flip_evals", ctypes.c_void_p)]
 
 
+class Step2Cfg(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("batch", ctypes.c_int32), ("T_r", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("pq_capacity", ctypes.c_int64),
+                ("max_expansions", ctypes.c_int64), ("T_u", ctypes.c_int64)]
+
+
+class Step2Stats(ctypes.Structure):
+    _fields_ = [("expansions", ctypes.c_int64), ("pushes", ctypes.c_int64),
+                ("dup_skips", ctypes.c_int64), ("evictions", ctypes.c_int64),
+                ("rounds", ctypes.c_int64), ("open_count", ctypes.c_int64),
+                ("best_E", ctypes.c_int32), ("best_round", ctypes.c_int32)]
+
+
+class Step2Out(ctypes.Structure):
+    _fields_ = [("best_seq", ctypes.c_void_p), ("best_E", ctypes.c_void_p),
+                ("stats", ctypes.c_void_p), ("open_seqs", ctypes.c_void_p),
+                ("open_E", ctypes.c_void_p), ("open_capacity", ctypes.c_int64)]
+
+
 def lib():
     """Load liblabs.so (never builds it)."""
     global _lib
@@ -76,6 +95,12 @@ def lib():
             L.labs_pool_topk_workspace.argtypes = [i64, i32, ctypes.POINTER(sz)]
             L.labs_pool_topk.restype = i32
             L.labs_pool_topk.argtypes = [ctypes.POINTER(Pool), i32, i32, vp, vp, vp, vp, sz, vp]
+            L.labs_refine_step2_workspace.restype = i32
+            L.labs_refine_step2_workspace.argtypes = [ctypes.POINTER(Step2Cfg), i64,
+                                                      ctypes.POINTER(sz)]
+            L.labs_refine_step2.restype = i32
+            L.labs_refine_step2.argtypes = [ctypes.POINTER(Step2Cfg), i64, vp,
+                                            ctypes.POINTER(Step2Out), vp, sz, vp]
             L.labs_timing_enable.restype = i32
             L.labs_timing_enable.argtypes = [i32]
             L.labs_timing_reset.restype = i32
@@ -256,3 +281,39 @@ def walk_step1(L: int, p: int, steps: int, tenure_lo: int, tenure_hi: int, seed:
                                  ctypes.byref(out), _ptr(workspace), workspace.numel(),
                                  _stream(torch.device(device))))
     return r
+
+
+# ---------------------------------------------------------------- second step
+def refine_step2(L: int, cands, batch: int, pq_capacity: int, max_expansions: int, T_u: int,
+                 open_capacity: int = 0, workspace=None):
+    """labs_refine_step2 over packed candidates (int32 [n, W] device tensor).
+    Returns a dict with best_seq, best_E, the stats and (optionally) Open."""
+    torch = _torch()
+    c = _dev(cands, torch.int32, "cands")
+    n = c.shape[0]
+    dev = c.device
+    cfg = Step2Cfg(L, batch, 0, 0, pq_capacity, max_expansions, T_u)
+    sz = ctypes.c_size_t(0)
+    _check(lib().labs_refine_step2_workspace(ctypes.byref(cfg), n, ctypes.byref(sz)))
+    if workspace is None or workspace.numel() < sz.value:
+        workspace = torch.empty(int(sz.value), dtype=torch.uint8, device=dev)
+    W = words(L)
+    best_seq = torch.zeros(W, dtype=torch.int32, device=dev)
+    best_E = torch.zeros(1, dtype=torch.int32, device=dev)
+    stats = torch.zeros(ctypes.sizeof(Step2Stats), dtype=torch.uint8, device=dev)
+    oc = int(open_capacity)
+    open_seqs = torch.zeros((max(oc, 1), W), dtype=torch.int32, device=dev)
+    open_E = torch.zeros(max(oc, 1), dtype=torch.int32, device=dev)
+    out = Step2Out(best_seq.data_ptr(), best_E.data_ptr(), stats.data_ptr(),
+                   open_seqs.data_ptr() if oc else None, open_E.data_ptr() if oc else None, oc)
+    _check(lib().labs_refine_step2(ctypes.byref(cfg), n, _ptr(c), ctypes.byref(out), _ptr(workspace),
+                                   workspace.numel(), _stream(dev)))
+    st = Step2Stats.from_buffer_copy(bytes(stats.cpu().numpy().tobytes()))
+    res = {f: getattr(st, f) for f, _ in Step2Stats._fields_}
+    res["best_seq"] = best_seq
+    res["best_E_dev"] = best_E
+    if oc:
+        m = min(res["open_count"], oc)
+        res["open_seqs"] = open_seqs[:m]
+        res["open_E"] = open_E[:m]
+    return res

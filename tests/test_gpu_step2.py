@@ -1,0 +1,80 @@
+"""GPU parity of the second step (batch-synchronous best-first search)
+against the oracle: best, statistics and the final Open set, exactly."""
+import numpy as np
+import pytest
+
+import labs_inputs as li
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_07222_amd import labs
+    labs.lib()
+    return labs
+
+
+def _dev(packed):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(packed).view(np.int32)).cuda()
+
+
+def _run_both(lb, orc, L, cands, B, Q, X, T_u):
+    g = lb.refine_step2(L, _dev(li.pack(cands)), B, Q, X, T_u, open_capacity=Q)
+    o = orc.step2(L, list(cands), B, Q, X, T_u)
+    for f in ("expansions", "pushes", "dup_skips", "evictions", "rounds", "best_round"):
+        assert g[f] == o[f], (f, g[f], o[f])
+    assert g["best_E"] == o["best_E"]
+    gs = li.unpack(g["best_seq"].cpu().numpy().view(np.uint32), L)
+    assert orc.seq_key(gs) == o["best_key"]
+    assert g["open_count"] == len(o["open_keys"])
+    got = sorted((int(e), orc.seq_key(s)) for e, s in
+                 zip(g["open_E"].cpu().numpy(),
+                     li.unpack(g["open_seqs"].cpu().numpy().view(np.uint32), L)))
+    assert got == o["open_keys"]
+    return g, o
+
+
+@pytest.mark.parametrize("L,n,B,Q,X,T_u", [
+    (11, 3, 1, 1 << 20, 100, 1 << 40),     # Algorithm 2 exactly (batch 1)
+    (13, 4, 4, 30, 200, 1 << 40),          # capacity cut and re-pushes
+    (16, 2, 7, 1 << 20, 300, 1 << 40),     # even length, ragged batch
+    (33, 5, 3, 64, 150, 12),               # dynamic depth stop
+    (101, 6, 64, 3000, 1500, 300),         # second configuration's length
+    (200, 2, 32, 500, 400, 1 << 40),
+])
+def test_step2_parity(lb, orc, L, n, B, Q, X, T_u):
+    cands = li.random_pm1(L * 7 + n, n, L)
+    _run_both(lb, orc, L, cands, B, Q, X, T_u)
+
+
+def test_step2_L501(lb, orc):
+    L = 501
+    cands = li.random_skew(5, 3, L, 16)
+    _run_both(lb, orc, L, cands, 16, 1000, 48, 1 << 40)
+
+
+def test_step2_full_space(lb, orc):
+    """Room for all 2^10 sequences: the search ends at the published optimum."""
+    L = 10
+    cands = li.random_pm1(3, 2, L)
+    g, o = _run_both(lb, orc, L, cands, 5, 1 << 20, 1 << 20, 1 << 40)
+    assert g["best_E"] == 13 and g["expansions"] == 1 << L
+
+
+def test_step2_duplicate_candidates(lb, orc):
+    L = 21
+    c = li.random_pm1(9, 4, L)
+    cands = np.concatenate([c, c[:2], c[:1]])
+    _run_both(lb, orc, L, cands, 2, 100, 40, 1 << 40)
+
+
+def test_step2_zero_budget(lb, orc):
+    L = 15
+    cands = li.random_pm1(2, 3, L)
+    g, o = _run_both(lb, orc, L, cands, 4, 100, 0, 1 << 40)
+    assert g["expansions"] == 0 and g["rounds"] == 0
