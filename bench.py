@@ -4,9 +4,11 @@
 One benchmark step = one pass of the implemented hot path over a fresh seeded
 batch: walker init, the first-step walk of 16,384 skew-symmetric walkers
 (p = 16, tabu tenure in [L/10, L/5]) for 50,000 steps each, the F >= 8 sieve
-into a 2^20-entry pool (each walker's best offered too), and the pool's
-top 1024.  The headline value is flip-evaluations per second over the whole
-step.  A separate instrumented pass times the walk kernel alone for the
+into a 2^20-entry pool (each walker's best offered too), the pool's top 1024,
+and the second step from those 1024 candidates (batch-synchronous best-first,
+2^20-entry queue, 10^7 expansions).  The headline value is flip-evaluations
+per second over the whole step (first-step skew flips plus second-step single
+flips).  A separate instrumented pass times the dominant kernels for the
 roofline; the oracle timed on the host cores gives the CPU baseline.
 """
 from __future__ import annotations
@@ -26,6 +28,8 @@ TAU_NUM, TAU_DEN = 8, 1
 METRIC = "flip-evals/sec and time-to-F>=tau at L=501, learned vs plain walker"
 # Nominal integer cost of one skew flip-evaluation: 4 ops per even lag, k lags.
 W_OPS = 2 * (L - 1)
+# Nominal cost of one single-flip evaluation in the second step: 4 ops per lag.
+W2_OPS = 4 * (L - 1)
 # gfx950 integer VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
 
@@ -37,6 +41,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--walkers", type=int, default=16384)
     ap.add_argument("--walk-steps", type=int, default=50000)
+    ap.add_argument("--s2-expansions", type=int, default=10_000_000)
+    ap.add_argument("--s2-batch", type=int, default=1024)
+    ap.add_argument("--s2-capacity", type=int, default=1 << 20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline-pass", action="store_true")
@@ -83,14 +90,27 @@ def main():
     pool = labs.PoolBuffers.empty(L, cap, device=dev)
     cfg_ws = None
 
+    s2_ws = None
+
     def one(seed):
-        nonlocal cfg_ws
+        nonlocal cfg_ws, s2_ws
         pool.count.zero_()
         pool.dropped.zero_()
         r = labs.walk_step1(L, P, a.walk_steps, lo, hi, seed, a.walkers, e_max=e_max, pool=pool,
                             pool_walker_best=True, device=dev, workspace=cfg_ws)
         s, E = labs.pool_topk(pool, topk)
-        return r, E
+        if a.s2_expansions > 0:
+            if s2_ws is None:
+                cfg2 = labs.Step2Cfg(L, a.s2_batch, 0, 0, a.s2_capacity, a.s2_expansions, 1 << 62)
+                sz2 = ctypes.c_size_t(0)
+                labs._check(labs.lib().labs_refine_step2_workspace(ctypes.byref(cfg2), topk,
+                                                                   ctypes.byref(sz2)))
+                s2_ws = torch.empty(int(sz2.value), dtype=torch.uint8, device=dev)
+            r2 = labs.refine_step2(L, s.contiguous(), a.s2_batch, a.s2_capacity, a.s2_expansions,
+                                   1 << 62, workspace=s2_ws)
+        else:
+            r2 = {"expansions": 0, "best_E": int(E[0].item())}
+        return r, E, r2
 
     # workspace reuse across steps
     import ctypes
@@ -102,14 +122,21 @@ def main():
     for i in range(a.warmup):
         one(1000 + i)
     torch.cuda.synchronize()
-    evals = 0
-    best_E = None
+    evals = evals1 = evals2 = 0
+    best_E = best1_E = None
     t0 = time.perf_counter()
     for i in range(a.steps):
-        r, E = one(4 + i)
-        evals += int(r.flip_evals.item())
+        r, E, r2 = one(4 + i)
+        e1 = int(r.flip_evals.item())
+        e2 = int(r2["expansions"]) * L
+        evals1 += e1
+        evals2 += e2
+        evals += e1 + e2
         e = int(E[0].item()) if E.numel() else None
-        if e is not None and (best_E is None or e < best_E):
+        if e is not None and (best1_E is None or e < best1_E):
+            best1_E = e
+        e = int(r2["best_E"])
+        if best_E is None or e < best_E:
             best_E = e
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -118,17 +145,27 @@ def main():
     if not a.no_roofline_pass:
         labs.timing_reset()
         labs.timing_enable(True)
-        r, _ = one(2000)
+        tr0 = time.perf_counter()
+        r, _, r2 = one(2000)
         torch.cuda.synchronize()
+        t_pass = time.perf_counter() - tr0
         labs.timing_enable(False)
         ms, launches = labs.timing_read("walk")
+        ms2, launches2 = labs.timing_read("expand")
         ops = int(r.flip_evals.item()) * W_OPS
         achieved = ops / (ms / 1e3) / 1e12
         peak = PEAK_INT_OPS / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
                 "frac": achieved / peak, "traffic": None,
                 "kernel": "walk", "launches": launches, "avg_launch_ms": ms / max(launches, 1),
-                "ops_per_flip_eval": W_OPS}
+                "ops_per_flip_eval": W_OPS, "kernel_share_of_pass": ms / 1e3 / t_pass}
+        if launches2:
+            ops2 = int(r2["expansions"]) * L * W2_OPS
+            a2 = ops2 / (ms2 / 1e3) / 1e12
+            roof["step2_expand"] = {"achieved": a2, "frac": a2 / peak, "launches": launches2,
+                                    "avg_launch_ms": ms2 / launches2,
+                                    "ops_per_neighbour_eval": W2_OPS,
+                                    "kernel_share_of_pass": ms2 / 1e3 / t_pass}
 
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.cpu_seconds)
     value = evals / dt
@@ -137,13 +174,19 @@ def main():
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt * 1e3 / a.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "first step at L=501 (p=16, tenure [50,100], %d walkers x %d steps, "
-                               "F>=8 sieve into a 2^20 pool with walker bests, top-1024)"
-                               % (a.walkers, a.walk_steps),
+        "config": {"workload": "dual step at L=501: first step p=16, tenure [50,100], %d walkers x "
+                               "%d steps, F>=8 sieve into a 2^20 pool with walker bests, top-1024; "
+                               "second step from the top-1024, batch %d, queue %d, %d expansions"
+                               % (a.walkers, a.walk_steps, a.s2_batch, a.s2_capacity,
+                                  a.s2_expansions),
                    "L": L, "p": P, "walkers": a.walkers, "walk_steps": a.walk_steps,
                    "tau": TAU_NUM / TAU_DEN, "pool_capacity": cap, "topk": topk,
+                   "s2_batch": a.s2_batch, "s2_capacity": a.s2_capacity,
+                   "s2_expansions": a.s2_expansions,
                    "parallelism": "single GPU"},
         "best_F": (L * L / (2.0 * best_E)) if best_E else None,
+        "best_F_step1": (L * L / (2.0 * best1_E)) if best1_E else None,
+        "step1_flip_evals_per_s": evals1 / dt, "step2_neighbour_evals_per_s": evals2 / dt,
         "time_to_tau_s": None,
         "roofline": roof,
         "cpu_baseline": cpu,

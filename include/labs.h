@@ -185,21 +185,26 @@ labs_status labs_pool_topk(const labs_pool* pool, int32_t L, int32_t k, uint32_t
 /* ----------------------------------------------------------------------------
  * Second step (Alg. 2) as a batch-synchronous best-first search.
  *
+ * Order in this step: (E, z, sequence) with z the sequence's Zobrist key: the
+ * XOR, over the positions i with s_i = +1, of output i-1 of the SplitMix64
+ * stream started at state 0x6A09E667F3BCC909, with its lowest bit set.  (Ties in
+ * energy are unspecified by the paper; a pseudo-random tie order keeps the
+ * selection cheap on the GPU.)
  * Open (the priority queue) starts as the distinct candidates, cut to the
- * pq_capacity smallest in key order; Closed starts empty; best = min(Open).
+ * pq_capacity smallest; Closed starts empty; best = min(Open).
  * While Open is non-empty, expansions < max_expansions and u < T_u, a round:
- *   - pops the min(batch, max_expansions - expansions) smallest Open entries in
- *     key order into Closed (expansions grows by their number);
+ *   - pops the min(batch, max_expansions - expansions) smallest Open entries
+ *     into Closed (expansions grows by their number);
  *   - expands every single flip s_i -> -s_i (i = 1..L) of every popped pivot; a
  *     neighbour already in Closed, in Open or produced earlier in this round is
  *     skipped (Alg. 2's PQ.contains test, by exact sequence); the others are
  *     pushed with their exact energy;
  *   - if the round's smallest pushed energy is below best's, best becomes the
- *     smallest pushed entry in key order and u = 0; otherwise u grows by the
+ *     smallest pushed entry and u = 0; otherwise u grows by the
  *     number of pivots (u counts pops since the last strict improvement; with
  *     batch = 1 this is Alg. 2's dynamic depth exactly);
- *   - cuts Open to the pq_capacity smallest in key order (evicted sequences
- *     are forgotten and may be pushed again later).
+ *   - cuts Open to the pq_capacity smallest (evicted sequences are forgotten
+ *     and may be pushed again later).
  * Results do not depend on scheduling.  The call synchronises `stream`.
  */
 typedef struct {

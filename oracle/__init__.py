@@ -316,13 +316,33 @@ def topk(entries, k: int):
 
 
 # ---------------------------------------------------------------- second step
+# Second-step tie order (a reading; the paper is silent on ties): (E, z, key)
+# where z is the sequence's Zobrist key -- the XOR, over the positions i with
+# s_i = +1, of output i-1 of the SplitMix64 stream started at ZOBRIST_STATE, with
+# its lowest bit set -- and key the sequence as above.
+ZOBRIST_STATE = 0x6A09E667F3BCC909
+
+
+def zobrist_table(L: int) -> list:
+    return splitmix64_stream(ZOBRIST_STATE, L)
+
+
+def zobrist(key: int, L: int, table=None) -> int:
+    z = table if table is not None else zobrist_table(L)
+    h = 0
+    for i in range(L):
+        if (key >> (L - 1 - i)) & 1:
+            h ^= z[i]
+    return h | 1
+
+
 def step2(L: int, candidates, batch: int, pq_capacity: int, max_expansions: int,
           T_u: int, T_r: int = 0):
     """Second step (Algorithm 2) as a batch-synchronous best-first search.
 
     Open (the priority queue) and Closed (popped sequences) are exact sets of
     sequences.  Each round pops the min(batch, remaining) smallest Open entries in
-    (E, key) order, moves them to Closed, and expands every single flip of every
+    (E, Zobrist key, key) order, moves them to Closed, and expands every single flip of every
     pivot; a neighbour already in Closed, Open or this round's batch is skipped
     (the PQ.contains test).  Energies are recomputed from the definition.  The
     best sequence improves only on a strictly lower energy; u counts pops since
@@ -334,6 +354,11 @@ def step2(L: int, candidates, batch: int, pq_capacity: int, max_expansions: int,
     if T_r != 0:
         raise NotImplementedError("rotations are not part of the second-step reading")
     lb = lib()
+    zt = zobrist_table(L)
+
+    def order(key, E):
+        return (E, zobrist(key, L, zt), key)
+
     open_ = {}
     for c in candidates:
         s = _seq(c)
@@ -341,27 +366,27 @@ def step2(L: int, candidates, batch: int, pq_capacity: int, max_expansions: int,
             raise ValueError("candidate length")
         open_[seq_key(s)] = energy(s)
     if len(open_) > pq_capacity:
-        keep = sorted((E, k) for k, E in open_.items())[:pq_capacity]
-        open_ = {k: E for E, k in keep}
+        keep = sorted(order(k, E) for k, E in open_.items())[:pq_capacity]
+        open_ = {k: E for E, _, k in keep}
     closed = set()
     if not open_:
         return dict(best_E=None, best_key=None, expansions=0, pushes=0, dup_skips=0,
-                    evictions=0, best_round=-1, rounds=0)
-    bE, bK = min((E, k) for k, E in open_.items())
+                    evictions=0, best_round=-1, rounds=0, open_keys=[])
+    bE, _, bK = min(order(k, E) for k, E in open_.items())
     u = 0
     done = 0
     pushes = dups = evictions = 0
     best_round = -1
     rnd = 0
     while open_ and done < max_expansions and u < T_u:
-        order = sorted((E, k) for k, E in open_.items())
-        P = order[:min(batch, max_expansions - done)]
-        for E, k in P:
+        ordered = sorted(order(k, E) for k, E in open_.items())
+        P = ordered[:min(batch, max_expansions - done)]
+        for E, _, k in P:
             del open_[k]
             closed.add(k)
         done += len(P)
         new = {}
-        for E, k in P:
+        for E, _, k in P:
             s = key_seq(k, L)
             for i in range(L):
                 nk = k ^ (1 << (L - 1 - i))
@@ -373,7 +398,7 @@ def step2(L: int, candidates, batch: int, pq_capacity: int, max_expansions: int,
                 new[nk] = int(lb.or_energy(L, _p(t, _i8p), None))
         pushes += len(new)
         if new:
-            mE, mK = min((E, k) for k, E in new.items())
+            mE, _, mK = min(order(k, E) for k, E in new.items())
             if mE < bE:
                 bE, bK = mE, mK
                 u = 0
@@ -384,9 +409,9 @@ def step2(L: int, candidates, batch: int, pq_capacity: int, max_expansions: int,
             u += len(P)
         open_.update(new)
         if len(open_) > pq_capacity:
-            keep = sorted((E, k) for k, E in open_.items())
+            keep = sorted(order(k, E) for k, E in open_.items())
             evictions += len(keep) - pq_capacity
-            open_ = {k: E for E, k in keep[:pq_capacity]}
+            open_ = {k: E for E, _, k in keep[:pq_capacity]}
         rnd += 1
     return dict(best_E=bE, best_key=bK, expansions=done, pushes=pushes, dup_skips=dups,
                 evictions=evictions, best_round=best_round, rounds=rnd,

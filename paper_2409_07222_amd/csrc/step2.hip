@@ -1,26 +1,31 @@
 // Second step (Algorithm 2) as a device-resident, batch-synchronous best-first
-// search.  Every round runs as a fixed sequence of kernels that read a control
-// block in device memory; the host enqueues rounds and looks at the stop flag
-// every few rounds.
+// search.  Every round is a fixed sequence of kernels that read a control block
+// in device memory; the host enqueues rounds and looks at the stop flag every
+// few rounds.
 //
 // Data structures (all in the caller's workspace):
 //  * a hash set H keyed by the exact sequence (open addressing, linear probing).
-//    A slot holds a 64-bit Zobrist key (0 = empty), a state (0 = being written,
-//    OPEN, CLOSED, EVICTED), E and the packed sequence.  Zobrist keys make the
-//    neighbour key one XOR away from the pivot's (Alg. 2's HASH_FLIP).  H holds
-//    Closed U Open U evicted; an EVICTED slot counts as absent and is re-opened
-//    when its sequence is pushed again.
-//  * the Open list: (E, slot) pairs, unordered, with dead entries (E = DEAD)
-//    left by pops and evictions and compacted away when space runs short.
-//  * an exact "T smallest in key order" selection: radix select on E in 11-bit
-//    digits, then an MSD byte-wise radix select on the sequence among entries
-//    tied at the threshold energy.
+//    A slot holds a 64-bit Zobrist key (0 = empty), a state (OPEN, CLOSED,
+//    EVICTED), E and the packed sequence.  Zobrist keys make a neighbour's key one
+//    XOR away from its pivot's (Alg. 2's HASH_FLIP).  H holds Closed U Open U
+//    evicted sequences; an EVICTED slot counts as absent and is re-opened when its
+//    sequence is pushed again.  When half of H is claimed it is rebuilt without
+//    the evicted tombstones.
+//  * the Open list: (E, slot) pairs, unordered.  Pops mark entries dead; the
+//    capacity cut at the end of each round compacts the list into the other
+//    buffer, so every round starts from a dense list.
+//  * an exact "T smallest" selection in the order (E, Zobrist key, sequence):
+//    radix select on E in 11-bit digits, then a byte-wise radix select on the
+//    Zobrist key and the sequence among the entries tied at the threshold energy,
+//    skipping digit positions on which they all agree.
 //
-// Insertion is exact without sorting: a lane claims an empty slot with a 64-bit
-// CAS of its key and then publishes the slot (data first, state last); a lane
-// that meets its own key in a slot waits (bounded) for publication and compares
-// sequences.  Claim-and-publish precedes the wait in program order, so a
-// publisher in the same wavefront has always published before anyone waits.
+// Insertion is exact and uses no fences: in phase 1 a candidate walks its probe
+// sequence with 64-bit CAS on the key word; an empty slot is claimed (the claimer
+// writes the sequence with plain stores), a slot already holding its key makes
+// the candidate "pending".  After the kernel boundary, phase 2 compares each
+// pending candidate with the slot's sequence (a duplicate, or a re-push of an
+// evicted sequence); a mismatch is a true 64-bit key collision and goes to
+// phase 3, which finishes those insertions one at a time in a single thread.
 #include "labs_internal.h"
 
 #include <climits>
@@ -34,10 +39,13 @@ constexpr uint32_t ST_OPEN = 1, ST_CLOSED = 2, ST_EVICTED = 3;
 constexpr uint64_t ZKEY = 0x6A09E667F3BCC909ull;   // Zobrist stream key
 constexpr int kSelBits = 11;
 constexpr int kSelBins = 1 << kSelBits;
+constexpr int kSelBlocks = 128;
+constexpr int kSelThreads = 512;
+constexpr int kGridBlocks = 512;                     // grid-stride kernels over the Open list
 constexpr int kMaxL = 1023;
 constexpr int kPad = 1024;
 constexpr int kSv = kMaxL + 2 * kPad + 2;
-constexpr int kSpinLimit = 1 << 22;
+constexpr int kExThreads = 256;
 
 struct Table {
     unsigned long long* hkey;
@@ -55,9 +63,8 @@ struct Ctl {
     int32_t best_E, best_slot, best_round, stop;
     int32_t error, which, pad0, pad1;
     // per round
-    long long n_piv, batch_begin;
-    int32_t batch_minE, improved, need_compact, pad2;
-    long long compact_count;
+    long long n_piv, batch_begin, n_pend, n_slow, survivors;
+    int32_t batch_minE, improved, pad2, pad3;
     // selection
     long long T, c_lt, need;
     uint32_t emin, emax;
@@ -65,55 +72,71 @@ struct Ctl {
     int32_t hi_shift, lo_shift;
     uint32_t prefix, Dt;
     int32_t resolved, n_cand;
-    int32_t Et, pad3;
     // table occupancy (claimed slots, tombstones included) and rebuild scratch
     long long claimed, claimed_new;
+    long long out_count;
+};
+
+// A pending insertion: the slot whose key matched, the source of the sequence
+// (a pivot slot and a flip position, or a candidate index when src < 0) and E.
+struct Pend {
+    int32_t slot, src, flip, E;
 };
 
 struct Params {
     int32_t L, W, B;
     long long Q, X, T_u;
-    long long cap_o;
+    long long cap_o, cap_pend;
     Table H;
     Ctl* ctl;
     int32_t* oE[2];
     int32_t* oS[2];
-    uint32_t* flag;     // [cap_o]
-    int32_t* cand[2];   // [cap_o] each
-    int32_t* piv;       // [B]
-    uint32_t* ghist;    // [kSelBins]
-    uint32_t* best_seq; // [W] copy of the best sequence
+    uint32_t* flag;        // [cap_o]
+    int32_t* cand[2];      // [cap_o] each
+    int32_t* piv;          // [B]
+    uint32_t* ghist;       // [kSelBlocks][kSelBins]
+    uint32_t* best_seq;    // [W] copy of the best sequence
+    Pend* pend;            // [cap_pend]
+    Pend* slow;            // [cap_pend]
+    const uint32_t* cands; // seeding input
 };
 
 __device__ __forceinline__ uint64_t zob(int i) { return sm64_at(ZKEY, (uint64_t)i); }
 
-__device__ __forceinline__ uint32_t ld_acq(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t ld_rlx(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long ld_rlx64(const unsigned long long* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Wave-aggregated append: returns this lane's index (valid only where `take`).
-__device__ __forceinline__ long long wave_append(long long* counter, bool take) {
+// Block-aggregated append: every thread of the block must call it (uniformly).
+__device__ long long block_append(long long* counter, bool take) {
+    __shared__ int wcnt[16];
+    __shared__ long long bbase;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
     const uint64_t m = __ballot(take);
-    if (!m) return -1;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    long long base = 0;
-    if (lane == leader) base = atomicAdd((unsigned long long*)counter, (unsigned long long)__popcll(m));
-    base = __shfl(base, leader, 64);
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    return base + __popcll(m & lt);
+    if (lane == 0) wcnt[wv] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int k = 0; k < nw; ++k) {
+            const int t = wcnt[k];
+            wcnt[k] = run;
+            run += t;
+        }
+        bbase = run ? (long long)atomicAdd((unsigned long long*)counter, (unsigned long long)run) : 0;
+    }
+    __syncthreads();
+    const long long idx = bbase + wcnt[wv] + __popcll(m & lt);
+    __syncthreads();
+    return take ? idx : -1;
 }
 
-__device__ __forceinline__ int wave_min_i32(int v) { return __ockl_wfred_min_i32(v); }
+__device__ __forceinline__ void atomic_min_batch(Ctl* c, bool take, int32_t E) {
+    const int mn = __ockl_wfred_min_i32(take ? E : INT32_MAX);
+    if ((threadIdx.x & 63) == 0 && mn != INT32_MAX) atomicMin(&c->batch_minE, mn);
+}
 
-// Key order between the sequences of two slots (words compared as unsigned).
+// Tie order between two slots of equal energy: Zobrist key, then the sequence
+// (words compared as unsigned).
 __device__ __forceinline__ bool key_less(const Table& H, int a, int b) {
+    if (H.hkey[a] != H.hkey[b]) return H.hkey[a] < H.hkey[b];
     for (int w = 0; w < H.W; ++w) {
         uint32_t x = H.seq[(size_t)a * H.W + w], y = H.seq[(size_t)b * H.W + w];
         if (x != y) return x < y;
@@ -121,127 +144,156 @@ __device__ __forceinline__ bool key_less(const Table& H, int a, int b) {
     return false;
 }
 
-enum { INS_DUP = 0, INS_PUSHED = 1, INS_FAIL = 2 };
-
-// Insert the sequence `wrd` (W words) with energy E and key; returns the slot
-// through *slot_out when pushed.  Called by every lane of a wavefront (lanes
-// with active = false do nothing).  The probe loop runs until no lane of the
-// wave is left probing, so no lane leaves it early: a lane that claims a slot
-// publishes it in the same iteration, before any lane of the wave waits on a
-// claimed-but-unpublished slot.  That rules out a wait cycle between waves.
-__device__ int table_insert(const Table& H, const uint32_t* wrd, int32_t E, unsigned long long key,
-                            int* slot_out, Ctl* ctl, bool active) {
-    uint64_t s = key & H.mask;
-    bool done = !active;
-    int res = INS_DUP;
-    uint64_t probes = 0;
-    while (__ballot(!done)) {
-        unsigned long long cur = 0;
-        bool claimed = false;
-        if (!done) {
-            cur = ld_rlx64(&H.hkey[s]);
-            if (cur == 0ull) {
-                unsigned long long prev = atomicCAS(&H.hkey[s], 0ull, key);
-                if (prev == 0ull) claimed = true;
-                else cur = prev;
-            }
-        }
-        if (claimed) {
-            for (int w = 0; w < H.W; ++w) H.seq[s * H.W + w] = wrd[w];
-            H.E[s] = E;
-            __hip_atomic_store(&H.state[s], ST_OPEN, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            *slot_out = (int)s;
-            res = INS_PUSHED;
-            done = true;
-        }
-        {
-            const uint64_t cm = __ballot(claimed);
-            if (cm && (threadIdx.x & 63) == (unsigned)(__ffsll((unsigned long long)cm) - 1))
-                atomicAdd((unsigned long long*)&ctl->claimed, (unsigned long long)__popcll(cm));
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (!done && cur == key) {
-            uint32_t st = ld_acq(&H.state[s]);
-            for (int it = 0; st == 0 && it < kSpinLimit; ++it) {
-                __builtin_amdgcn_s_sleep(2);
-                st = ld_acq(&H.state[s]);
-            }
-            if (st == 0) {
-                atomicExch(&ctl->error, 1);
-                res = INS_FAIL;
-                done = true;
-            } else {
-                bool eq = true;
-                for (int w = 0; w < H.W; ++w)
-                    if (ld_rlx(&H.seq[s * H.W + w]) != wrd[w]) { eq = false; break; }
-                if (eq) {
-                    res = INS_DUP;
-                    if (st == ST_EVICTED &&
-                        atomicCAS(&H.state[s], ST_EVICTED, ST_OPEN) == ST_EVICTED) {
-                        *slot_out = (int)s;
-                        res = INS_PUSHED;
-                    }
-                    done = true;
-                }
-            }
-        }
-        if (!done) {
-            s = (s + 1) & H.mask;
-            if (++probes > H.mask) {
-                atomicExch(&ctl->error, 2);
-                res = INS_FAIL;
-                done = true;
-            }
-        }
-    }
-    return res;
+__device__ __forceinline__ uint32_t src_word(const Params& P, int src, int flip, int w) {
+    if (src < 0) return P.cands[(size_t)(-src - 1) * P.W + w];
+    uint32_t x = P.H.seq[(size_t)src * P.W + w];
+    if (flip > 0 && w == ((flip - 1) >> 5)) x ^= 1u << (31 - ((flip - 1) & 31));
+    return x;
 }
 
-// Unpack W words into the zero-padded int8 array and compute C_1..C_{L-1}.
-__device__ void load_seq_and_c(const uint32_t* words, int L, int8_t* sv, int32_t* Cl, int lane) {
+enum { INS_NONE = 0, INS_CLAIMED = 1, INS_PENDING = 2 };
+
+// Phase 1: claim an empty slot or stop at a slot holding the same key.
+__device__ int claim_or_pend(const Params& P, unsigned long long key, int src, int flip, int32_t E,
+                             int* slot_out) {
+    const Table& H = P.H;
+    uint64_t s = key & H.mask;
+    for (uint64_t probe = 0; probe <= H.mask; ++probe) {
+        const unsigned long long prev = atomicCAS(&H.hkey[s], 0ull, key);
+        if (prev == 0ull) {
+            for (int w = 0; w < H.W; ++w) H.seq[s * H.W + w] = src_word(P, src, flip, w);
+            H.E[s] = E;
+            H.state[s] = ST_OPEN;
+            *slot_out = (int)s;
+            return INS_CLAIMED;
+        }
+        if (prev == key) {
+            *slot_out = (int)s;
+            return INS_PENDING;
+        }
+        s = (s + 1) & H.mask;
+    }
+    atomicExch(&P.ctl->error, 2);
+    return INS_NONE;
+}
+
+__device__ __forceinline__ void push_open(const Params& P, bool take, int32_t E, int slot) {
+    Ctl* c = P.ctl;
+    const long long o = block_append(&c->n_tot, take);
+    if (take && o >= P.cap_o) atomicExch(&c->error, 4);
+    if (take && o < P.cap_o) {
+        P.oE[c->which][o] = E;
+        P.oS[c->which][o] = slot;
+    }
+    atomic_min_batch(c, take, E);
+}
+
+__device__ __forceinline__ void push_pending(const Params& P, bool take, const Pend& pd) {
+    Ctl* c = P.ctl;
+    const long long o = block_append(&c->n_pend, take);
+    if (take && o >= P.cap_pend) atomicExch(&c->error, 5);
+    if (take && o < P.cap_pend) P.pend[o] = pd;
+}
+
+// ---------------------------------------------------------------- seeding
+__global__ __launch_bounds__(64) void k_seed(Params P, long long n_cand) {
+    __shared__ int8_t sv[kSv];
+    const int lane = threadIdx.x;
+    const long long j = blockIdx.x;
+    const int L = P.L, W = P.W;
+    const uint32_t* wrd = P.cands + j * W;
     for (int i = lane; i < kSv; i += 64) sv[i] = 0;
     __syncthreads();
-    for (int x = 1 + lane; x <= L; x += 64) sv[kPad + x] = packed_bit(words, x) ? 1 : -1;
+    for (int x = 1 + lane; x <= L; x += 64) sv[kPad + x] = packed_bit(wrd, x) ? 1 : -1;
     __syncthreads();
+    int e = 0;
     for (int d = 1 + lane; d <= L - 1; d += 64) {
-        int c = 0;
-        for (int i = 1; i <= L - d; ++i) c += (int)sv[kPad + i] * (int)sv[kPad + i + d];
-        Cl[d] = c;
+        int cd = 0;
+        for (int i = 1; i <= L - d; ++i) cd += (int)sv[kPad + i] * (int)sv[kPad + i + d];
+        e += cd * cd;
     }
-    __syncthreads();
-}
-
-__device__ unsigned long long zobrist_of(const int8_t* sv, int L, int lane) {
+    e = __ockl_wfred_add_i32(e);
     unsigned long long h = 0;
     for (int x = 1 + lane; x <= L; x += 64)
         if (sv[kPad + x] > 0) h ^= zob(x - 1);
     for (int o = 32; o > 0; o >>= 1) h ^= __shfl_xor(h, o, 64);
-    return h;
+    const unsigned long long key = h | 1ull;
+    int slot = -1, res = INS_NONE;
+    if (lane == 0) res = claim_or_pend(P, key, (int)(-j - 1), 0, e, &slot);
+    push_open(P, res == INS_CLAIMED, e, slot);
+    Pend pd{slot, (int)(-j - 1), 0, e};
+    push_pending(P, res == INS_PENDING, pd);
 }
 
-// ---------------------------------------------------------------- seeding
-__global__ __launch_bounds__(64) void k_seed(Params P, const uint32_t* cand, long long n_cand) {
-    __shared__ int8_t sv[kSv];
-    __shared__ int32_t Cl[kMaxL + 1];
-    __shared__ uint32_t wrd[32];
-    const int lane = threadIdx.x;
-    const long long j = blockIdx.x;
-    const int L = P.L, W = P.W;
-    if (lane < W) wrd[lane] = cand[j * W + lane];
-    __syncthreads();
-    load_seq_and_c(wrd, L, sv, Cl, lane);
-    int e = 0;
-    for (int d = 1 + lane; d <= L - 1; d += 64) e += Cl[d] * Cl[d];
-    e = __ockl_wfred_add_i32(e);
-    unsigned long long key = zobrist_of(sv, L, lane) | 1ull;
-    int slot = -1;
-    const int res = table_insert(P.H, wrd, e, key, &slot, P.ctl, lane == 0);
-    const bool take = lane == 0 && res == INS_PUSHED;
-    long long idx = wave_append(&P.ctl->n_tot, take);
-    if (take) {
-        P.oE[0][idx] = e;
-        P.oS[0][idx] = slot;
-        atomicAdd((unsigned long long*)&P.ctl->n_live, 1ull);
+// ---------------------------------------------------------------- phases 2 and 3
+__global__ __launch_bounds__(512) void k_resolve(Params P) {
+    Ctl* c = P.ctl;
+    if (c->stop) return;
+    const long long n = c->n_pend < P.cap_pend ? c->n_pend : P.cap_pend;
+    for (long long base = (long long)blockIdx.x * blockDim.x; base < n;
+         base += (long long)gridDim.x * blockDim.x) {
+        const long long q = base + threadIdx.x;
+        bool pushed = false, coll = false;
+        Pend pd{0, 0, 0, 0};
+        if (q < n) {
+            pd = P.pend[q];
+            bool eq = true;
+            for (int w = 0; w < P.W; ++w)
+                if (P.H.seq[(size_t)pd.slot * P.W + w] != src_word(P, pd.src, pd.flip, w)) {
+                    eq = false;
+                    break;
+                }
+            if (!eq) coll = true;
+            else if (P.H.state[pd.slot] == ST_EVICTED &&
+                     atomicCAS(&P.H.state[pd.slot], ST_EVICTED, ST_OPEN) == ST_EVICTED)
+                pushed = true;
+        }
+        push_open(P, pushed, pd.E, pd.slot);
+        const long long o = block_append(&c->n_slow, coll);
+        if (coll && o < P.cap_pend) P.slow[o] = pd;
+    }
+}
+
+// Phase 3: key collisions, one at a time (no concurrency, so plain accesses).
+__global__ void k_slow(Params P) {
+    Ctl* c = P.ctl;
+    if (c->stop || c->n_slow == 0) return;
+    const Table& H = P.H;
+    const long long n = c->n_slow < P.cap_pend ? c->n_slow : P.cap_pend;
+    for (long long q = 0; q < n; ++q) {
+        const Pend pd = P.slow[q];
+        const unsigned long long key = H.hkey[pd.slot];
+        uint64_t s = (pd.slot + 1) & H.mask;
+        for (uint64_t probe = 0; probe <= H.mask; ++probe, s = (s + 1) & H.mask) {
+            if (H.hkey[s] == 0ull) {
+                H.hkey[s] = key;
+                for (int w = 0; w < H.W; ++w) H.seq[s * H.W + w] = src_word(P, pd.src, pd.flip, w);
+                H.E[s] = pd.E;
+                H.state[s] = ST_OPEN;
+                const long long o = c->n_tot++;
+                if (o < P.cap_o) {
+                    P.oE[c->which][o] = pd.E;
+                    P.oS[c->which][o] = (int)s;
+                }
+                if (pd.E < c->batch_minE) c->batch_minE = pd.E;
+                break;
+            }
+            if (H.hkey[s] != key) continue;
+            bool eq = true;
+            for (int w = 0; w < H.W; ++w)
+                if (H.seq[s * H.W + w] != src_word(P, pd.src, pd.flip, w)) { eq = false; break; }
+            if (!eq) continue;
+            if (H.state[s] == ST_EVICTED) {
+                H.state[s] = ST_OPEN;
+                const long long o = c->n_tot++;
+                if (o < P.cap_o) {
+                    P.oE[c->which][o] = pd.E;
+                    P.oS[c->which][o] = (int)s;
+                }
+                if (pd.E < c->batch_minE) c->batch_minE = pd.E;
+            }
+            break;
+        }
     }
 }
 
@@ -257,52 +309,29 @@ __global__ void k_round_begin(Params P) {
     if (T > P.B) T = P.B;
     c->T = T;
     c->sel_enabled = 1;
+    c->sel_all = T >= c->n_live ? 1 : 0;
     c->n_piv = 0;
+    c->n_pend = 0;
+    c->n_slow = 0;
+    c->batch_begin = c->n_tot;
     c->batch_minE = INT32_MAX;
     c->improved = 0;
-    c->need_compact = (c->n_tot + (long long)P.B * P.L > P.cap_o) ? 1 : 0;
-    c->compact_count = 0;
-}
-
-// Move live entries to the other buffer when space runs short.
-__global__ void k_compact(Params P) {
-    Ctl* c = P.ctl;
-    if (c->stop || !c->need_compact) return;
-    const int src = c->which;
-    const long long n = c->n_tot;
-    for (long long base = (long long)blockIdx.x * blockDim.x; base < n;
-         base += (long long)gridDim.x * blockDim.x) {
-        const long long i = base + threadIdx.x;
-        const bool live = i < n && P.oE[src][i] != DEAD;
-        const long long o = wave_append(&c->compact_count, live);
-        if (live) {
-            P.oE[1 - src][o] = P.oE[src][i];
-            P.oS[1 - src][o] = P.oS[src][i];
-        }
-    }
-}
-
-__global__ void k_compact_fin(Params P) {
-    Ctl* c = P.ctl;
-    if (c->stop || !c->need_compact) return;
-    c->n_tot = c->compact_count;
-    c->which ^= 1;
+    c->emin = UINT32_MAX;
+    c->emax = 0;
+    c->out_count = 0;
 }
 
 // ---------------------------------------------------------------- selection
 // Selects the T smallest live Open entries in key order into flag[].
-__global__ void k_sel_reset(Params P) {
+__global__ __launch_bounds__(kSelThreads) void k_sel_minmax(Params P) {
     Ctl* c = P.ctl;
-    if (c->stop || !c->sel_enabled) return;
-    c->emin = UINT32_MAX;
-    c->emax = 0;
-    c->n_cand = 0;
-    c->sel_all = c->T >= c->n_live ? 1 : 0;
-}
-
-__global__ void k_sel_minmax(Params P) {
-    Ctl* c = P.ctl;
-    if (c->stop || !c->sel_enabled) return;
+    if (c->stop || !c->sel_enabled || c->sel_all) return;
+    __shared__ uint32_t smn, smx;
+    if (threadIdx.x == 0) {
+        smn = UINT32_MAX;
+        smx = 0;
+    }
+    __syncthreads();
     const int cur = c->which;
     uint32_t mn = UINT32_MAX, mx = 0;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < c->n_tot;
@@ -316,34 +345,44 @@ __global__ void k_sel_minmax(Params P) {
     mn = (uint32_t)__ockl_wfred_min_i32((int)min(mn, (uint32_t)INT32_MAX));
     mx = __ockl_wfred_max_u32(mx);
     if ((threadIdx.x & 63) == 0) {
-        atomicMin(&c->emin, mn);
-        atomicMax(&c->emax, mx);
+        atomicMin(&smn, mn);
+        atomicMax(&smx, mx);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicMin(&c->emin, smn);
+        atomicMax(&c->emax, smx);
     }
 }
 
-__global__ void k_sel_setup(Params P) {
-    Ctl* c = P.ctl;
-    if (c->stop || !c->sel_enabled) return;
-    const uint32_t R = c->emax - c->emin;
-    const int nbits = R ? 32 - __clz((int)R) : 0;
-    c->hi_shift = nbits;
-    c->lo_shift = nbits > kSelBits ? nbits - kSelBits : 0;
-    c->prefix = 0;
-    c->c_lt = 0;
-    c->need = c->T;
-    c->resolved = (nbits == 0) ? 1 : 0;
-    c->Dt = 0;
+// Level 0 derives the digit layout from [emin, emax]; later levels read it back.
+__device__ __forceinline__ void level_shifts(const Ctl* c, int level, int* hs, int* ls, uint32_t* prefix) {
+    if (level == 0) {
+        const uint32_t R = c->emax - c->emin;
+        const int nbits = R ? 32 - __clz((int)R) : 0;
+        *hs = nbits;
+        *ls = nbits > kSelBits ? nbits - kSelBits : 0;
+        *prefix = 0;
+    } else {
+        *hs = c->hi_shift;
+        *ls = c->lo_shift;
+        *prefix = c->prefix;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_sel_hist(Params P) {
+__global__ __launch_bounds__(kSelThreads) void k_sel_hist(Params P, int level) {
     Ctl* c = P.ctl;
-    if (c->stop || !c->sel_enabled || c->sel_all || c->resolved) return;
+    if (c->stop || !c->sel_enabled || c->sel_all) return;
+    if (level > 0 && c->resolved) return;
+    if (level == 0 && c->emax == c->emin) return;
     __shared__ uint32_t h[kSelBins];
     for (int b = threadIdx.x; b < kSelBins; b += blockDim.x) h[b] = 0;
     __syncthreads();
+    int hs, ls;
+    uint32_t prefix;
+    level_shifts(c, level, &hs, &ls, &prefix);
     const int cur = c->which;
-    const uint32_t emin = c->emin, prefix = c->prefix;
-    const int hs = c->hi_shift, ls = c->lo_shift;
+    const uint32_t emin = c->emin;
     const uint32_t dmask = (1u << (hs - ls)) - 1u;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < c->n_tot;
          i += (long long)gridDim.x * blockDim.x) {
@@ -354,17 +393,33 @@ __global__ __launch_bounds__(256) void k_sel_hist(Params P) {
         atomicAdd(&h[(D >> ls) & dmask], 1u);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < kSelBins; b += blockDim.x)
-        if (h[b]) atomicAdd(&P.ghist[b], h[b]);
+    uint32_t* row = P.ghist + (size_t)blockIdx.x * kSelBins;
+    for (int b = threadIdx.x; b < kSelBins; b += blockDim.x) row[b] = h[b];
 }
 
-__global__ __launch_bounds__(1024) void k_sel_find(Params P) {
+__global__ __launch_bounds__(1024) void k_sel_find(Params P, int level) {
     Ctl* c = P.ctl;
-    if (c->stop || !c->sel_enabled || c->sel_all || c->resolved) return;
-    __shared__ uint32_t part[1024];
-    // 2 bins per thread
+    if (c->stop || !c->sel_enabled || c->sel_all) return;
+    if (level > 0 && c->resolved) return;
     const int t = threadIdx.x;
-    const uint32_t a = P.ghist[2 * t], b = P.ghist[2 * t + 1];
+    if (level == 0 && c->emax == c->emin) {   // every live entry has one energy
+        if (t == 0) {
+            c->c_lt = 0;
+            c->resolved = 1;
+            c->Dt = 0;
+        }
+        return;
+    }
+    __shared__ uint32_t part[1024];
+    int hs, ls;
+    uint32_t prefix;
+    level_shifts(c, level, &hs, &ls, &prefix);
+    const long long c_lt = level == 0 ? 0 : c->c_lt;
+    uint32_t a = 0, b = 0;
+    for (int r = 0; r < kSelBlocks; ++r) {
+        a += P.ghist[(size_t)r * kSelBins + 2 * t];
+        b += P.ghist[(size_t)r * kSelBins + 2 * t + 1];
+    }
     part[t] = a + b;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
@@ -373,7 +428,7 @@ __global__ __launch_bounds__(1024) void k_sel_find(Params P) {
         part[t] += x;
         __syncthreads();
     }
-    const long long need = c->need - c->c_lt;   // entries still to take at this level
+    const long long need = c->T - c_lt;
     const long long before = (long long)part[t] - (a + b);
     int v = -1;
     long long below = 0;
@@ -384,25 +439,22 @@ __global__ __launch_bounds__(1024) void k_sel_find(Params P) {
         v = 2 * t + 1;
         below = before + a;
     }
-    __syncthreads();
     if (v >= 0) {
-        const int hs = c->hi_shift, ls = c->lo_shift;
-        c->c_lt += below;
-        c->prefix = (c->prefix << (hs - ls)) | (uint32_t)v;
+        c->c_lt = c_lt + below;
+        const uint32_t np = (prefix << (hs - ls)) | (uint32_t)v;
+        c->prefix = np;
         if (ls == 0) {
             c->resolved = 1;
-            c->Dt = c->prefix;
+            c->Dt = np;
         } else {
+            c->resolved = 0;
             c->hi_shift = ls;
             c->lo_shift = ls > kSelBits ? ls - kSelBits : 0;
         }
     }
-    __syncthreads();
-    P.ghist[2 * t] = 0;
-    P.ghist[2 * t + 1] = 0;
 }
 
-__global__ void k_sel_classify(Params P) {
+__global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
     Ctl* c = P.ctl;
     if (c->stop || !c->sel_enabled) return;
     const int cur = c->which;
@@ -421,42 +473,72 @@ __global__ void k_sel_classify(Params P) {
             }
             P.flag[i] = f;
         }
-        const uint64_t m = __ballot(tie);
-        if (m) {
-            const int lane = threadIdx.x & 63;
-            const int leader = __ffsll((unsigned long long)m) - 1;
-            int base_idx = 0;
-            if (lane == leader) base_idx = atomicAdd(&c->n_cand, __popcll(m));
-            base_idx = __shfl(base_idx, leader, 64);
-            const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-            if (tie) P.cand[0][base_idx + __popcll(m & lt)] = (int32_t)i;
-        }
+        const long long o = block_append(&c->out_count, tie);
+        if (tie) P.cand[0][o] = (int32_t)i;
     }
 }
 
-// Among the tied candidates, flag the `need - c_lt` smallest by sequence.
+// Tie digits of a slot: bytes 0..7 are the Zobrist key (most significant first),
+// bytes 8.. the packed sequence.
+__device__ __forceinline__ int tie_digit(const Table& H, int slot, int pos) {
+    if (pos < 8) return (int)((H.hkey[slot] >> (56 - 8 * pos)) & 255ull);
+    const int q = pos - 8;
+    return (int)((H.seq[(size_t)slot * H.W + (q >> 2)] >> (24 - 8 * (q & 3))) & 255u);
+}
+
+// First tie-digit position >= pos at which slots a and b differ (npos if none).
+__device__ __forceinline__ int first_diff(const Table& H, int a, int b, int pos, int npos) {
+    if (pos < 8) {
+        unsigned long long x = H.hkey[a] ^ H.hkey[b];
+        x &= ~0ull >> (8 * pos);
+        if (x) return __clzll((long long)x) >> 3;
+        pos = 8;
+    }
+    const int q0 = pos - 8;
+    for (int w = q0 >> 2; w < H.W; ++w) {
+        uint32_t x = H.seq[(size_t)a * H.W + w] ^ H.seq[(size_t)b * H.W + w];
+        if (w == (q0 >> 2)) x &= 0xffffffffu >> (8 * (q0 & 3));
+        if (x) return 8 + 4 * w + (__clz((int)x) >> 3);
+    }
+    return npos;
+}
+
+// Among the tied candidates, flag the `T - c_lt` smallest in tie order: an MSD
+// byte-wise radix select over the tie digits.  Each iteration first finds, in one
+// pass, the first digit position (from `pos` on) at which any candidate differs
+// from the first one, then partitions the candidates on that digit.
 __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
     Ctl* c = P.ctl;
     if (c->stop || !c->sel_enabled || c->sel_all) return;
     __shared__ uint32_t h[256];
-    __shared__ int s_v, s_m2;
+    __shared__ int s_pos, s_v, s_m2;
     __shared__ long long s_r;
     const int cur = c->which;
     const int t = threadIdx.x;
-    int m = c->n_cand;
-    long long r = c->need - c->c_lt;
+    const int npos = 8 + 4 * P.W;
+    int m = (int)c->out_count;
+    long long r = c->T - c->c_lt;
     int src = 0;
-    const int W = P.W;
-    for (int pos = 0; pos < 4 * W && r > 0; ++pos) {
-        if (r == m) break;
-        const int w = pos >> 2, sh = 24 - 8 * (pos & 3);
-        for (int b = t; b < 256; b += blockDim.x) h[b] = 0;
+    int pos = 0;
+    while (pos < npos && r > 0 && r < m) {
+        if (t == 0) s_pos = npos;
+        __syncthreads();
+        const int ref = P.oS[cur][P.cand[src][0]];
+        int first = npos;
+        for (int q = t; q < m; q += blockDim.x) {
+            const int d = first_diff(P.H, P.oS[cur][P.cand[src][q]], ref, pos, npos);
+            first = d < first ? d : first;
+        }
+        first = __ockl_wfred_min_i32(first);
+        if ((t & 63) == 0) atomicMin(&s_pos, first);
+        __syncthreads();
+        pos = s_pos;
+        if (pos >= npos) break;   // all remaining candidates equal: cannot happen for a set
+        for (int k = t; k < 256; k += blockDim.x) h[k] = 0;
         if (t == 0) s_m2 = 0;
         __syncthreads();
-        for (int q = t; q < m; q += blockDim.x) {
-            const int slot = P.oS[cur][P.cand[src][q]];
-            atomicAdd(&h[(P.H.seq[(size_t)slot * W + w] >> sh) & 255u], 1u);
-        }
+        for (int q = t; q < m; q += blockDim.x)
+            atomicAdd(&h[tie_digit(P.H, P.oS[cur][P.cand[src][q]], pos)], 1u);
         __syncthreads();
         if (t == 0) {
             long long cum = 0;
@@ -472,8 +554,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         const int v = s_v;
         for (int q = t; q < m; q += blockDim.x) {
             const int idx = P.cand[src][q];
-            const int slot = P.oS[cur][idx];
-            const int dgt = (P.H.seq[(size_t)slot * W + w] >> sh) & 255u;
+            const int dgt = tie_digit(P.H, P.oS[cur][idx], pos);
             if (dgt < v) P.flag[idx] = 1;
             else if (dgt == v) P.cand[1 - src][atomicAdd(&s_m2, 1)] = idx;
         }
@@ -481,6 +562,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         m = s_m2;
         r = s_r;
         src = 1 - src;
+        pos += 1;
         __syncthreads();
     }
     if (r > 0)
@@ -488,7 +570,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
 }
 
 // ---------------------------------------------------------------- pop / expand
-__global__ void k_pop(Params P) {
+__global__ __launch_bounds__(kSelThreads) void k_pop(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
     const int cur = c->which;
@@ -496,7 +578,7 @@ __global__ void k_pop(Params P) {
          base += (long long)gridDim.x * blockDim.x) {
         const long long i = base + threadIdx.x;
         const bool take = i < c->n_tot && P.flag[i] && P.oE[cur][i] != DEAD;
-        const long long o = wave_append(&c->n_piv, take);
+        const long long o = block_append(&c->n_piv, take);
         if (take && o >= P.B) atomicExch(&c->error, 3);
         if (take && o < P.B) {
             const int slot = P.oS[cur][i];
@@ -507,15 +589,8 @@ __global__ void k_pop(Params P) {
     }
 }
 
-__global__ void k_pop_fin(Params P) {
-    Ctl* c = P.ctl;
-    if (c->stop) return;
-    c->expansions += c->n_piv;
-    c->n_live -= c->n_piv;
-    c->batch_begin = c->n_tot;
-}
-
-__global__ __launch_bounds__(64) void k_expand(Params P) {
+// Direct O(L^2) expansion, one wavefront per pivot: the fallback for L > 641.
+__global__ __launch_bounds__(64) void k_expand_direct(Params P) {
     Ctl* c = P.ctl;
     if (c->stop || (long long)blockIdx.x >= c->n_piv) return;
     __shared__ int8_t sv[kSv];
@@ -523,20 +598,28 @@ __global__ __launch_bounds__(64) void k_expand(Params P) {
     __shared__ uint32_t pk[32];
     const int lane = threadIdx.x;
     const int L = P.L, W = P.W;
-    const int cur = c->which;
     const int ps = P.piv[blockIdx.x];
     const int32_t Ep = P.H.E[ps];
     if (lane < W) pk[lane] = P.H.seq[(size_t)ps * W + lane];
+    for (int i = lane; i < kSv; i += 64) sv[i] = 0;
     __syncthreads();
-    load_seq_and_c(pk, L, sv, Cl, lane);
-    const unsigned long long hp = zobrist_of(sv, L, lane);
-    uint32_t nb[32];
+    for (int x = 1 + lane; x <= L; x += 64) sv[kPad + x] = packed_bit(pk, x) ? 1 : -1;
+    __syncthreads();
+    for (int d = 1 + lane; d <= L - 1; d += 64) {
+        int cd = 0;
+        for (int i = 1; i <= L - d; ++i) cd += (int)sv[kPad + i] * (int)sv[kPad + i + d];
+        Cl[d] = cd;
+    }
+    __syncthreads();
+    unsigned long long hp = 0;
+    for (int x = 1 + lane; x <= L; x += 64)
+        if (sv[kPad + x] > 0) hp ^= zob(x - 1);
+    for (int o = 32; o > 0; o >>= 1) hp ^= __shfl_xor(hp, o, 64);
     for (int r0 = 0; r0 < L; r0 += 64) {
         const int i = 1 + r0 + lane;
         const bool valid = i <= L;
-        int slot = -1;
+        int slot = -1, res = INS_NONE;
         int32_t En = 0;
-        unsigned long long key = 0;
         if (valid) {
             const int si = sv[kPad + i];
             int g = 0, q = 0;
@@ -546,43 +629,199 @@ __global__ __launch_bounds__(64) void k_expand(Params P) {
                 q += t * t;
             }
             En = Ep - 4 * si * g + 4 * q;
-            for (int w = 0; w < W; ++w) nb[w] = pk[w];
-            nb[(i - 1) >> 5] ^= 1u << (31 - ((i - 1) & 31));
-            key = (hp ^ zob(i - 1)) | 1ull;
+            res = claim_or_pend(P, (hp ^ zob(i - 1)) | 1ull, ps, i, En, &slot);
         }
-        const int res = table_insert(P.H, nb, En, key, &slot, c, valid);
-        const bool take = res == INS_PUSHED;
-        const long long o = wave_append(&c->n_tot, take);
-        if (take && o >= P.cap_o) atomicExch(&c->error, 4);
-        if (take && o < P.cap_o) {
-            P.oE[cur][o] = En;
-            P.oS[cur][o] = slot;
-        }
-        const int mn = wave_min_i32(take ? En : INT32_MAX);
-        if (lane == 0 && mn != INT32_MAX) atomicMin(&c->batch_minE, mn);
+        push_open(P, res == INS_CLAIMED, En, slot);
+        Pend pd{slot, ps, i, En};
+        push_pending(P, res == INS_PENDING, pd);
     }
+}
+
+// Bit-sliced expansion, 4 wavefronts per pivot.  For the single flip of s_i:
+//   dE_i = sum_d dC_d (2 C_d + dC_d),  dC_d = -2 s_i t_d,  t_d = s_{i+d}[valid] + s_{i-d}[valid]
+//        = -4 s_i G_i + 4 Q_i,   G_i = sum_d C_d t_d,   Q_i = sum_d t_d^2.
+// With windows F_i = V >> i and B_i = VR >> (N-i+1) (bit d-1 = digit of s_{i+d} /
+// s_{i-d}, 0 outside 1..L) and the two's-complement bit planes P_j of (C_d)_d:
+//   G_i = 2 sum_j w_j (popc(P_j & F_i) + popc(P_j & B_i)) - PC[L-i] - PC[i-1],
+//   Q_i = (L-1) + 2 (M - 2 popc((F_i ^ B_i) & [d <= M])),  M = min(L-i, i-1),
+// PC being the prefix sums of C_d.  C_d itself is (L-d) - 2 popc((V ^ V>>d) & [j < L-d]).
+template <int NW2, int R2>
+__global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
+    Ctl* c = P.ctl;
+    if (c->stop || (long long)blockIdx.x >= c->n_piv) return;
+    constexpr int NQ2 = (NW2 + 1) / 2;      // chunks of 64 lags
+    constexpr int NVW = 2 * NW2 + 8;
+    __shared__ uint32_t V[NVW], VR[NVW], pk[32];
+    __shared__ int32_t Cl[32 * NW2 + 1], PC[32 * NW2 + 1];
+    __shared__ unsigned long long hpart[kExThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int L = P.L, W = P.W;
+    const int ps = P.piv[blockIdx.x];
+    const int32_t Ep = P.H.E[ps];
+    // V bit j = digit of s_{j+1} (LSB first): word w is the bit-reversed packed word;
+    // VR (reversal over N = 32W bits): word W-1-w is the packed word itself.
+    for (int w = tid; w < NVW; w += kExThreads) {
+        uint32_t x = 0, y = 0;
+        if (w < W) {
+            x = P.H.seq[(size_t)ps * W + w];
+            pk[w] = x;
+            y = P.H.seq[(size_t)ps * W + (W - 1 - w)];
+        }
+        V[w] = __builtin_bitreverse32(x);
+        VR[w] = y;
+    }
+    __syncthreads();
+    for (int d = 1 + tid; d <= 32 * NW2; d += kExThreads) {
+        int cd = 0;
+        if (d <= L - 1) {
+            const int q = d >> 5, r = d & 31, n = L - d;
+            int dis = 0;
+            for (int w = 0; w * 32 < n; ++w) {
+                const uint32_t sh = __builtin_amdgcn_alignbit(V[w + q + 1], V[w + q], r);
+                const int left = n - 32 * w;
+                const uint32_t m = left >= 32 ? 0xffffffffu : ((1u << left) - 1u);
+                dis += __popc((V[w] ^ sh) & m);
+            }
+            cd = n - 2 * dis;
+        }
+        Cl[d] = cd;
+    }
+    if (tid == 0) Cl[0] = 0;
+    __syncthreads();
+    if (wv == 0) {
+        int carry = 0;
+        for (int base = 0; base <= 32 * NW2; base += 64) {
+            int v = (base + lane <= 32 * NW2 && base + lane >= 1) ? Cl[base + lane] : 0;
+            for (int o = 1; o < 64; o <<= 1) {
+                int u = __shfl_up(v, o, 64);
+                if (lane >= o) v += u;
+            }
+            if (base + lane <= 32 * NW2) PC[base + lane] = carry + v;
+            carry += __shfl(v, 63, 64);
+        }
+    }
+    unsigned long long hz = 0;
+    for (int x = 1 + tid; x <= L; x += kExThreads)
+        if ((pk[(x - 1) >> 5] >> (31 - ((x - 1) & 31))) & 1u) hz ^= zob(x - 1);
+    for (int o = 32; o > 0; o >>= 1) hz ^= __shfl_xor(hz, o, 64);
+    if (lane == 0) hpart[wv] = hz;
+    __syncthreads();
+    unsigned long long hp = 0;
+    for (int k = 0; k < kExThreads / 64; ++k) hp ^= hpart[k];
+    int32_t Cq[NQ2];
+    uint32_t orv = 0;
+#pragma unroll
+    for (int q = 0; q < NQ2; ++q) {
+        const int d = 64 * q + lane + 1;
+        Cq[q] = d <= 32 * NW2 ? Cl[d] : 0;
+        orv |= (uint32_t)(Cq[q] ^ (Cq[q] >> 31));
+    }
+    orv = __ockl_wfred_or_u32(orv);
+    const int nb = (32 - __clz((int)orv)) + 1;
+    const int N = 32 * W;
+    uint32_t F[R2][NW2], B[R2][NW2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+        int i = 1 + lane + 64 * (wv + 4 * r);
+        if (i > L) i = L;
+        const int qf = i >> 5, hf = i & 31;
+        const int sb = N - i + 1, qb = sb >> 5, hb = sb & 31;
+#pragma unroll
+        for (int w = 0; w < NW2; ++w) {
+            F[r][w] = __builtin_amdgcn_alignbit(V[qf + w + 1], V[qf + w], hf);
+            B[r][w] = __builtin_amdgcn_alignbit(VR[qb + w + 1], VR[qb + w], hb);
+        }
+    }
+    int32_t H[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) H[r] = 0;
+    for (int jp = 0; jp < nb; ++jp) {
+        uint32_t acc[R2];
+#pragma unroll
+        for (int r = 0; r < R2; ++r) acc[r] = 0;
+#pragma unroll
+        for (int q = 0; q < NQ2; ++q) {
+            const uint64_t bal = __ballot((Cq[q] >> jp) & 1);
+            const uint32_t lo = (uint32_t)bal, hi = (uint32_t)(bal >> 32);
+#pragma unroll
+            for (int r = 0; r < R2; ++r) {
+                acc[r] += __popc(lo & F[r][2 * q]) + __popc(lo & B[r][2 * q]);
+                if (2 * q + 1 < NW2) acc[r] += __popc(hi & F[r][2 * q + 1]) + __popc(hi & B[r][2 * q + 1]);
+            }
+        }
+        const int wgt = (jp == nb - 1) ? -(1 << jp) : (1 << jp);
+#pragma unroll
+        for (int r = 0; r < R2; ++r) H[r] += wgt * (int)acc[r];
+    }
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+        const int i0 = 1 + lane + 64 * (wv + 4 * r);
+        const bool valid = i0 <= L;
+        const int i = valid ? i0 : L;
+        const int Mf = L - i, Mb = i - 1, M = Mf < Mb ? Mf : Mb;
+        int dis = 0;
+#pragma unroll
+        for (int w = 0; w < NW2; ++w) {
+            const int left = M - 32 * w;
+            const uint32_t m = left >= 32 ? 0xffffffffu : (left <= 0 ? 0u : ((1u << left) - 1u));
+            dis += __popc((F[r][w] ^ B[r][w]) & m);
+        }
+        const int si = ((pk[(i - 1) >> 5] >> (31 - ((i - 1) & 31))) & 1u) ? 1 : -1;
+        const int G = 2 * H[r] - PC[Mf] - PC[Mb];
+        const int Q = (L - 1) + 2 * (M - 2 * dis);
+        const int32_t En = Ep - 4 * si * G + 4 * Q;
+        int slot = -1, res = INS_NONE;
+        if (valid) res = claim_or_pend(P, (hp ^ zob(i - 1)) | 1ull, ps, i, En, &slot);
+        push_open(P, res == INS_CLAIMED, En, slot);
+        Pend pd{slot, ps, i, En};
+        push_pending(P, res == INS_PENDING, pd);
+    }
+}
+
+typedef void (*expand_kernel_t)(Params);
+
+expand_kernel_t pick_expand(int L, unsigned* threads) {
+    const int nw2 = (L - 1 + 31) / 32;
+    const int r2 = (L + kExThreads - 1) / kExThreads;
+    *threads = kExThreads;
+#define EXP(NWV, RV) if (nw2 <= NWV && r2 <= RV) return k_expand<NWV, RV>;
+    EXP(2, 1) EXP(4, 1) EXP(8, 1) EXP(12, 2) EXP(16, 2) EXP(17, 3) EXP(20, 3)
+#undef EXP
+    *threads = 64;
+    return k_expand_direct;
 }
 
 __global__ void k_expand_fin(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
+    c->expansions += c->n_piv;
+    c->n_live -= c->n_piv;
     const long long n_new = c->n_tot - c->batch_begin;
     c->pushes += n_new;
     c->dups += c->n_piv * P.L - n_new;
     c->n_live += n_new;
+    c->claimed += n_new;   // re-pushes claim nothing: an over-count, so rebuilds come early
     if (c->batch_minE < c->best_E) c->improved = 1;
     else c->u += c->n_piv;
+    // capacity cut setup
+    c->T = P.Q;
+    c->sel_enabled = c->n_live > P.Q ? 1 : 0;
+    c->sel_all = 0;
+    c->emin = UINT32_MAX;
+    c->emax = 0;
+    c->survivors = 0;
+    c->out_count = 0;
 }
 
-// best = smallest key among live entries in [lo, n_tot) with E == target.
+// best = smallest key among live entries in [batch_begin, n_tot) with E == batch_minE.
 __global__ __launch_bounds__(1024) void k_best(Params P, int initial) {
     Ctl* c = P.ctl;
     if (c->stop) return;
     if (!initial && !c->improved) return;
     __shared__ int best[1024];
     const int cur = c->which;
-    const long long lo = initial ? 0 : c->batch_begin;
-    const int32_t target = initial ? (int32_t)c->emin : c->batch_minE;
+    const long long lo = c->batch_begin;
+    const int32_t target = c->batch_minE;
     int mine = -1;
     for (long long i = lo + threadIdx.x; i < c->n_tot; i += blockDim.x) {
         if (P.oE[cur][i] != target) continue;
@@ -610,37 +849,38 @@ __global__ __launch_bounds__(1024) void k_best(Params P, int initial) {
     }
 }
 
-__global__ void k_evict_setup(Params P) {
+// Keep the flagged live entries (all live entries when no cut is needed) in the
+// other buffer; the rest become EVICTED.
+__global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
-    c->sel_enabled = c->n_live > P.Q ? 1 : 0;
-    c->T = P.Q;
-}
-
-__global__ void k_evict(Params P) {
-    Ctl* c = P.ctl;
-    if (c->stop || !c->sel_enabled) return;
     const int cur = c->which;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < c->n_tot;
-         i += (long long)gridDim.x * blockDim.x) {
-        if (P.oE[cur][i] == DEAD || P.flag[i]) continue;
-        P.H.state[P.oS[cur][i]] = ST_EVICTED;
-        P.oE[cur][i] = DEAD;
+    const bool cut = c->sel_enabled;
+    for (long long base = (long long)blockIdx.x * blockDim.x; base < c->n_tot;
+         base += (long long)gridDim.x * blockDim.x) {
+        const long long i = base + threadIdx.x;
+        bool keep = false;
+        if (i < c->n_tot && P.oE[cur][i] != DEAD) {
+            keep = !cut || P.flag[i];
+            if (!keep) P.H.state[P.oS[cur][i]] = ST_EVICTED;
+        }
+        const long long o = block_append(&c->survivors, keep);
+        if (keep) {
+            P.oE[1 - cur][o] = P.oE[cur][i];
+            P.oS[1 - cur][o] = P.oS[cur][i];
+        }
     }
 }
 
-__global__ void k_evict_fin(Params P) {
-    Ctl* c = P.ctl;
-    if (c->stop || !c->sel_enabled) return;
-    c->evictions += c->n_live - P.Q;
-    c->n_live = P.Q;
-    c->sel_enabled = 0;
-}
-
-__global__ void k_round_end(Params P) {
+__global__ void k_round_end(Params P, int count_round) {
     Ctl* c = P.ctl;
     if (c->stop) return;
-    c->rounds += 1;
+    if (c->sel_enabled) c->evictions += c->n_live - c->survivors;
+    c->n_live = c->survivors;
+    c->n_tot = c->survivors;
+    c->which ^= 1;
+    c->sel_enabled = 0;
+    if (count_round) c->rounds += 1;
 }
 
 __global__ void k_outputs(Params P, uint32_t* best_seq, int32_t* best_E, labs_step2_stats* st,
@@ -661,18 +901,14 @@ __global__ void k_outputs(Params P, uint32_t* best_seq, int32_t* best_E, labs_st
         st->best_round = c->best_round;
     }
     if (!open_seqs && !open_E) return;
-    // live entries in list order; ranks via one block-serial prefix is too slow,
-    // so emit with a counter (order is unspecified by the ABI)
     const int cur = c->which;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < c->n_tot;
          i += (long long)gridDim.x * blockDim.x) {
-        if (P.oE[cur][i] == DEAD) continue;
-        const long long o = (long long)atomicAdd((unsigned long long*)&c->compact_count, 1ull);
-        if (o >= open_cap) continue;
+        if (P.oE[cur][i] == DEAD || i >= open_cap) continue;
         const int s = P.oS[cur][i];
-        if (open_E) open_E[o] = P.oE[cur][i];
+        if (open_E) open_E[i] = P.oE[cur][i];
         if (open_seqs)
-            for (int w = 0; w < W; ++w) open_seqs[o * W + w] = P.H.seq[(size_t)s * W + w];
+            for (int w = 0; w < W; ++w) open_seqs[i * W + w] = P.H.seq[(size_t)s * W + w];
     }
 }
 
@@ -721,15 +957,36 @@ __global__ void k_init_ctl(Ctl* c) {
     *c = z;
 }
 
-__global__ void k_prepare_outputs(Ctl* c) { c->compact_count = 0; }
+// After seeding: count the live entries and set up the capacity cut.
+__global__ void k_seed_fin(Params P) {
+    Ctl* c = P.ctl;
+    c->n_live = c->n_tot;
+    c->claimed = c->n_tot;
+    c->T = P.Q;
+    c->sel_enabled = c->n_live > P.Q ? 1 : 0;
+    c->sel_all = 0;
+    c->emin = UINT32_MAX;
+    c->emax = 0;
+    c->survivors = 0;
+    c->out_count = 0;
+}
 
-// The initial best is the smallest live entry; k_sel_minmax provides its energy.
-__global__ void k_initial_best_setup(Params P) { P.ctl->sel_enabled = 1; }
+// Before the initial best: the whole (cut) Open list is the "batch".
+__global__ void k_seed_best_setup(Ctl* c) {
+    c->batch_begin = 0;
+    c->batch_minE = INT32_MAX;
+}
 
-inline unsigned grid_for(long long n, int t, unsigned cap = 2048) {
-    long long b = (n + t - 1) / t;
-    if (b < 1) b = 1;
-    return (unsigned)(b > cap ? cap : b);
+// Minimum E over live entries into batch_minE (the initial best's energy).
+__global__ __launch_bounds__(kSelThreads) void k_min_live(Params P) {
+    Ctl* c = P.ctl;
+    const int cur = c->which;
+    int mn = INT32_MAX;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < c->n_tot;
+         i += (long long)gridDim.x * blockDim.x)
+        mn = min(mn, (int)P.oE[cur][i]);
+    mn = __ockl_wfred_min_i32(mn);
+    if ((threadIdx.x & 63) == 0 && mn != INT32_MAX) atomicMin(&c->batch_minE, mn);
 }
 
 uint64_t next_pow2(uint64_t x) {
@@ -738,11 +995,11 @@ uint64_t next_pow2(uint64_t x) {
     return p;
 }
 
-constexpr int kCheck = 16;   // rounds between host looks at the control block
+constexpr int kCheck = 8;    // rounds between host looks at the control block
 
 struct S2Layout {
     uint64_t cap_ht;
-    long long cap_o;
+    long long cap_o, cap_pend;
     size_t total;
 };
 
@@ -751,7 +1008,8 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     const int W = words_of(c.L);
     const long long base = (n_cand > c.pq_capacity ? n_cand : c.pq_capacity);
     const long long BL = (long long)c.batch * c.L;
-    lo.cap_o = base + 2 * BL + 1024;
+    lo.cap_o = base + BL + 1024;
+    lo.cap_pend = (BL > n_cand ? BL : n_cand) + 1024;
     // live slots never exceed n_cand + X + Q + BL; the table is rebuilt when half
     // of it is claimed, with kCheck rounds of claims as headroom.
     const long long live = n_cand + c.max_expansions + c.pq_capacity + BL;
@@ -763,15 +1021,16 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
         t += align_up(sizeof(int32_t) * lo.cap_ht, 256);
         t += align_up(sizeof(uint32_t) * lo.cap_ht * W, 256);
     }
-    t += align_up(sizeof(uint32_t) * lo.cap_ht, 256);     // remap
+    t += align_up(sizeof(uint32_t) * lo.cap_ht, 256);                  // remap
     t += align_up(sizeof(Ctl), 256);
-    t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);   // oE
-    t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);   // oS
-    t += align_up(sizeof(uint32_t) * lo.cap_o, 256);      // flag
-    t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);   // cand
-    t += align_up(sizeof(int32_t) * c.batch, 256);        // piv
-    t += align_up(sizeof(uint32_t) * kSelBins, 256);      // ghist
-    t += align_up(sizeof(uint32_t) * 32, 256);            // best sequence
+    t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // oE
+    t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // oS
+    t += align_up(sizeof(uint32_t) * lo.cap_o, 256);                   // flag
+    t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // cand
+    t += align_up(sizeof(int32_t) * c.batch, 256);                     // piv
+    t += align_up(sizeof(uint32_t) * kSelBins * kSelBlocks, 256);      // histograms
+    t += align_up(sizeof(uint32_t) * 32, 256);                         // best sequence
+    t += 2 * align_up(sizeof(Pend) * lo.cap_pend, 256);                // pending, collisions
     lo.total = t + 4096;
     return lo;
 }
@@ -782,7 +1041,7 @@ size_t step2_workspace_bytes(const labs_step2_cfg& c, long long n_cand) {
     return s2_layout(c, n_cand).total;
 }
 
-// The host loop.  `timer_begin/end` bracket every expansion launch.
+// The host loop.  `tb`/`te` bracket every expansion launch (launch timing).
 labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_t* cand_seqs,
                       const labs_step2_out& out, void* ws, size_t ws_bytes, hipStream_t st,
                       labs_status (*tb)(void*, hipStream_t), labs_status (*te)(void*, hipStream_t),
@@ -801,14 +1060,15 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.X = cfg.max_expansions;
     P.T_u = cfg.T_u;
     P.cap_o = lo.cap_o;
+    P.cap_pend = lo.cap_pend;
     Table tabs[2];
-    for (int tb = 0; tb < 2; ++tb) {
-        tabs[tb].hkey = cv.take<unsigned long long>(lo.cap_ht);
-        tabs[tb].state = cv.take<uint32_t>(lo.cap_ht);
-        tabs[tb].E = cv.take<int32_t>(lo.cap_ht);
-        tabs[tb].seq = cv.take<uint32_t>(lo.cap_ht * P.W);
-        tabs[tb].mask = lo.cap_ht - 1;
-        tabs[tb].W = P.W;
+    for (int tb2 = 0; tb2 < 2; ++tb2) {
+        tabs[tb2].hkey = cv.take<unsigned long long>(lo.cap_ht);
+        tabs[tb2].state = cv.take<uint32_t>(lo.cap_ht);
+        tabs[tb2].E = cv.take<int32_t>(lo.cap_ht);
+        tabs[tb2].seq = cv.take<uint32_t>(lo.cap_ht * P.W);
+        tabs[tb2].mask = lo.cap_ht - 1;
+        tabs[tb2].W = P.W;
     }
     uint32_t* remap = cv.take<uint32_t>(lo.cap_ht);
     int tcur = 0;
@@ -819,61 +1079,58 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.flag = cv.take<uint32_t>(lo.cap_o);
     for (int b = 0; b < 2; ++b) P.cand[b] = cv.take<int32_t>(lo.cap_o);
     P.piv = cv.take<int32_t>(cfg.batch);
-    P.ghist = cv.take<uint32_t>(kSelBins);
+    P.ghist = cv.take<uint32_t>((size_t)kSelBins * kSelBlocks);
     P.best_seq = cv.take<uint32_t>(32);
+    P.pend = cv.take<Pend>(lo.cap_pend);
+    P.slow = cv.take<Pend>(lo.cap_pend);
+    P.cands = cand_seqs;
     if (!cv.ok()) return invalid("workspace layout overflow");
 
     LABS_HIP(hipMemsetAsync(P.H.hkey, 0, sizeof(unsigned long long) * lo.cap_ht, st));
     LABS_HIP(hipMemsetAsync(P.H.state, 0, sizeof(uint32_t) * lo.cap_ht, st));
     LABS_HIP(hipMemsetAsync(P.best_seq, 0, sizeof(uint32_t) * 32, st));
-    LABS_HIP(hipMemsetAsync(P.ghist, 0, sizeof(uint32_t) * kSelBins, st));
-    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, st, P.ctl);
-    hipLaunchKernelGGL(k_seed, dim3((unsigned)n_cand), dim3(64), 0, st, P, cand_seqs, n_cand);
-    LABS_LAUNCHED("step2 seed");
-
-    const unsigned gsel = grid_for(lo.cap_o, 256);
-    auto select = [&]() -> labs_status {
-        hipLaunchKernelGGL(k_sel_reset, dim3(1), dim3(1), 0, st, P);
-        hipLaunchKernelGGL(k_sel_minmax, dim3(gsel), dim3(256), 0, st, P);
-        hipLaunchKernelGGL(k_sel_setup, dim3(1), dim3(1), 0, st, P);
+    const dim3 gS(kGridBlocks), tS(kSelThreads);
+    auto select = [&]() {
+        hipLaunchKernelGGL(k_sel_minmax, dim3(kSelBlocks), tS, 0, st, P);
         for (int lv = 0; lv < 3; ++lv) {
-            hipLaunchKernelGGL(k_sel_hist, dim3(gsel), dim3(256), 0, st, P);
-            hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(1024), 0, st, P);
+            hipLaunchKernelGGL(k_sel_hist, dim3(kSelBlocks), tS, 0, st, P, lv);
+            hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(1024), 0, st, P, lv);
         }
-        hipLaunchKernelGGL(k_sel_classify, dim3(gsel), dim3(256), 0, st, P);
+        hipLaunchKernelGGL(k_sel_classify, gS, tS, 0, st, P);
         hipLaunchKernelGGL(k_sel_keys, dim3(1), dim3(1024), 0, st, P);
-        LABS_LAUNCHED("step2 select");
-        return LABS_OK;
     };
-    labs_status s;
-    // initial cut to Q and the initial best
-    hipLaunchKernelGGL(k_evict_setup, dim3(1), dim3(1), 0, st, P);
-    if ((s = select()) != LABS_OK) return s;
-    hipLaunchKernelGGL(k_evict, dim3(gsel), dim3(256), 0, st, P);
-    hipLaunchKernelGGL(k_evict_fin, dim3(1), dim3(1), 0, st, P);
-    hipLaunchKernelGGL(k_initial_best_setup, dim3(1), dim3(1), 0, st, P);
-    hipLaunchKernelGGL(k_sel_reset, dim3(1), dim3(1), 0, st, P);
-    hipLaunchKernelGGL(k_sel_minmax, dim3(gsel), dim3(256), 0, st, P);
-    hipLaunchKernelGGL(k_best, dim3(1), dim3(1024), 0, st, P, 1);
-    LABS_LAUNCHED("step2 init");
 
+    // seeding: insert the candidates (exact dedupe), cut to Q, best = minimum
+    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, st, P.ctl);
+    hipLaunchKernelGGL(k_seed, dim3((unsigned)n_cand), dim3(64), 0, st, P, n_cand);
+    hipLaunchKernelGGL(k_resolve, gS, tS, 0, st, P);
+    hipLaunchKernelGGL(k_slow, dim3(1), dim3(1), 0, st, P);
+    hipLaunchKernelGGL(k_seed_fin, dim3(1), dim3(1), 0, st, P);
+    select();
+    hipLaunchKernelGGL(k_keep, gS, tS, 0, st, P);
+    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, P, 0);
+    hipLaunchKernelGGL(k_seed_best_setup, dim3(1), dim3(1), 0, st, P.ctl);
+    hipLaunchKernelGGL(k_min_live, gS, tS, 0, st, P);
+    hipLaunchKernelGGL(k_best, dim3(1), dim3(1024), 0, st, P, 1);
+    LABS_LAUNCHED("step2 seeding");
+
+    labs_status s;
+    unsigned eth = 64;
+    const expand_kernel_t ek = pick_expand(cfg.L, &eth);
     for (long long r = 0;; ++r) {
         hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, P);
-        hipLaunchKernelGGL(k_compact, dim3(gsel), dim3(256), 0, st, P);
-        hipLaunchKernelGGL(k_compact_fin, dim3(1), dim3(1), 0, st, P);
-        if ((s = select()) != LABS_OK) return s;
-        hipLaunchKernelGGL(k_pop, dim3(gsel), dim3(256), 0, st, P);
-        hipLaunchKernelGGL(k_pop_fin, dim3(1), dim3(1), 0, st, P);
+        select();
+        hipLaunchKernelGGL(k_pop, gS, tS, 0, st, P);
         if (tb && (s = tb(tctx, st)) != LABS_OK) return s;
-        hipLaunchKernelGGL(k_expand, dim3((unsigned)cfg.batch), dim3(64), 0, st, P);
+        hipLaunchKernelGGL(ek, dim3((unsigned)cfg.batch), dim3(eth), 0, st, P);
         if (te && (s = te(tctx, st)) != LABS_OK) return s;
+        hipLaunchKernelGGL(k_resolve, gS, tS, 0, st, P);
+        hipLaunchKernelGGL(k_slow, dim3(1), dim3(1), 0, st, P);
         hipLaunchKernelGGL(k_expand_fin, dim3(1), dim3(1), 0, st, P);
         hipLaunchKernelGGL(k_best, dim3(1), dim3(1024), 0, st, P, 0);
-        hipLaunchKernelGGL(k_evict_setup, dim3(1), dim3(1), 0, st, P);
-        if ((s = select()) != LABS_OK) return s;
-        hipLaunchKernelGGL(k_evict, dim3(gsel), dim3(256), 0, st, P);
-        hipLaunchKernelGGL(k_evict_fin, dim3(1), dim3(1), 0, st, P);
-        hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, P);
+        select();
+        hipLaunchKernelGGL(k_keep, gS, tS, 0, st, P);
+        hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, P, 1);
         LABS_LAUNCHED("step2 round");
         if ((r + 1) % kCheck == 0) {
             int32_t flags[2];
@@ -890,9 +1147,8 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
                 Table& dst = tabs[1 - tcur];
                 LABS_HIP(hipMemsetAsync(dst.hkey, 0, sizeof(unsigned long long) * lo.cap_ht, st));
                 LABS_HIP(hipMemsetAsync(dst.state, 0, sizeof(uint32_t) * lo.cap_ht, st));
-                hipLaunchKernelGGL(k_rebuild, dim3(grid_for((long long)lo.cap_ht, 256, 8192)), dim3(256), 0, st,
-                                   tabs[tcur], dst, remap, P.ctl);
-                hipLaunchKernelGGL(k_remap, dim3(gsel), dim3(256), 0, st, P, remap);
+                hipLaunchKernelGGL(k_rebuild, dim3(8192), dim3(256), 0, st, tabs[tcur], dst, remap, P.ctl);
+                hipLaunchKernelGGL(k_remap, gS, tS, 0, st, P, remap);
                 hipLaunchKernelGGL(k_rebuild_fin, dim3(1), dim3(1), 0, st, P.ctl, remap);
                 LABS_LAUNCHED("step2 rebuild");
                 tcur = 1 - tcur;
@@ -900,9 +1156,8 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
             }
         }
     }
-    hipLaunchKernelGGL(k_prepare_outputs, dim3(1), dim3(1), 0, st, P.ctl);
-    hipLaunchKernelGGL(k_outputs, dim3(gsel), dim3(256), 0, st, P, out.best_seq, out.best_E, out.stats,
-                       out.open_seqs, out.open_E, (long long)out.open_capacity);
+    hipLaunchKernelGGL(k_outputs, gS, tS, 0, st, P, out.best_seq, out.best_E, out.stats, out.open_seqs,
+                       out.open_E, (long long)out.open_capacity);
     LABS_LAUNCHED("step2 outputs");
     LABS_HIP(hipStreamSynchronize(st));
     return LABS_OK;

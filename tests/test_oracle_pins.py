@@ -386,3 +386,19 @@ def test_step2_capacity_eviction(orc):
     r = orc.step2(L, list(c), 4, 50, 200, 1 << 40)
     assert r["evictions"] > 0
     assert len(r["open_keys"]) <= 50
+
+
+def test_zobrist_keys(orc):
+    """Zobrist keys: XOR of SplitMix64 outputs over the +1 positions (low bit
+    forced to 1), so one flip changes the key by exactly that position's output
+    (Alg. 2's HASH_FLIP)."""
+    L = 37
+    z = orc.zobrist_table(L)
+    assert z == orc.splitmix64_stream(orc.ZOBRIST_STATE, L)
+    s = li.random_pm1(3, 1, L)[0]
+    k = orc.seq_key(s)
+    h = orc.zobrist(k, L)
+    assert h & 1
+    for i in range(L):
+        assert orc.zobrist(k ^ (1 << (L - 1 - i)), L) == (h ^ z[i]) | 1
+    assert orc.zobrist(0, L) == 1
