@@ -34,6 +34,7 @@
  *     calling thread.  No C++ exception crosses this interface.
  *   Limits: odd L for skew operations; 1 <= L <= 1023 for energies and deltas;
  *     first-step walks need 5 <= L <= 639 (at most 10 words of even lags);
+ *     second-step searches 2 <= L <= 1023;
  *     |C_k| <= L-1 and E < 2^31 for every L accepted.
  */
 #ifndef LABS_H
@@ -160,13 +161,40 @@ typedef struct {
 labs_status labs_walk_step1_workspace(const labs_step1_cfg* cfg, int32_t n_cfg,
                                       int64_t pool_capacity, size_t* bytes);
 
-/* Run the first step.  cfg, pools and outs are HOST arrays of n_cfg structs
- * (n_cfg = 1 in this build); pools may be NULL when every cfg has e_max < 0.
- * prop must be NULL (plain walker).  When a pool is used the call synchronises
- * `stream` between walk segments and returns after the pool is final. */
+/* Run the first step.  cfg, pools and outs are HOST arrays of n_cfg structs;
+ * prop must be NULL (plain walker).
+ *   n_cfg = 1: one configuration in segmented launches of one wavefront per
+ *     walker; pools may be NULL when e_max < 0.  When a pool is used the call
+ *     synchronises `stream` between walk segments and returns after the pool is
+ *     final.
+ *   n_cfg > 1: a batch of configurations of any (odd) lengths in one
+ *     hipGraph-captured launch: per shape class of the walker kernel, a
+ *     persistent kernel drains a queue of (configuration, walker) items, the
+ *     most expensive first.  Every cfg must have e_max < 0 and flags = 0, and
+ *     pools must be NULL.  The graph is cached per (cfg, outs, workspace) and
+ *     replayed on identical calls; the call returns without synchronising.
+ *   Per-walker results are identical in both forms. */
 labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void* prop,
                             labs_pool* pools, labs_step1_out* outs, void* ws, size_t ws_bytes,
                             void* stream);
+
+/* ----------------------------------------------------------------------------
+ * Autotuner of the walker's tiles.  A shape class is (NW, R): NW = ceil(k/32)
+ * words of even lags and R = ceil((k+1-p)/64) free positions per lane.  Its tile
+ * is RB, the slots a lane scans per pass (R, or ceil(R/2) to free registers for
+ * occupancy), and the resident waves per SIMD requested by persistent launches
+ * (1, 2, 4 or 8).  labs_autotune_step1 times every candidate tile on the largest
+ * length of each class among Ls (host array of n_L odd lengths) with `walkers`
+ * walkers x `steps` steps, and keeps the fastest in a process-wide table used by
+ * every later walk.  It allocates and frees its own scratch and synchronises
+ * `stream`.  The table can be written to / read from a JSON file; labs_autotune_get
+ * reports the tile used for (L, p) (host outputs).
+ */
+labs_status labs_autotune_step1(const int32_t* Ls, int32_t n_L, int32_t p, int32_t walkers,
+                                int32_t steps, void* stream);
+labs_status labs_autotune_save(const char* path);
+labs_status labs_autotune_load(const char* path);
+labs_status labs_autotune_get(int32_t L, int32_t p, int32_t* rb, int32_t* waves_per_simd);
 
 /* ----------------------------------------------------------------------------
  * labs_pool_topk -- the k smallest distinct sequences of a pool in key order.
@@ -247,7 +275,8 @@ labs_status labs_refine_step2(const labs_step2_cfg* cfg, int64_t n_cand, const u
  * is bracketed by HIP events on the stream it runs on, and the entry point
  * that launched it synchronises that stream before returning and adds the
  * elapsed times to a process-wide table.  Timed kernel names: "walk" (the
- * first-step scan/apply kernel), "expand" (the second-step expansion kernel).  total_ms and launches are HOST outputs.
+ * first-step scan/apply kernel), "walk_batched" (a whole batched launch),
+ * "expand" (the second-step expansion kernel).  total_ms and launches are HOST outputs.
  */
 labs_status labs_timing_enable(int32_t on);
 labs_status labs_timing_reset(void);

@@ -251,11 +251,27 @@ labs_status labs_flip_deltas(int32_t L, int32_t p, int32_t skew, int64_t n, cons
     return launch_flip_deltas(L, p, skew, n, seqs, dE, S(stream));
 }
 
+static labs_status check_batch(const labs_step1_cfg* cfg, int32_t n_cfg) {
+    if (n_cfg < 2 || n_cfg > 4096) return invalid("a batch holds 2..4096 configurations");
+    for (int i = 0; i < n_cfg; ++i) {
+        labs_status s = check_step1_cfg(cfg[i]);
+        if (s != LABS_OK) return s;
+        if (cfg[i].e_max >= 0 || cfg[i].flags) return invalid("batched walks take no pool (cfg %d)", i);
+    }
+    return LABS_OK;
+}
+
 labs_status labs_walk_step1_workspace(const labs_step1_cfg* cfg, int32_t n_cfg, int64_t pool_capacity,
                                       size_t* bytes) {
     clear_error();
     if (!cfg || !bytes) return invalid("cfg and bytes must not be NULL");
-    if (n_cfg != 1) return invalid("this build runs one configuration per call (n_cfg = 1)");
+    if (n_cfg > 1) {
+        labs_status sb = check_batch(cfg, n_cfg);
+        if (sb != LABS_OK) return sb;
+        *bytes = batch_workspace_bytes(cfg, n_cfg);
+        return LABS_OK;
+    }
+    if (n_cfg != 1) return invalid("n_cfg must be >= 1");
     labs_status s = check_step1_cfg(cfg[0]);
     if (s != LABS_OK) return s;
     const bool pool = uses_pool(cfg[0]);
@@ -270,8 +286,21 @@ labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void
                             void* stream) {
     clear_error();
     if (!cfg || !outs) return invalid("cfg and outs must not be NULL");
-    if (n_cfg != 1) return invalid("this build runs one configuration per call (n_cfg = 1)");
     if (prop) return invalid("prop must be NULL for the plain walker");
+    if (n_cfg > 1) {
+        labs_status sb = check_batch(cfg, n_cfg);
+        if (sb != LABS_OK) return sb;
+        if (pools) return invalid("batched walks take no pool");
+        for (int i = 0; i < n_cfg; ++i)
+            if (!outs[i].final_seqs || !outs[i].final_E) return invalid("final_seqs and final_E must not be NULL");
+        if (!ws) return invalid("workspace must not be NULL");
+        LaunchTimer tb("walk_batched");
+        if ((sb = tb.begin(S(stream))) != LABS_OK) return sb;
+        if ((sb = batch_walk(cfg, n_cfg, outs, ws, ws_bytes, S(stream), nullptr, true)) != LABS_OK) return sb;
+        if ((sb = tb.end(S(stream))) != LABS_OK) return sb;
+        return tb.flush();
+    }
+    if (n_cfg != 1) return invalid("n_cfg must be >= 1");
     const labs_step1_cfg c = cfg[0];
     labs_status s = check_step1_cfg(c);
     if (s != LABS_OK) return s;
@@ -460,6 +489,51 @@ labs_status labs_refine_step2(const labs_step2_cfg* cfg, int64_t n_cand, const u
     s = step2_run(*cfg, n_cand, cand_seqs, *out, ws, ws_bytes, S(stream), timer_begin_cb, timer_end_cb, &te);
     if (s != LABS_OK) return s;
     return te.flush();
+}
+
+labs_status labs_autotune_step1(const int32_t* Ls, int32_t n_L, int32_t p, int32_t walkers, int32_t steps,
+                                void* stream) {
+    clear_error();
+    if (!Ls || n_L < 1) return invalid("Ls must hold at least one length");
+    for (int i = 0; i < n_L; ++i) {
+        labs_step1_cfg c{};
+        c.L = Ls[i];
+        c.p = p;
+        c.steps = steps;
+        c.n_walkers = walkers;
+        labs_status s = check_step1_cfg(c);
+        if (s != LABS_OK) return s;
+    }
+    if (walkers < 1 || steps < 1) return invalid("walkers and steps must be >= 1");
+    return autotune_step1(Ls, n_L, p, walkers, steps, S(stream));
+}
+
+labs_status labs_autotune_save(const char* path) {
+    clear_error();
+    if (!path) return invalid("path must not be NULL");
+    return autotune_save(path);
+}
+
+labs_status labs_autotune_load(const char* path) {
+    clear_error();
+    if (!path) return invalid("path must not be NULL");
+    return autotune_load(path);
+}
+
+labs_status labs_autotune_get(int32_t L, int32_t p, int32_t* rb, int32_t* waves_per_simd) {
+    clear_error();
+    if (!rb || !waves_per_simd) return invalid("outputs must not be NULL");
+    labs_step1_cfg c{};
+    c.L = L;
+    c.p = p;
+    c.n_walkers = 1;
+    labs_status s = check_step1_cfg(c);
+    if (s != LABS_OK) return s;
+    int a = 0, b = 0;
+    autotune_get(L, p, &a, &b);
+    *rb = a;
+    *waves_per_simd = b;
+    return LABS_OK;
 }
 
 labs_status labs_timing_enable(int32_t on) {

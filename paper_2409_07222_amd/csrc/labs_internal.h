@@ -124,6 +124,16 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
                       labs_status (*tb)(void*, hipStream_t), labs_status (*te)(void*, hipStream_t),
                       void* tctx);
 labs_status launch_walker_init(const WalkArgs& A, hipStream_t st);
+labs_status launch_walker_init_items(const WalkArgs* args, const int2* items, int n_items, hipStream_t st);
+// Autotuned register tile (slots per pass) for the walker of (L, p); R when untuned.
+int walk_tile_rb(int L, int p, int R);
+size_t batch_workspace_bytes(const labs_step1_cfg* c, int n);
+labs_status batch_walk(const labs_step1_cfg* c, int n, const labs_step1_out* outs, void* ws, size_t wsb,
+                       hipStream_t st, const void* tile_override, bool use_graph);
+labs_status autotune_step1(const int32_t* Ls, int n_L, int p, int walkers, int steps, hipStream_t st);
+labs_status autotune_save(const char* path);
+labs_status autotune_load(const char* path);
+labs_status autotune_get(int L, int p, int* rb, int* waves);
 labs_status launch_walk(const WalkArgs& A, hipStream_t st);
 labs_status launch_offer_best(const WalkArgs& A, hipStream_t st);
 labs_status launch_walk_outputs(const WalkArgs& A, const labs_step1_out& o, hipStream_t st);

@@ -1,0 +1,386 @@
+// Templates of the first-step walker (shared by the instantiation units).
+// See walk.hip for the method and the notation.
+#pragma once
+#include "labs_internal.h"
+
+#include <climits>
+
+namespace labsdev {
+namespace walkimpl {
+
+template <int NW>
+struct Lds {
+    static constexpr int K = 32 * NW;          // max even-lag count
+    static constexpr int PADL = 2 * K;         // sv index of position x is PADL + x
+    static constexpr int SV = 5 * K + 8;
+    static constexpr int VW = 2 * NW + 4;
+    int8_t sv[SV];
+    uint32_t V[2][VW];
+    uint32_t VR[2][VW];
+    int32_t Cev[K + 1];
+    int32_t PC[K + 1];
+    uint32_t pk[32];
+    uint32_t pkbest[32];
+};
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Fill sv, V, VR from the packed sequence held in S.pk.
+template <int NW>
+__device__ inline void build_from_packed(Lds<NW>& S, int L, int k, int lane) {
+    constexpr int PADL = Lds<NW>::PADL;
+    for (int i = lane; i < Lds<NW>::SV; i += 64) S.sv[i] = 0;
+    for (int i = lane; i < 2 * Lds<NW>::VW; i += 64) {
+        (&S.V[0][0])[i] = 0;
+        (&S.VR[0][0])[i] = 0;
+    }
+    __syncthreads();
+    for (int x = 1 + lane; x <= L; x += 64) S.sv[PADL + x] = packed_bit(S.pk, x) ? 1 : -1;
+    __syncthreads();
+    const int NV = (k + 1 + 31) >> 5;  // words holding j = 0..k
+    const int N = 32 * NV;
+    for (int pi = 0; pi < 2; ++pi) {
+        for (int base = 0; base < N; base += 64) {
+            int j = base + lane;
+            int x = 2 * j + 2 - pi;
+            bool bit = (x >= 1 && x <= L) && S.sv[PADL + x] > 0;
+            uint64_t m = __ballot(bit);
+            // reversed: VR bit i = V bit N-1-i
+            int jr = N - 1 - j;
+            int xr = 2 * jr + 2 - pi;
+            bool bitr = (jr >= 0 && xr >= 1 && xr <= L) && S.sv[PADL + xr] > 0;
+            uint64_t mr = __ballot(bitr);
+            if (lane == 0) {
+                S.V[pi][base >> 5] = (uint32_t)m;
+                if ((base >> 5) + 1 < Lds<NW>::VW) S.V[pi][(base >> 5) + 1] = (uint32_t)(m >> 32);
+                S.VR[pi][base >> 5] = (uint32_t)mr;
+                if ((base >> 5) + 1 < Lds<NW>::VW) S.VR[pi][(base >> 5) + 1] = (uint32_t)(mr >> 32);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// C_{2m} for this lane's lags m = 64q + lane + 1 (0 beyond K), from sv.
+template <int NW>
+__device__ inline void compute_cev(const Lds<NW>& S, int L, int K, int lane, int32_t* C) {
+    constexpr int NQ = (NW + 1) / 2;
+    constexpr int PADL = Lds<NW>::PADL;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        int m = 64 * q + lane + 1;
+        int c = 0;
+        if (m <= K) {
+            int d = 2 * m;
+            for (int i = 1; i <= L - d; ++i) c += (int)S.sv[PADL + i] * (int)S.sv[PADL + i + d];
+        }
+        C[q] = c;
+    }
+}
+
+template <int NW>
+__device__ inline void store_tables(Lds<NW>& S, int K, int lane, const int32_t* C) {
+    constexpr int NQ = (NW + 1) / 2;
+    int carry = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        int m = 64 * q + lane + 1;
+        int v = (m <= K) ? C[q] : 0;
+        int s = wave_incl_scan(v, lane);
+        if (m <= K) {
+            S.Cev[m] = C[q];
+            S.PC[m] = carry + s;
+        }
+        carry += __shfl(s, 63, 64);
+    }
+    if (lane == 0) {
+        S.Cev[0] = 0;
+        S.PC[0] = 0;
+    }
+}
+
+template <int NW, int R>
+__device__ __forceinline__ void build_windows(const Lds<NW>& S, int p, int k, int lane,
+                                              uint32_t (&F)[R][NW],
+                                              uint32_t (&B)[R][(NW + 1) / 2]) {
+    constexpr int NQ = (NW + 1) / 2;
+    const int NV = (k + 1 + 31) >> 5;
+    const int N = 32 * NV;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int a = p + 1 + lane + 64 * r;
+        if (a > k + 1) a = k + 1;
+        const int pi = a & 1;
+        const int ja = (a - 1) >> 1;
+        const int sf = ja + 1, qf = sf >> 5, hf = sf & 31;
+        const int sb = N - ja, qb = sb >> 5, hb = sb & 31;
+        const uint32_t* Vp = S.V[pi];
+        const uint32_t* VRp = S.VR[pi];
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+            F[r][w] = __builtin_amdgcn_alignbit(Vp[qf + w + 1], Vp[qf + w], hf);
+#pragma unroll
+        for (int w = 0; w < NQ; ++w)
+            B[r][w] = __builtin_amdgcn_alignbit(VRp[qb + w + 1], VRp[qb + w], hb);
+    }
+}
+
+// One walker (walker index j of configuration A) for steps t0+1..t1.  Slots are
+// scanned in groups of RB (R = RB: one pass with every window resident; smaller
+// RB: fewer window registers, the bit planes re-ballotted once per group).
+template <int NW, int R, int RB>
+__device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>& S) {
+    constexpr int NQ = (NW + 1) / 2;
+    constexpr int PADL = Lds<NW>::PADL;
+    constexpr int NG = (R + RB - 1) / RB;
+    const int lane = threadIdx.x & 63;
+    const int L = A.L, k = A.k, p = A.p, K = A.k, W = A.W, nf = A.nf;
+    const int t0 = A.t0, t1 = A.t1;
+
+    __syncthreads();
+    int halted = A.halted[j];
+    if (halted) {
+        if (A.traj)
+            for (int t = t0 + 1 + lane; t <= t1; t += 64)
+                A.traj[j * A.steps_total + (t - 1)] = -1;
+        return;
+    }
+    if (lane < W) {
+        S.pk[lane] = A.seq[j * W + lane];
+        S.pkbest[lane] = A.bestSeq[j * W + lane];
+    }
+    __syncthreads();
+    build_from_packed<NW>(S, L, k, lane);
+    int32_t C[NQ];
+    compute_cev<NW>(S, L, K, lane, C);
+    store_tables<NW>(S, K, lane, C);
+    int32_t tabu[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int i = lane + 64 * r;
+        tabu[r] = (i < nf) ? A.tabu[j * nf + i] : INT_MAX;
+    }
+    int E = A.E[j];
+    int bestE = A.bestE[j];
+    int bestT = A.bestT[j];
+    const int tenure = A.tenure[j];
+    const bool sieve = A.e_max >= 0;
+    int thr = A.e_max;
+    if (sieve && A.thr) thr = min(thr, *A.thr);
+    const int64_t wid = A.walker_begin + j;
+    __syncthreads();
+
+    // masks of lags m <= Mb for the backward-overlap count
+    uint32_t QM[R][NQ];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int a = p + 1 + lane + 64 * r;
+        if (a > k + 1) a = k + 1;
+        const int Mb = (a - 1) >> 1;
+#pragma unroll
+        for (int w = 0; w < NQ; ++w) {
+            int c = Mb - 32 * w;
+            QM[r][w] = c >= 32 ? 0xffffffffu : (c <= 0 ? 0u : ((1u << c) - 1u));
+        }
+    }
+
+    for (int t = t0 + 1; t <= t1; ++t) {
+        // ---- number of bit planes for the current C table
+        uint32_t orv = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) orv |= (uint32_t)(C[q] ^ (C[q] >> 31));
+        orv = __ockl_wfred_or_u32(orv);
+        const int nb = (32 - __clz((int)orv)) + 1;
+
+        // ---- H = H_f + H_b, bit-sliced, then the exact dE, RB slots at a time
+        int dlt[R];
+        bool adm[R];
+        int dmin = INT_MAX;
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+            uint32_t F[RB][NW], B[RB][NQ];
+            build_windows<NW, RB>(S, p + 64 * RB * gi, k, lane, F, B);
+            int32_t H[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) H[r] = 0;
+            for (int jp = 0; jp < nb; ++jp) {
+                uint32_t acc[RB];
+#pragma unroll
+                for (int r = 0; r < RB; ++r) acc[r] = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const uint64_t bal = __ballot((C[q] >> jp) & 1);
+                    const uint32_t lo = (uint32_t)bal, hi = (uint32_t)(bal >> 32);
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) {
+                        acc[r] += __popc(lo & F[r][2 * q]);
+                        if (2 * q + 1 < NW) acc[r] += __popc(hi & F[r][2 * q + 1]);
+                        if (2 * q < NQ) acc[r] += __popc(lo & B[r][2 * q]);
+                        if (2 * q + 1 < NQ) acc[r] += __popc(hi & B[r][2 * q + 1]);
+                    }
+                }
+                const int wgt = (jp == nb - 1) ? -(1 << jp) : (1 << jp);
+#pragma unroll
+                for (int r = 0; r < RB; ++r) H[r] += wgt * (int)acc[r];
+            }
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+                const int r = gi * RB + rr;
+                if (r >= R) break;
+                const int a0 = p + 1 + lane + 64 * r;
+                const bool valid = a0 <= k + 1;
+                const int a = valid ? a0 : k + 1;
+                const int Mf = (L - a) >> 1, Mb = (a - 1) >> 1;
+                const int sa = S.sv[PADL + a];
+                int d;
+                if (a == k + 1) {
+                    d = -8 * sa * (H[rr] - S.PC[Mb]) + 16 * Mb;
+                } else {
+                    const int mp = k + 1 - a;
+                    const int sbv = S.sv[PADL + L + 1 - a];
+                    int X = 0;
+#pragma unroll
+                    for (int w = 0; w < NQ; ++w) X += __popc((F[rr][w] ^ B[rr][w]) & QM[r][w]);
+                    const int G = 2 * H[rr] - S.PC[Mf] - S.PC[Mb] - S.Cev[mp] * sbv;
+                    const int corr = (mp <= Mb) ? 2 * sbv * S.sv[PADL + a - 2 * mp] : 0;
+                    const int Q = Mf - 1 + 3 * Mb - 4 * X - corr;
+                    d = -8 * sa * G + 16 * Q;
+                }
+                dlt[r] = d;
+                adm[r] = valid && tabu[r] < t;
+                if (adm[r]) dmin = min(dmin, d);
+            }
+        }
+        const int g = __ockl_wfred_min_i32(dmin);
+        if (g == INT_MAX) {
+            halted = t;
+            break;
+        }
+        int astar = -1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t m = __ballot(adm[r] && dlt[r] == g);
+            if (astar < 0 && m) astar = p + 1 + 64 * r + (__ffsll((unsigned long long)m) - 1);
+        }
+        // ---- apply: C update from the old sequence
+        const int as = astar, bs = L + 1 - astar;
+        const bool cen = (as == k + 1);
+        const int s_as = S.sv[PADL + as];
+        const int s_bs = S.sv[PADL + bs];
+        const int mps = k + 1 - as;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int m = 64 * q + lane + 1;
+            if (m <= K) {
+                int u;
+                if (cen) u = S.sv[PADL + as - 2 * m];
+                else u = S.sv[PADL + as + 2 * m] + S.sv[PADL + as - 2 * m] - (m == mps ? s_bs : 0);
+                C[q] += -4 * s_as * u;
+            }
+        }
+        E += g;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (p + 1 + lane + 64 * r == as) tabu[r] = t + tenure;
+        __syncthreads();
+        store_tables<NW>(S, K, lane, C);
+        if (lane == 0 || (lane == 1 && !cen)) {
+            const int x = lane == 0 ? as : bs;
+            S.sv[PADL + x] = (int8_t)(-S.sv[PADL + x]);
+            const int pi = x & 1, jj = (x - 1) >> 1;
+            const int NV = (k + 1 + 31) >> 5;
+            const int ir = 32 * NV - 1 - jj;
+            atomicXor(&S.V[pi][jj >> 5], 1u << (jj & 31));
+            atomicXor(&S.VR[pi][ir >> 5], 1u << (ir & 31));
+            atomicXor(&S.pk[(x - 1) >> 5], 1u << (31 - ((x - 1) & 31)));
+        }
+        __syncthreads();
+        if (E < bestE) {
+            bestE = E;
+            bestT = t;
+            if (lane < W) S.pkbest[lane] = S.pk[lane];
+        }
+        if (A.traj && lane == 0) A.traj[j * A.steps_total + (t - 1)] = E;
+        if (sieve && E <= thr) {
+            uint32_t slot = 0;
+            if (lane == 0) slot = atomicAdd(A.st_count, 1u);
+            slot = __shfl(slot, 0, 64);
+            if (slot < A.st_cap && lane < W + 3) {
+                uint32_t v;
+                if (lane == 0) v = (uint32_t)E;
+                else if (lane <= W) v = S.pk[lane - 1];
+                else if (lane == W + 1) v = (uint32_t)wid;
+                else v = (uint32_t)t;
+                A.rec[(int64_t)lane * A.rec_stride + slot] = v;
+            }
+        }
+    }
+    __syncthreads();
+    if (halted && A.traj)
+        for (int t = halted + lane; t <= t1; t += 64) A.traj[j * A.steps_total + (t - 1)] = -1;
+    if (lane < W) {
+        A.seq[j * W + lane] = S.pk[lane];
+        A.bestSeq[j * W + lane] = S.pkbest[lane];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int i = lane + 64 * r;
+        if (i < nf) A.tabu[j * nf + i] = tabu[r];
+    }
+    if (lane == 0) {
+        A.E[j] = E;
+        A.bestE[j] = bestE;
+        A.bestT[j] = bestT;
+        A.halted[j] = halted;
+    }
+}
+
+
+template <int NW, int R, int RB>
+__global__ __launch_bounds__(64) void k_walk(WalkArgs A) {
+    __shared__ Lds<NW> S;
+    walk_body<NW, R, RB>(A, blockIdx.x, S);
+}
+
+// Persistent form: each wavefront takes (configuration, walker) items from a
+// queue until it is empty, so every wavefront exits.
+template <int NW, int R, int RB>
+__global__ __launch_bounds__(64) void k_walk_persistent(const WalkArgs* args, const int2* items,
+                                                        int n_items, unsigned* head) {
+    __shared__ Lds<NW> S;
+    for (;;) {
+        unsigned it = 0;
+        if (threadIdx.x == 0) it = atomicAdd(head, 1u);
+        it = __shfl(it, 0, 64);
+        if (it >= (unsigned)n_items) break;
+        const int2 w = items[it];
+        const WalkArgs A = args[w.x];
+        walk_body<NW, R, RB>(A, (int64_t)w.y, S);
+    }
+}
+
+typedef void (*walk_kernel_t)(WalkArgs);
+typedef void (*walk_persistent_t)(const WalkArgs*, const int2*, int, unsigned*);
+
+}  // namespace walkimpl
+
+// Kernel lookup across the instantiation units: plain and persistent forms for
+// (NW, R, RB); R is rounded up to an instantiated value, RB to R or ceil(R/2).
+struct WalkKernels {
+    walkimpl::walk_kernel_t plain;
+    walkimpl::walk_persistent_t persistent;
+    int R, RB;
+};
+bool walk_kernels_lookup(int NW, int R, int RB, WalkKernels* out);
+bool walk_kernels_a(int NW, int R, int RB, WalkKernels* out);   // NW 1..4
+bool walk_kernels_b(int NW, int R, int RB, WalkKernels* out);   // NW 5..7
+bool walk_kernels_c(int NW, int R, int RB, WalkKernels* out);   // NW 8..10
+
+}  // namespace labsdev

@@ -101,6 +101,14 @@ def lib():
             L.labs_refine_step2.restype = i32
             L.labs_refine_step2.argtypes = [ctypes.POINTER(Step2Cfg), i64, vp,
                                             ctypes.POINTER(Step2Out), vp, sz, vp]
+            L.labs_autotune_step1.restype = i32
+            L.labs_autotune_step1.argtypes = [ctypes.POINTER(i32), i32, i32, i32, i32, vp]
+            L.labs_autotune_save.restype = i32
+            L.labs_autotune_save.argtypes = [ctypes.c_char_p]
+            L.labs_autotune_load.restype = i32
+            L.labs_autotune_load.argtypes = [ctypes.c_char_p]
+            L.labs_autotune_get.restype = i32
+            L.labs_autotune_get.argtypes = [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
             L.labs_timing_enable.restype = i32
             L.labs_timing_enable.argtypes = [i32]
             L.labs_timing_reset.restype = i32
@@ -317,3 +325,74 @@ def refine_step2(L: int, cands, batch: int, pq_capacity: int, max_expansions: in
         res["open_seqs"] = open_seqs[:m]
         res["open_E"] = open_E[:m]
     return res
+
+
+# ---------------------------------------------------------------- batched first step
+def walk_step1_batch(cfgs, want_traj: bool = False, device="cuda", workspace=None, results=None):
+    """One batched launch over several configurations (dicts with L, p, steps,
+    tenure_lo, tenure_hi, seed, n_walkers and optionally walker_begin).
+    Returns (results, workspace); the launch is asynchronous.  Passing back the
+    same results and workspace replays the captured graph."""
+    torch = _torch()
+    n = len(cfgs)
+    arr = (Step1Cfg * n)()
+    for i, c in enumerate(cfgs):
+        arr[i] = Step1Cfg(c["L"], c["p"], c["steps"], c["tenure_lo"], c["tenure_hi"], -1,
+                          c.get("walker_begin", 0), c["n_walkers"], c["seed"], 0, 0)
+    sz = ctypes.c_size_t(0)
+    _check(lib().labs_walk_step1_workspace(arr, n, 0, ctypes.byref(sz)))
+    if workspace is None or workspace.numel() < sz.value:
+        workspace = torch.empty(int(sz.value), dtype=torch.uint8, device=device)
+    outs = (Step1Out * n)()
+    res = []
+    for i, c in enumerate(cfgs):
+        if results is not None:
+            r = results[i]
+            r.flip_evals.zero_()
+            outs[i] = Step1Out(r.final_seqs.data_ptr(), r.final_E.data_ptr(), r.best_seqs.data_ptr(),
+                               r.best_E.data_ptr(), r.best_step.data_ptr(),
+                               r.traj_E.data_ptr() if r.traj_E is not None else None,
+                               r.flip_evals.data_ptr())
+            res.append(r)
+            continue
+        L, nw = c["L"], c["n_walkers"]
+        W = words(L)
+        steps_eff = c["steps"] if c["steps"] else 4 * (L + 1)
+        r = Step1Result(
+            final_seqs=torch.empty((nw, W), dtype=torch.int32, device=device),
+            final_E=torch.empty(nw, dtype=torch.int32, device=device),
+            best_seqs=torch.empty((nw, W), dtype=torch.int32, device=device),
+            best_E=torch.empty(nw, dtype=torch.int32, device=device),
+            best_step=torch.empty(nw, dtype=torch.int32, device=device),
+            traj_E=(torch.empty((nw, steps_eff), dtype=torch.int32, device=device)
+                    if want_traj else None),
+            flip_evals=torch.zeros(1, dtype=torch.int64, device=device))
+        outs[i] = Step1Out(r.final_seqs.data_ptr(), r.final_E.data_ptr(), r.best_seqs.data_ptr(),
+                           r.best_E.data_ptr(), r.best_step.data_ptr(),
+                           r.traj_E.data_ptr() if want_traj else None, r.flip_evals.data_ptr())
+        res.append(r)
+    _check(lib().labs_walk_step1(arr, n, None, None, outs, _ptr(workspace), workspace.numel(),
+                                 _stream(torch.device(device))))
+    return res, workspace
+
+
+def autotune_step1(Ls, p: int, walkers: int, steps: int, device="cuda") -> None:
+    torch = _torch()
+    arr = (ctypes.c_int32 * len(Ls))(*Ls)
+    _check(lib().labs_autotune_step1(arr, len(Ls), p, walkers, steps,
+                                     _stream(torch.device(device))))
+
+
+def autotune_save(path: str) -> None:
+    _check(lib().labs_autotune_save(path.encode()))
+
+
+def autotune_load(path: str) -> None:
+    _check(lib().labs_autotune_load(path.encode()))
+
+
+def autotune_get(L: int, p: int):
+    rb = ctypes.c_int32(0)
+    wv = ctypes.c_int32(0)
+    _check(lib().labs_autotune_get(L, p, ctypes.byref(rb), ctypes.byref(wv)))
+    return int(rb.value), int(wv.value)
