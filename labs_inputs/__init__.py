@@ -137,3 +137,18 @@ def hex_decode(h: str, L: int) -> np.ndarray:
     if pad < 0 or pad > 3 or "1" in bits[:pad]:
         raise ValueError("hex string does not hold a sequence of length %d" % L)
     return np.array([1 if b == "1" else -1 for b in bits[pad:]], dtype=np.int8)
+
+
+def mlp_init(seed: int, d_in: int, d_h: int, d_out: int) -> dict:
+    """Initial MLP weights: U(-1/sqrt(fan_in), 1/sqrt(fan_in)) per layer from a
+    seeded PCG64 stream, zero biases (float32).  W1 [d_h, d_in], W2 [d_h, d_h],
+    W3 [d_out, d_h]."""
+    g = rng(seed)
+
+    def u(rows, cols):
+        b = 1.0 / np.sqrt(cols)
+        return g.uniform(-b, b, size=(rows, cols)).astype(np.float32)
+
+    return {"W1": u(d_h, d_in), "b1": np.zeros(d_h, np.float32),
+            "W2": u(d_h, d_h), "b2": np.zeros(d_h, np.float32),
+            "W3": u(d_out, d_h), "b3": np.zeros(d_out, np.float32)}
