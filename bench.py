@@ -47,7 +47,43 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline-pass", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (the reference "
+                         "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib: int):
+    import torch
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n, "launches": 5}), flush=True)
+
+
+WALK_SOURCES = ["walk_impl.h", "walk.hip", "walk_inst_a.hip", "walk_inst_b.hip", "walk_inst_c.hip"]
+COUNTERS = os.path.join(ROOT, "profiles", "walk_L501_hbm_counters.txt")
+
+
+def walk_traffic():
+    """HBM bytes per walk launch from the committed counter summary, or None when
+    the walk kernel's sources have changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(COUNTERS).read()
+    except OSError:
+        return None
+    vals = dict(line.strip().split(": ", 1) for line in txt.splitlines()
+                if line.strip().startswith(("traffic_bytes_per_launch:", "kernel_sources_sha256:")))
+    h = hashlib.sha256()
+    for f in WALK_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2409_07222_amd", "csrc", f), "rb").read())
+    if vals.get("kernel_sources_sha256") != h.hexdigest():
+        return None
+    return int(vals["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(budget_s: float):
@@ -72,6 +108,9 @@ def cpu_baseline(budget_s: float):
 
 def main():
     a = parse()
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(walkers shard by id range; see DESIGN.md)", file=sys.stderr)
@@ -156,7 +195,7 @@ def main():
         achieved = ops / (ms / 1e3) / 1e12
         peak = PEAK_INT_OPS / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
-                "frac": achieved / peak, "traffic": None,
+                "frac": achieved / peak, "traffic": walk_traffic(),
                 "kernel": "walk", "launches": launches, "avg_launch_ms": ms / max(launches, 1),
                 "ops_per_flip_eval": W_OPS, "kernel_share_of_pass": ms / 1e3 / t_pass}
         if launches2:

@@ -282,6 +282,163 @@ labs_status labs_timing_enable(int32_t on);
 labs_status labs_timing_reset(void);
 labs_status labs_timing_read(const char* kernel, double* total_ms, int64_t* launches);
 
+
+/* ============================================================================
+ * Learned flip proposal.  Not part of the paper's method: a small network
+ * reorders which skew flips (Alg. 1 neighbourhood, Eq. (2) partners) receive an
+ * exact energy evaluation; every accepted move is still scored exactly.
+ *
+ * Network: x -> GELU(W1 x + b1) -> GELU(W2 h1 + b2) -> W3 h2 + b3, GELU in its
+ * tanh form.  For odd L = 2k+1:
+ *   x  (d_in = L + k values)   s_1..s_L as +1/-1, then C_{2m}/(L-2m), m = 1..k
+ *   z  (d_out = k + 1 logits)  logit j scores the skew flip of position j+1
+ * Products take bfloat16 operands (round to nearest even) and accumulate in
+ * FP32; biases, pre-activations and logits are FP32; hidden activations are
+ * stored as bf16.
+ *
+ * Parameter blob: one FP32 array of n_params elements (the masters) and a bf16
+ * copy with the same offsets (the product operands; its bias slots are unused):
+ *   W1 [hidden][ld_in] at off_W1     b1 [hidden] at off_b1
+ *   W2 [hidden][hidden] at off_W2    b2 [hidden] at off_b2
+ *   W3 [ld_out][hidden] at off_W3    b3 [ld_out] at off_b3
+ * Pad columns of W1 (d_in..ld_in-1) and pad rows of W3 / entries of b3
+ * (d_out..ld_out-1) do not affect any result.
+ * Feature rows X are bf16 (uint16 bit patterns) with row stride ld_in, pads 0.
+ * Logit rows have stride ld_out; their pad columns are not written.
+ * Admissibility masks: mask_words uint32 per row, bit (j mod 32) of word j/32
+ * set when logit j may be chosen.  Labels: int32 in [0, d_out).
+ * -------------------------------------------------------------------------- */
+typedef struct {
+    int32_t L, k, d_in, d_out, hidden;
+    int32_t ld_in;        /* d_in rounded up to a multiple of 64 */
+    int32_t ld_out;       /* d_out rounded up to a multiple of 64 */
+    int32_t mask_words;   /* ceil(d_out / 32) */
+    int64_t off_W1, off_b1, off_W2, off_b2, off_W3, off_b3;
+    int64_t n_params;     /* elements of the blob (each slice 64-aligned) */
+} labs_mlp_layout;
+
+/* Host-only.  L odd in [5, 1023]; hidden a multiple of 64 in [64, 1024]. */
+labs_status labs_mlp_layout_of(int32_t L, int32_t hidden, labs_mlp_layout* out);
+
+/* Features of n packed sequences of length L (odd): X [n*ld_in] bf16, written. */
+labs_status labs_mlp_features(int32_t L, int64_t n, const uint32_t* seqs, uint16_t* X, void* stream);
+
+/* Forward pass: logits [n*ld_out] FP32 from features X [n*ld_in].
+ *   params       FP32 blob (biases are read from it)
+ *   params_bf16  bf16 blob (weights are read from it)
+ *   ws           scratch of labs_mlp_forward_workspace bytes (device) */
+labs_status labs_mlp_forward_workspace(const labs_mlp_layout* lay, int64_t n, size_t* bytes);
+labs_status labs_mlp_forward(const labs_mlp_layout* lay, const float* params, const uint16_t* params_bf16,
+                             int64_t n, const uint16_t* X, float* logits, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/* Gradients of the mean masked softmax cross-entropy over n rows:
+ *   loss_r = logsumexp_{j admissible} z_rj - z_r,label   (the label always counts
+ *   as admissible), loss = mean_r loss_r.
+ * grads (FP32 blob, every element overwritten; pads 0) and *loss (device float)
+ * are written.  The backward products use the same bf16 rounding as the
+ * forward, applied to the upstream gradient too; bias gradients sum FP32 values. */
+labs_status labs_mlp_grads_workspace(const labs_mlp_layout* lay, int64_t n, size_t* bytes);
+labs_status labs_mlp_grads(const labs_mlp_layout* lay, const float* params, const uint16_t* params_bf16,
+                           int64_t n, const uint16_t* X, const uint32_t* mask, const int32_t* labels,
+                           float* grads, float* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* One Adam step (Kingma and Ba 2015) over the whole blob, t >= 1 counting from 1:
+ *   m = b1 m + (1-b1) g;  v = b2 v + ((1-b2) g) g;
+ *   p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)
+ * in FP32 with each operation rounded separately (constants rounded to FP32
+ * once: b1, 1-b1, b2, 1-b2, 1-b^t, lr, eps); params_bf16 is refreshed. */
+labs_status labs_mlp_adam(const labs_mlp_layout* lay, float* params, uint16_t* params_bf16,
+                          const float* grads, float* m, float* v, int32_t t, double lr, double beta1,
+                          double beta2, double eps, void* stream);
+
+/* params_bf16 = bf16(params), elementwise. */
+labs_status labs_mlp_cast(const labs_mlp_layout* lay, const float* params, uint16_t* params_bf16,
+                          void* stream);
+
+/* One training step on logged walker states: features of seqs [n*W], then
+ * labs_mlp_grads, then labs_mlp_adam with step t.  grads is written. */
+labs_status labs_mlp_train_workspace(const labs_mlp_layout* lay, int64_t n, size_t* bytes);
+labs_status labs_mlp_train_step(const labs_mlp_layout* lay, float* params, uint16_t* params_bf16,
+                                float* grads, float* m, float* v, int32_t t, double lr, double beta1,
+                                double beta2, double eps, int64_t n, const uint32_t* seqs,
+                                const uint32_t* mask, const int32_t* labels, float* loss, void* ws,
+                                size_t ws_bytes, void* stream);
+
+
+/* ----------------------------------------------------------------------------
+ * labs_learned_walk -- the first-step walk (Alg. 1 neighbourhood: skew flips of
+ * the free positions p+1..k+1, Eq. (3)) with the candidate set narrowed by a
+ * proposer.  Walkers start exactly as in labs_walk_step1 (same seed, walker ids,
+ * initial sequences and tenures).  At step t (from 1) of a walker:
+ *   admissible  = free positions a with tabu_until(a) < t
+ *   candidates  = every admissible position when (t-1) mod fallback_every == 0
+ *                 (a full exact scan: the plain walker's step), otherwise the
+ *                 top_m admissible positions by proposer score (ties: lower a)
+ *   move        = the candidate of least exact integer dE (ties: lower a),
+ *                 dE computed from the current C table by definition
+ *   then E += dE, tabu_until(a) = t + tenure, as in the plain walker.
+ * With fallback_every = 1, or top_m >= k+1-p, every step is the plain walker's.
+ * Proposers:
+ *   LABS_PROPOSE_MLP     score = logit a-1 of the network (labs_mlp_* layout,
+ *                        hidden width prop->hidden) on the current state
+ *   LABS_PROPOSE_RANDOM  score = a SplitMix64 draw keyed by (prop->seed,
+ *                        walker, t, a): top_m uniformly random admissible
+ *                        positions (the ablation without a network)
+ * Training log (prop->log_every > 0): n_log = steps / log_every records per
+ * walker, stored step-major (record r of walker j at index r*n + j, so that
+ * consecutive records come from different walkers); it describes step
+ * t = (r+1)*log_every: the packed state before the move (W words), the
+ * admissible positions (mask_words words, bit (a-1) mod 32 of word (a-1)/32)
+ * and the label a-1 of the chosen move.  Logged from a walker with
+ * fallback_every = 1 the label is the plain walker's best admissible flip.
+ * Outputs (device, nullable except flip_evals):
+ *   final_seqs/final_E, best_seqs/best_E/best_step as labs_walk_step1
+ *   hit_step  [n]  first step with E <= cfg->e_max (-1 if none or e_max < 0)
+ *   traj_E    [n*steps] E after each step (-1 after a halt)
+ *   moves     [n*steps] moved position a (-1 after a halt)
+ *   cands     [n*steps*top_m] the rescored positions of each non-full step in
+ *             descending score order (-1 on full-scan steps and as padding)
+ *   flip_evals [1] exact dE evaluations over all walkers and steps
+ * cfg: as labs_walk_step1 with n_cfg = 1; flags must be 0.  Limits: L <= 639,
+ * 1 <= top_m <= 64, fallback_every >= 1.  The network weights must not change
+ * while the call runs.
+ * -------------------------------------------------------------------------- */
+#define LABS_PROPOSE_MLP 0
+#define LABS_PROPOSE_RANDOM 1
+
+typedef struct {
+    int32_t mode;
+    int32_t top_m;
+    int32_t fallback_every;
+    int32_t hidden;
+    const float* params;          /* FP32 blob (MLP mode) */
+    const uint16_t* params_bf16;  /* bf16 blob (MLP mode) */
+    uint64_t seed;                /* RANDOM mode */
+    int32_t log_every;
+    int32_t reserved;             /* must be 0 */
+} labs_proposer;
+
+typedef struct {
+    uint32_t* final_seqs;
+    int32_t* final_E;
+    uint32_t* best_seqs;
+    int32_t* best_E;
+    int32_t* best_step;
+    int32_t* hit_step;
+    int32_t* traj_E;
+    int32_t* moves;
+    int16_t* cands;
+    uint32_t* log_seqs;
+    uint32_t* log_mask;
+    int32_t* log_label;
+    int64_t* flip_evals;
+} labs_learned_out;
+
+labs_status labs_learned_walk_workspace(const labs_step1_cfg* cfg, const labs_proposer* prop, size_t* bytes);
+labs_status labs_learned_walk(const labs_step1_cfg* cfg, const labs_proposer* prop, const labs_learned_out* out,
+                              void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

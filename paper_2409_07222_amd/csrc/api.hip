@@ -208,6 +208,10 @@ struct HostPair {
 
 }  // namespace
 
+namespace labsdev {
+labs_status validate_step1_cfg(const labs_step1_cfg& c) { return check_step1_cfg(c); }
+}  // namespace labsdev
+
 extern "C" {
 
 int32_t labs_abi_version(void) { return LABS_ABI_VERSION; }

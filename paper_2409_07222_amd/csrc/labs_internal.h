@@ -65,6 +65,13 @@ __device__ __forceinline__ uint64_t walker_key(uint64_t seed, int32_t L, int64_t
     return sm64_mix(seed ^ sm64_mix(lw));
 }
 
+// bfloat16 bit pattern of an FP32 value, round to nearest even.
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 // Packed wire format: s_i (1-based) is bit 31-((i-1)&31) of word (i-1)>>5.
 __device__ __forceinline__ int packed_bit(const uint32_t* w, int i) {
     return (w[(i - 1) >> 5] >> (31 - ((i - 1) & 31))) & 1;
@@ -141,5 +148,26 @@ labs_status launch_walk_outputs(const WalkArgs& A, const labs_step1_out& o, hipS
 // leaving the permutation in *perm_out (device array of n uint32, inside ws).
 labs_status radix_sort_records(const RecBuf& rb, int64_t n, int32_t nkeys, void* ws,
                                size_t ws_bytes, uint32_t** perm_out, hipStream_t st);
+
+// Learned proposal network (mlp.hip).
+bool mlp_layout(int L, int hidden, labs_mlp_layout* o);
+labs_status launch_features(int L, int64_t n, const uint32_t* seqs, uint16_t* X, int ld_in, hipStream_t st);
+size_t mlp_forward_ws(const labs_mlp_layout& y, int64_t n);
+labs_status mlp_forward(const labs_mlp_layout& y, const float* P, const uint16_t* Pb, int64_t n, const uint16_t* X,
+                        float* logits, void* ws, size_t wsb, hipStream_t st);
+size_t mlp_grads_ws(const labs_mlp_layout& y, int64_t n);
+labs_status mlp_grads(const labs_mlp_layout& y, const float* P, const uint16_t* Pb, int64_t n, const uint16_t* X,
+                      const uint32_t* mask, const int32_t* labels, float* G, float* loss, void* ws, size_t wsb,
+                      hipStream_t st);
+labs_status mlp_adam(const labs_mlp_layout& y, float* P, uint16_t* Pb, const float* G, float* M, float* V, int t,
+                     double lr, double b1, double b2, double eps, hipStream_t st);
+labs_status mlp_cast(const labs_mlp_layout& y, const float* P, uint16_t* Pb, hipStream_t st);
+
+// First-step walk with a proposer (learned.hip).
+labs_status validate_step1_cfg(const labs_step1_cfg& c);
+bool learned_walk_supported(int L);
+size_t learned_walk_ws(const labs_step1_cfg& c, const labs_proposer& pr);
+labs_status learned_walk(const labs_step1_cfg& c, const labs_proposer& pr, const labs_learned_out& o, void* ws,
+                         size_t wsb, hipStream_t st);
 
 }  // namespace labsdev

@@ -1,0 +1,487 @@
+// First-step walk with a proposer narrowing the candidate flips (the learned
+// form): every candidate is rescored with its exact integer energy change, and
+// every fallback_every-th step is the plain walker's full scan.
+//
+// One wavefront per walker and step.  The walker state lives in HBM between
+// steps (packed sequence, energy, tabu deadlines, tenure, best), so the network
+// can run as batched products between two step launches; the C_{2m} table is
+// rebuilt each step from the packed bits (L-2m overlapping bits, popcount of
+// their XOR), which costs less than storing and reloading it.
+#include "labs_internal.h"
+
+#include <climits>
+#include <map>
+#include <mutex>
+#include <string>
+
+namespace labsdev {
+
+namespace {
+
+constexpr int kLwLmax = 639;
+constexpr int kLwWmax = 20;
+constexpr int kLwKmax = 319;
+constexpr int kLwSlots = 5;   // ceil((kLwKmax + 1) / 64) free positions per lane
+
+struct LwArgs {
+    int32_t L, p, k, nf, W, MW, ld_in, ld_out;
+    int32_t top_m, fallback_every, mode, log_every, steps, n_log;
+    int64_t n, walker_begin;
+    uint64_t prop_seed;
+    int32_t e_max;
+    uint32_t* seq;
+    int32_t* E;
+    const int32_t* tenure;
+    int32_t* halted;
+    int32_t* tabu;
+    int32_t* bestE;
+    int32_t* bestT;
+    uint32_t* bestSeq;
+    int32_t* tstep;
+    int64_t* evals;
+    int32_t* hit;
+    const float* logits;
+    uint16_t* X;
+    int32_t* traj;
+    int32_t* moves;
+    int16_t* cands;
+    uint32_t* log_seqs;
+    uint32_t* log_mask;
+    int32_t* log_label;
+};
+
+struct LwLds {
+    uint32_t pk[kLwWmax + 1];
+    int32_t C[kLwKmax + 1];       // C[m] = C_{2m}, m = 1..k
+    int32_t cand[kLwKmax + 2];    // candidate positions a
+    int8_t sv[kLwLmax + 1];       // sv[i-1] = s_i
+};
+
+// C_d = (L-d) - 2 popcount(b XOR (b << d)) over the L-d overlapping bits.
+__device__ __forceinline__ int corr(const uint32_t* pk, int W, int L, int d) {
+    const int len = L - d, q = d >> 5, sh = d & 31;
+    int pc = 0;
+    for (int w = 0; w * 32 < len; ++w) {
+        const uint32_t hi = pk[w + q];
+        const uint32_t lo = (w + q + 1 < W) ? pk[w + q + 1] : 0u;
+        const uint32_t sft = sh ? ((hi << sh) | (lo >> (32 - sh))) : hi;
+        uint32_t x = pk[w] ^ sft;
+        const int rem = len - w * 32;
+        if (rem < 32) x &= ~(0xFFFFFFFFu >> rem);
+        pc += __popc(x);
+    }
+    return len - 2 * pc;
+}
+
+// Change of C_d when the set {a, b} flips (b = a for the centre): a product
+// s_x s_{x+d} changes sign exactly when one of x, x+d lies in the set.
+__device__ __forceinline__ int dC(const int8_t* sv, int L, int a, int b, int d) {
+    int ua = 0;
+    const int i1 = a + d, i2 = a - d;
+    if (i1 <= L && i1 != b) ua += sv[i1 - 1];
+    if (i2 >= 1 && i2 != b) ua += sv[i2 - 1];
+    int r = sv[a - 1] * ua;
+    if (b != a) {
+        int ub = 0;
+        const int j1 = b + d, j2 = b - d;
+        if (j1 <= L && j1 != a) ub += sv[j1 - 1];
+        if (j2 >= 1 && j2 != a) ub += sv[j2 - 1];
+        r += sv[b - 1] * ub;
+    }
+    return -2 * r;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+__device__ __forceinline__ int64_t wave_min_i64(int64_t v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t w = __shfl_xor(v, o);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+// Order-preserving map of an FP32 score to uint32 (-0 counts as +0).
+__device__ __forceinline__ uint32_t score_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if (u == 0x80000000u) u = 0;
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ __launch_bounds__(64) void k_lw_step(LwArgs A) {
+    __shared__ LwLds S;
+    const int lane = threadIdx.x;
+    const int64_t j = blockIdx.x;
+    const int L = A.L, k = A.k, p = A.p, nf = A.nf, W = A.W;
+    const int t = A.tstep[j] + 1;
+    const bool full = ((t - 1) % A.fallback_every) == 0;
+    const int64_t tb = j * nf;
+    const int64_t ti = j * A.steps + (t - 1);
+
+    if (A.halted[j]) {
+        if (lane == 0) {
+            if (A.traj) A.traj[ti] = -1;
+            if (A.moves) A.moves[ti] = -1;
+            A.tstep[j] = t;
+        }
+        if (A.cands)
+            for (int i = lane; i < A.top_m; i += 64) A.cands[ti * A.top_m + i] = -1;
+        return;
+    }
+
+    if (lane < W) S.pk[lane] = A.seq[j * W + lane];
+    if (lane == 0) S.pk[W] = 0;
+    __syncthreads();
+    for (int i = lane; i < L; i += 64) S.sv[i] = ((S.pk[i >> 5] >> (31 - (i & 31))) & 1) ? 1 : -1;
+    for (int m = 1 + lane; m <= k; m += 64) S.C[m] = corr(S.pk, W, L, 2 * m);
+
+    // ---- candidates
+    int ncand = 0;
+    if (full) {
+        for (int f0 = 0; f0 < nf; f0 += 64) {
+            const int f = f0 + lane;
+            const bool ok = f < nf && A.tabu[tb + f] < t;
+            const uint64_t bal = __ballot(ok);
+            if (ok) S.cand[ncand + __popcll(bal & ((1ull << lane) - 1ull))] = p + 1 + f;
+            ncand += __popcll(bal);
+        }
+    } else {
+        uint64_t key[kLwSlots];
+        uint64_t rkey = 0;
+        if (A.mode == LABS_PROPOSE_RANDOM) rkey = walker_key(A.prop_seed, L, A.walker_begin + j);
+        for (int r = 0; r < kLwSlots; ++r) {
+            const int f = lane + 64 * r;
+            key[r] = 0;
+            if (f < nf && A.tabu[tb + f] < t) {
+                const int a = p + 1 + f;
+                uint32_t sc;
+                if (A.mode == LABS_PROPOSE_MLP)
+                    sc = score_bits(A.logits[j * A.ld_out + (a - 1)]);
+                else
+                    sc = (uint32_t)(sm64_at(rkey, (uint64_t)(t - 1) * (uint64_t)(k + 1) + (uint64_t)(a - 1)) >> 32);
+                key[r] = ((uint64_t)sc << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)f);
+            }
+        }
+        for (int c = 0; c < A.top_m; ++c) {
+            uint64_t best = 0;
+            for (int r = 0; r < kLwSlots; ++r) best = key[r] > best ? key[r] : best;
+            best = wave_max_u64(best);
+            if (best == 0) break;
+            for (int r = 0; r < kLwSlots; ++r)
+                if (key[r] == best) key[r] = 0;
+            if (lane == 0) S.cand[c] = p + 1 + (int)(0xFFFFFFFFu - (uint32_t)best);
+            ++ncand;
+        }
+    }
+    __syncthreads();
+
+    // ---- exact dE of every candidate: lanes split over (candidate, lag group)
+    int G = 1;
+    if (ncand < 64) {
+        int p2 = 1;
+        while (p2 < ncand) p2 <<= 1;
+        G = 64 / p2;
+    }
+    const int per = 64 / G;
+    int64_t bestkey = LLONG_MAX;
+    for (int c0 = 0; c0 < ncand; c0 += per) {
+        const int c = c0 + lane / G, g = lane % G;
+        int acc = 0, a = 0;
+        if (c < ncand) {
+            a = S.cand[c];
+            const int b = L + 1 - a;
+            for (int m = 1 + g; m <= k; m += G) {
+                const int d = dC(S.sv, L, a, b, 2 * m);
+                acc += d * (2 * S.C[m] + d);
+            }
+        }
+        for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (c < ncand && g == 0) {
+            const int64_t key = (int64_t)acc * 4294967296LL + (int64_t)a;
+            bestkey = key < bestkey ? key : bestkey;
+        }
+    }
+    bestkey = wave_min_i64(bestkey);
+
+    if (ncand == 0) {   // no admissible move: the walk halts here
+        if (lane == 0) {
+            A.halted[j] = t;
+            if (A.traj) A.traj[ti] = -1;
+            if (A.moves) A.moves[ti] = -1;
+            A.tstep[j] = t;
+        }
+        if (A.cands)
+            for (int i = lane; i < A.top_m; i += 64) A.cands[ti * A.top_m + i] = -1;
+        return;
+    }
+    const int dE = (int)(bestkey >> 32);
+    const int a = (int)(bestkey & 0xFFFFFFFFLL);
+    const int b = L + 1 - a;
+    const int E0 = A.E[j], bE0 = A.bestE[j], newE = E0 + dE;
+
+    // ---- training log: the state before the move
+    if (A.log_every > 0 && t % A.log_every == 0) {
+        const int64_t r = (int64_t)(t / A.log_every - 1) * A.n + j;   // step-major records
+        if (lane < W) A.log_seqs[r * W + lane] = S.pk[lane];
+        for (int w = lane; w < A.MW; w += 64) {
+            uint32_t bits = 0;
+            for (int q = 0; q < 32; ++q) {
+                const int pos = 32 * w + q + 1;
+                if (pos > p && pos <= k + 1 && A.tabu[tb + pos - p - 1] < t) bits |= 1u << q;
+            }
+            A.log_mask[r * A.MW + w] = bits;
+        }
+        if (lane == 0) A.log_label[r] = a - 1;
+    }
+    if (A.cands)
+        for (int i = lane; i < A.top_m; i += 64) A.cands[ti * A.top_m + i] = (!full && i < ncand) ? (int16_t)S.cand[i] : (int16_t)-1;
+    __syncthreads();
+
+    // ---- apply
+    if (lane == 0) {
+        S.pk[(a - 1) >> 5] ^= 1u << (31 - ((a - 1) & 31));
+        if (b != a) S.pk[(b - 1) >> 5] ^= 1u << (31 - ((b - 1) & 31));
+        A.E[j] = newE;
+        A.tabu[tb + (a - p - 1)] = t + A.tenure[j];
+        if (A.traj) A.traj[ti] = newE;
+        if (A.moves) A.moves[ti] = a;
+        A.evals[j] += ncand;
+        A.tstep[j] = t;
+        if (A.e_max >= 0 && newE <= A.e_max && A.hit[j] < 0) A.hit[j] = t;
+        if (newE < bE0) {
+            A.bestE[j] = newE;
+            A.bestT[j] = t;
+        }
+    }
+    __syncthreads();
+    if (lane < W) {
+        A.seq[j * W + lane] = S.pk[lane];
+        if (newE < bE0) A.bestSeq[j * W + lane] = S.pk[lane];
+    }
+
+    // ---- features of the new state for the next step's network pass
+    if (A.X && (t % A.fallback_every) != 0 && t < A.steps) {
+        uint16_t* x = A.X + j * A.ld_in;
+        for (int i = lane; i < A.ld_in; i += 64) {
+            uint16_t v = 0;
+            if (i < L) {
+                int s = S.sv[i];
+                if (i + 1 == a || i + 1 == b) s = -s;
+                v = s > 0 ? (uint16_t)0x3F80 : (uint16_t)0xBF80;
+            } else if (i < L + k) {
+                const int m = i - L + 1, d = 2 * m;
+                const int c = S.C[m] + dC(S.sv, L, a, b, d);
+                v = f2bf((float)c / (float)(L - d));
+            }
+            x[i] = v;
+        }
+    }
+}
+
+__global__ void k_lw_init(int64_t n, int32_t* tstep, int64_t* evals, int32_t* hit) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        tstep[i] = 0;
+        evals[i] = 0;
+        hit[i] = -1;
+    }
+}
+
+__global__ void k_lw_outputs(LwArgs A, uint32_t* final_seqs, int32_t* final_E, uint32_t* best_seqs,
+                             int32_t* best_E, int32_t* best_step, int32_t* hit_step) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < A.n * A.W) {
+        if (final_seqs) final_seqs[i] = A.seq[i];
+        if (best_seqs) best_seqs[i] = A.bestSeq[i];
+    }
+    if (i < A.n) {
+        if (final_E) final_E[i] = A.E[i];
+        if (best_E) best_E[i] = A.bestE[i];
+        if (best_step) best_step[i] = A.bestT[i];
+        if (hit_step) hit_step[i] = A.hit[i];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sum_i64(int64_t n, const int64_t* v, int64_t* out) {
+    __shared__ int64_t part[256];
+    int64_t s = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += v[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = part[0];
+}
+
+struct LwBuffers {
+    WalkArgs wa;
+    LwArgs la;
+    void* fwd_ws;
+    size_t fwd_bytes;
+    size_t bytes;   // workspace used
+    bool ok;
+};
+
+LwBuffers carve_lw(const labs_step1_cfg& c, const labs_proposer& pr, const labs_mlp_layout* lay, void* ws,
+                   size_t wsb) {
+    LwBuffers B{};
+    Carve cv(ws, wsb);
+    const int L = c.L, k = (L - 1) / 2, nf = k + 1 - c.p, W = words_of(L);
+    const int64_t n = c.n_walkers;
+    WalkArgs& w = B.wa;
+    w.L = L; w.p = c.p; w.k = k; w.nf = nf; w.W = W;
+    w.t0 = 0; w.t1 = 0; w.steps_total = c.steps;
+    w.n = n; w.walker_begin = c.walker_begin; w.seed = c.seed;
+    w.tenure_lo = c.tenure_lo; w.tenure_hi = c.tenure_hi;
+    w.seq = cv.take<uint32_t>((size_t)n * W);
+    w.E = cv.take<int32_t>(n);
+    w.tenure = cv.take<int32_t>(n);
+    w.halted = cv.take<int32_t>(n);
+    w.tabu = cv.take<int32_t>((size_t)n * nf);
+    w.bestE = cv.take<int32_t>(n);
+    w.bestT = cv.take<int32_t>(n);
+    w.bestSeq = cv.take<uint32_t>((size_t)n * W);
+    w.traj = nullptr;
+    w.e_max = c.e_max;
+    LwArgs& a = B.la;
+    a.L = L; a.p = c.p; a.k = k; a.nf = nf; a.W = W; a.MW = (k + 1 + 31) / 32;
+    a.ld_in = lay ? lay->ld_in : 0;
+    a.ld_out = lay ? lay->ld_out : 0;
+    a.top_m = pr.top_m; a.fallback_every = pr.fallback_every; a.mode = pr.mode;
+    a.log_every = pr.log_every; a.steps = c.steps;
+    a.n_log = pr.log_every > 0 ? c.steps / pr.log_every : 0;
+    a.n = n; a.walker_begin = c.walker_begin; a.prop_seed = pr.seed; a.e_max = c.e_max;
+    a.seq = w.seq; a.E = w.E; a.tenure = w.tenure; a.halted = w.halted; a.tabu = w.tabu;
+    a.bestE = w.bestE; a.bestT = w.bestT; a.bestSeq = w.bestSeq;
+    a.tstep = cv.take<int32_t>(n);
+    a.evals = cv.take<int64_t>(n);
+    a.hit = cv.take<int32_t>(n);
+    if (lay) {
+        a.X = cv.take<uint16_t>((size_t)n * lay->ld_in);
+        a.logits = cv.take<float>((size_t)n * lay->ld_out);
+        B.fwd_bytes = mlp_forward_ws(*lay, n);
+        B.fwd_ws = cv.take<char>(B.fwd_bytes);
+    }
+    B.bytes = cv.used;
+    B.ok = cv.ok() && ws != nullptr;
+    return B;
+}
+
+hipStream_t capture_stream_lw() {
+    static hipStream_t cs = nullptr;
+    if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) cs = nullptr;
+    return cs;
+}
+
+// Executable graphs of one period of steps, keyed by everything their launches
+// capture (kernel arguments and network pointers); kept until the process ends.
+std::mutex g_lw_mu;
+std::map<std::string, hipGraphExec_t> g_lw_graphs;
+
+}  // namespace
+
+size_t learned_walk_ws(const labs_step1_cfg& c, const labs_proposer& pr) {
+    labs_mlp_layout lay;
+    const bool mlp = pr.mode == LABS_PROPOSE_MLP && mlp_layout(c.L, pr.hidden, &lay);
+    return carve_lw(c, pr, mlp ? &lay : nullptr, nullptr, 0).bytes + 256;
+}
+
+bool learned_walk_supported(int L) { return L <= kLwLmax; }
+
+labs_status learned_walk(const labs_step1_cfg& c, const labs_proposer& pr, const labs_learned_out& o, void* ws,
+                         size_t wsb, hipStream_t st) {
+    labs_mlp_layout lay;
+    const bool mlp = pr.mode == LABS_PROPOSE_MLP;
+    if (mlp && !mlp_layout(c.L, pr.hidden, &lay)) return invalid("unsupported network width %d", pr.hidden);
+    LwBuffers B = carve_lw(c, pr, mlp ? &lay : nullptr, ws, wsb);
+    if (!B.ok) return invalid("workspace too small");
+    LwArgs& A = B.la;
+    A.traj = o.traj_E;
+    A.moves = o.moves;
+    A.cands = o.cands;
+    A.log_seqs = o.log_seqs;
+    A.log_mask = o.log_mask;
+    A.log_label = o.log_label;
+    if (!mlp) {
+        A.X = nullptr;
+        A.logits = nullptr;
+    }
+    const int64_t n = A.n;
+    labs_status s = launch_walker_init(B.wa, st);
+    if (s) return s;
+    hipLaunchKernelGGL(k_lw_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, A.tstep, A.evals, A.hit);
+    LABS_LAUNCHED("k_lw_init");
+
+    // One launch sequence per step; steps t with (t-1) mod F == 0 need no network pass.
+    const int F = pr.fallback_every;
+    auto enqueue_step = [&](int t, hipStream_t q) -> labs_status {
+        if (mlp && ((t - 1) % F) != 0) {
+            labs_status r = mlp_forward(lay, pr.params, pr.params_bf16, n, A.X, const_cast<float*>(A.logits),
+                                        B.fwd_ws, B.fwd_bytes, q);
+            if (r) return r;
+        }
+        hipLaunchKernelGGL(k_lw_step, dim3((unsigned)n), dim3(64), 0, q, A);
+        LABS_LAUNCHED("k_lw_step");
+        return LABS_OK;
+    };
+    // The launch pattern repeats with period F (network mode) or 1; a block of
+    // `period` steps is recorded once into a graph and replayed.
+    const int period = mlp ? F : 64;
+    const int reps = c.steps / period;
+    int t = 1;
+    if (reps >= 2) {
+        std::string key((const char*)&A, sizeof(A));
+        key.append((const char*)&pr, sizeof(pr));
+        key.append((const char*)&B.fwd_ws, sizeof(B.fwd_ws));
+        key.append((const char*)&period, sizeof(period));
+        std::lock_guard<std::mutex> g(g_lw_mu);
+        hipGraphExec_t exec = nullptr;
+        auto it = g_lw_graphs.find(key);
+        if (it != g_lw_graphs.end()) {
+            exec = it->second;
+        } else {
+            hipStream_t cs = capture_stream_lw();
+            if (!cs) return invalid("cannot create the graph capture stream");
+            LABS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            labs_status r = LABS_OK;
+            for (int q = 1; q <= period && r == LABS_OK; ++q) r = enqueue_step(q, cs);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(cs, &graph);
+            if (r != LABS_OK || e != hipSuccess) {
+                if (graph) hipGraphDestroy(graph);
+                return r != LABS_OK ? r : device_error(e, "hipStreamEndCapture");
+            }
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e != hipSuccess) return device_error(e, "hipGraphInstantiate");
+            if (g_lw_graphs.size() >= 32) {
+                // free an old graph only once nothing queued can still use it
+                LABS_HIP(hipDeviceSynchronize());
+                hipGraphExecDestroy(g_lw_graphs.begin()->second);
+                g_lw_graphs.erase(g_lw_graphs.begin());
+            }
+            g_lw_graphs[key] = exec;
+        }
+        for (int q = 0; q < reps; ++q) LABS_HIP(hipGraphLaunch(exec, st));
+        t = reps * period + 1;
+    }
+    for (; t <= c.steps; ++t)
+        if ((s = enqueue_step(t, st))) return s;
+
+    const int64_t tot = n * A.W > n ? n * A.W : n;
+    hipLaunchKernelGGL(k_lw_outputs, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, o.final_seqs,
+                       o.final_E, o.best_seqs, o.best_E, o.best_step, o.hit_step);
+    LABS_LAUNCHED("k_lw_outputs");
+    hipLaunchKernelGGL(k_sum_i64, dim3(1), dim3(256), 0, st, n, A.evals, o.flip_evals);
+    LABS_LAUNCHED("k_sum_i64");
+    return LABS_OK;
+}
+
+}  // namespace labsdev

@@ -66,6 +66,33 @@ class Step2Out(ctypes.Structure):
                 ("open_E", ctypes.c_void_p), ("open_capacity", ctypes.c_int64)]
 
 
+class MlpLayout(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("k", ctypes.c_int32), ("d_in", ctypes.c_int32),
+                ("d_out", ctypes.c_int32), ("hidden", ctypes.c_int32), ("ld_in", ctypes.c_int32),
+                ("ld_out", ctypes.c_int32), ("mask_words", ctypes.c_int32),
+                ("off_W1", ctypes.c_int64), ("off_b1", ctypes.c_int64), ("off_W2", ctypes.c_int64),
+                ("off_b2", ctypes.c_int64), ("off_W3", ctypes.c_int64), ("off_b3", ctypes.c_int64),
+                ("n_params", ctypes.c_int64)]
+
+
+class Proposer(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("top_m", ctypes.c_int32),
+                ("fallback_every", ctypes.c_int32), ("hidden", ctypes.c_int32),
+                ("params", ctypes.c_void_p), ("params_bf16", ctypes.c_void_p),
+                ("seed", ctypes.c_uint64), ("log_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class LearnedOut(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in (
+        "final_seqs", "final_E", "best_seqs", "best_E", "best_step", "hit_step", "traj_E", "moves",
+        "cands", "log_seqs", "log_mask", "log_label", "flip_evals")]
+
+
+PROPOSE_MLP = 0
+PROPOSE_RANDOM = 1
+
+
 def lib():
     """Load liblabs.so (never builds it)."""
     global _lib
@@ -115,6 +142,33 @@ def lib():
             L.labs_timing_read.restype = i32
             L.labs_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(i64)]
+            LP = ctypes.POINTER(MlpLayout)
+            dbl = ctypes.c_double
+            L.labs_mlp_layout_of.restype = i32
+            L.labs_mlp_layout_of.argtypes = [i32, i32, LP]
+            L.labs_mlp_features.restype = i32
+            L.labs_mlp_features.argtypes = [i32, i64, vp, vp, vp]
+            for name in ("labs_mlp_forward_workspace", "labs_mlp_grads_workspace",
+                         "labs_mlp_train_workspace"):
+                getattr(L, name).restype = i32
+                getattr(L, name).argtypes = [LP, i64, ctypes.POINTER(sz)]
+            L.labs_mlp_forward.restype = i32
+            L.labs_mlp_forward.argtypes = [LP, vp, vp, i64, vp, vp, vp, sz, vp]
+            L.labs_mlp_grads.restype = i32
+            L.labs_mlp_grads.argtypes = [LP, vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+            L.labs_mlp_adam.restype = i32
+            L.labs_mlp_adam.argtypes = [LP, vp, vp, vp, vp, vp, i32, dbl, dbl, dbl, dbl, vp]
+            L.labs_mlp_cast.restype = i32
+            L.labs_mlp_cast.argtypes = [LP, vp, vp, vp]
+            L.labs_mlp_train_step.restype = i32
+            L.labs_mlp_train_step.argtypes = [LP, vp, vp, vp, vp, vp, i32, dbl, dbl, dbl, dbl, i64,
+                                              vp, vp, vp, vp, vp, sz, vp]
+            L.labs_learned_walk_workspace.restype = i32
+            L.labs_learned_walk_workspace.argtypes = [ctypes.POINTER(Step1Cfg),
+                                                      ctypes.POINTER(Proposer), ctypes.POINTER(sz)]
+            L.labs_learned_walk.restype = i32
+            L.labs_learned_walk.argtypes = [ctypes.POINTER(Step1Cfg), ctypes.POINTER(Proposer),
+                                            ctypes.POINTER(LearnedOut), vp, sz, vp]
             _lib = L
     return _lib
 
@@ -396,3 +450,157 @@ def autotune_get(L: int, p: int):
     wv = ctypes.c_int32(0)
     _check(lib().labs_autotune_get(L, p, ctypes.byref(rb), ctypes.byref(wv)))
     return int(rb.value), int(wv.value)
+
+
+# ---------------------------------------------------------------- learned proposal network
+MLP_KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def mlp_layout(L: int, hidden: int = 256) -> MlpLayout:
+    lay = MlpLayout()
+    _check(lib().labs_mlp_layout_of(L, hidden, ctypes.byref(lay)))
+    return lay
+
+
+def _mlp_slices(lay: MlpLayout):
+    h = lay.hidden
+    return {"W1": (lay.off_W1, (h, lay.ld_in), (h, lay.d_in)),
+            "b1": (lay.off_b1, (h,), (h,)),
+            "W2": (lay.off_W2, (h, h), (h, h)),
+            "b2": (lay.off_b2, (h,), (h,)),
+            "W3": (lay.off_W3, (lay.ld_out, h), (lay.d_out, h)),
+            "b3": (lay.off_b3, (lay.ld_out,), (lay.d_out,))}
+
+
+def mlp_blob_from_dict(lay: MlpLayout, P: dict):
+    """Host-side placement of {W1 [h,d_in], b1, W2 [h,h], b2, W3 [d_out,h], b3} into the
+    FP32 parameter blob (numpy), pads zero."""
+    import numpy as np
+    blob = np.zeros(lay.n_params, np.float32)
+    for key, (off, full, used) in _mlp_slices(lay).items():
+        size = int(np.prod(full))
+        view = blob[off:off + size].reshape(full)
+        view[tuple(slice(0, u) for u in used)] = np.asarray(P[key], np.float32)
+    return blob
+
+
+def mlp_dict_from_blob(lay: MlpLayout, blob):
+    """Inverse of mlp_blob_from_dict (numpy in, numpy out)."""
+    import numpy as np
+    blob = np.asarray(blob)
+    out = {}
+    for key, (off, full, used) in _mlp_slices(lay).items():
+        size = int(np.prod(full))
+        out[key] = blob[off:off + size].reshape(full)[tuple(slice(0, u) for u in used)].copy()
+    return out
+
+
+def mlp_features(L: int, seqs):
+    torch = _torch()
+    s = _dev(seqs, torch.int32, "seqs")
+    lay = mlp_layout(L, 64)
+    n = s.numel() // words(L)
+    X = torch.empty((n, lay.ld_in), dtype=torch.bfloat16, device=s.device)
+    _check(lib().labs_mlp_features(L, n, _ptr(s), _ptr(X), _stream(s.device)))
+    return X
+
+
+def _ws(name, lay, n, device, ws):
+    torch = _torch()
+    b = ctypes.c_size_t(0)
+    _check(getattr(lib(), name)(ctypes.byref(lay), n, ctypes.byref(b)))
+    if ws is None or ws.numel() < b.value:
+        ws = torch.empty(max(1, b.value), dtype=torch.uint8, device=device)
+    return ws
+
+
+def mlp_forward(lay: MlpLayout, params, params_bf16, X, workspace=None):
+    torch = _torch()
+    n = X.shape[0]
+    logits = torch.empty((n, lay.ld_out), dtype=torch.float32, device=X.device)
+    ws = _ws("labs_mlp_forward_workspace", lay, n, X.device, workspace)
+    _check(lib().labs_mlp_forward(ctypes.byref(lay), _ptr(params), _ptr(params_bf16), n, _ptr(X),
+                                  _ptr(logits), _ptr(ws), ws.numel(), _stream(X.device)))
+    return logits
+
+
+def mlp_grads(lay: MlpLayout, params, params_bf16, X, mask, labels, workspace=None):
+    torch = _torch()
+    n = X.shape[0]
+    grads = torch.empty(lay.n_params, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    ws = _ws("labs_mlp_grads_workspace", lay, n, X.device, workspace)
+    _check(lib().labs_mlp_grads(ctypes.byref(lay), _ptr(params), _ptr(params_bf16), n, _ptr(X),
+                                _ptr(mask), _ptr(labels), _ptr(grads), _ptr(loss), _ptr(ws),
+                                ws.numel(), _stream(X.device)))
+    return grads, loss
+
+
+def mlp_adam(lay: MlpLayout, params, params_bf16, grads, m, v, t: int, lr=1e-3, beta1=0.9,
+             beta2=0.999, eps=1e-8):
+    _check(lib().labs_mlp_adam(ctypes.byref(lay), _ptr(params), _ptr(params_bf16), _ptr(grads),
+                               _ptr(m), _ptr(v), t, lr, beta1, beta2, eps, _stream(params.device)))
+
+
+def mlp_cast(lay: MlpLayout, params, params_bf16):
+    _check(lib().labs_mlp_cast(ctypes.byref(lay), _ptr(params), _ptr(params_bf16),
+                               _stream(params.device)))
+
+
+def mlp_train_step(lay: MlpLayout, params, params_bf16, grads, m, v, t: int, seqs, mask, labels,
+                   lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, workspace=None, loss=None):
+    torch = _torch()
+    n = seqs.shape[0]
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=seqs.device)
+    ws = _ws("labs_mlp_train_workspace", lay, n, seqs.device, workspace)
+    _check(lib().labs_mlp_train_step(ctypes.byref(lay), _ptr(params), _ptr(params_bf16), _ptr(grads),
+                                     _ptr(m), _ptr(v), t, lr, beta1, beta2, eps, n, _ptr(seqs),
+                                     _ptr(mask), _ptr(labels), _ptr(loss), _ptr(ws), ws.numel(),
+                                     _stream(seqs.device)))
+    return loss, ws
+
+
+# ---------------------------------------------------------------- walk with a proposer
+def learned_walk(L: int, p: int, steps: int, tenure_lo: int, tenure_hi: int, seed: int,
+                 n_walkers: int, mode: int = PROPOSE_MLP, top_m: int = 8, fallback_every: int = 64,
+                 hidden: int = 256, params=None, params_bf16=None, prop_seed: int = 0,
+                 log_every: int = 0, e_max: int = -1, walker_begin: int = 0, want_traj: bool = False,
+                 want_cands: bool = False, device="cuda", workspace=None):
+    """labs_learned_walk; returns a dict of device tensors (and the workspace)."""
+    torch = _torch()
+    dev = torch.device(device)
+    W = words(L)
+    k = (L - 1) // 2
+    steps = steps if steps else 4 * (L + 1)
+    cfg = Step1Cfg(L, p, steps, tenure_lo, tenure_hi, e_max, walker_begin, n_walkers, seed, 0, 0)
+    pr = Proposer(mode, top_m, fallback_every, hidden, _ptr(params).value, _ptr(params_bf16).value,
+                  prop_seed, log_every, 0)
+    b = ctypes.c_size_t(0)
+    _check(lib().labs_learned_walk_workspace(ctypes.byref(cfg), ctypes.byref(pr), ctypes.byref(b)))
+    if workspace is None or workspace.numel() < b.value:
+        workspace = torch.empty(b.value, dtype=torch.uint8, device=dev)
+    i32 = torch.int32
+    r = {"final_seqs": torch.empty((n_walkers, W), dtype=i32, device=dev),
+         "final_E": torch.empty(n_walkers, dtype=i32, device=dev),
+         "best_seqs": torch.empty((n_walkers, W), dtype=i32, device=dev),
+         "best_E": torch.empty(n_walkers, dtype=i32, device=dev),
+         "best_step": torch.empty(n_walkers, dtype=i32, device=dev),
+         "hit_step": torch.empty(n_walkers, dtype=i32, device=dev),
+         "flip_evals": torch.zeros(1, dtype=torch.int64, device=dev)}
+    if want_traj:
+        r["traj_E"] = torch.empty((n_walkers, steps), dtype=i32, device=dev)
+        r["moves"] = torch.empty((n_walkers, steps), dtype=i32, device=dev)
+    if want_cands:
+        r["cands"] = torch.empty((n_walkers, steps, top_m), dtype=torch.int16, device=dev)
+    n_log = steps // log_every if log_every > 0 else 0
+    if n_log:
+        mw = (k + 1 + 31) // 32
+        r["log_seqs"] = torch.empty((n_walkers * n_log, W), dtype=i32, device=dev)
+        r["log_mask"] = torch.empty((n_walkers * n_log, mw), dtype=i32, device=dev)
+        r["log_label"] = torch.empty(n_walkers * n_log, dtype=i32, device=dev)
+    out = LearnedOut(*[_ptr(r.get(name)).value for name, _ in LearnedOut._fields_])
+    _check(lib().labs_learned_walk(ctypes.byref(cfg), ctypes.byref(pr), ctypes.byref(out),
+                                   _ptr(workspace), workspace.numel(), _stream(dev)))
+    r["workspace"] = workspace
+    return r

@@ -45,3 +45,26 @@ def test_invalid_arguments_are_rejected_without_a_gpu():
     assert lib.labs_energy(37, 5, None, None, None, None) == -1
     lib.labs_last_error.restype = ctypes.c_char_p
     assert b"NULL" in lib.labs_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_mlp_layout_host_call():
+    """labs_mlp_layout_of is host-only: the L = 501 network of 751 -> 256 -> 256 -> 251
+    has 322,811 parameters, and the blob round-trips through the binding's placement."""
+    import numpy as np
+    from paper_2409_07222_amd import labs
+    lay = labs.mlp_layout(501, 256)
+    assert (lay.d_in, lay.d_out, lay.ld_in, lay.ld_out, lay.mask_words) == (751, 251, 768, 256, 8)
+    used = lay.hidden * lay.d_in + lay.hidden + lay.hidden ** 2 + lay.hidden + \
+        lay.d_out * lay.hidden + lay.d_out
+    assert used == 322811
+    offs = [lay.off_W1, lay.off_b1, lay.off_W2, lay.off_b2, lay.off_W3, lay.off_b3, lay.n_params]
+    assert offs == sorted(offs) and all(o % 64 == 0 for o in offs)
+    import labs_inputs as li
+    P = li.mlp_init(55, lay.d_in, 256, lay.d_out)
+    back = labs.mlp_dict_from_blob(lay, labs.mlp_blob_from_dict(lay, P))
+    assert all(np.array_equal(back[k], P[k]) for k in P)
+    with pytest.raises(labs.LabsError):
+        labs.mlp_layout(500, 256)
+    with pytest.raises(labs.LabsError):
+        labs.mlp_layout(501, 100)

@@ -1,0 +1,153 @@
+"""GPU parity of the walk with a proposer (labs_learned_walk) through the C ABI:
+full-scan and covering configurations equal the plain walker; the random
+proposer's whole trajectory equals the CPU reference; with the network, every
+step's move and energy are replayed exactly by the oracle on the logged
+candidate sets, and each set is the top-m of the CPU reference logits up to the
+logit tolerance; the training log holds the plain walker's states and moves."""
+import numpy as np
+import pytest
+
+import labs_inputs as li
+from oracle import learned as ol
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_07222_amd import labs
+    labs.lib()
+    return labs
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _net(lb, L, hidden, seed):
+    import torch
+    lay = lb.mlp_layout(L, hidden)
+    P = li.mlp_init(seed, lay.d_in, hidden, lay.d_out)
+    blob = torch.from_numpy(lb.mlp_blob_from_dict(lay, P)).cuda()
+    pb = torch.empty(lay.n_params, dtype=torch.bfloat16, device="cuda")
+    lb.mlp_cast(lay, blob, pb)
+    return lay, P, blob, pb
+
+
+@pytest.mark.parametrize("L,p,lo,hi,steps", [(37, 0, 3, 6, 300), (101, 8, 10, 20, 257)])
+def test_full_scan_every_step_equals_plain_walker(lb, orc, L, p, lo, hi, steps):
+    n = 96
+    plain = lb.walk_step1(L, p, steps, lo, hi, 21, n, want_traj=True)
+    r = lb.learned_walk(L, p, steps, lo, hi, 21, n, mode=lb.PROPOSE_RANDOM, top_m=4,
+                        fallback_every=1, want_traj=True)
+    assert np.array_equal(_np(r["traj_E"]), _np(plain.traj_E))
+    assert np.array_equal(_np(r["final_seqs"]), _np(plain.final_seqs))
+    assert np.array_equal(_np(r["best_E"]), _np(plain.best_E))
+    assert np.array_equal(_np(r["best_step"]), _np(plain.best_step))
+    # the plain walker counts every free position per step; this walk evaluates
+    # only the admissible ones: nf - min(t-1, tenure) at step t (the last `tenure`
+    # moved positions are distinct and still tabu)
+    nf = (L - 1) // 2 + 1 - p
+    want = 0
+    for w in range(n):
+        ten = orc.walker_init(21, L, p, w, lo, hi)[1]
+        want += sum(nf - min(t - 1, ten) for t in range(1, steps + 1))
+    assert int(r["flip_evals"].item()) == want
+    assert int(plain.flip_evals.item()) == n * steps * nf
+
+
+def test_covering_top_m_equals_plain_walker_with_network(lb):
+    L, p, lo, hi, steps, n = 101, 8, 10, 20, 200, 64
+    lay, P, blob, pb = _net(lb, L, 64, 55)
+    plain = lb.walk_step1(L, p, steps, lo, hi, 5, n, want_traj=True)
+    r = lb.learned_walk(L, p, steps, lo, hi, 5, n, mode=lb.PROPOSE_MLP, top_m=64,
+                        fallback_every=8, hidden=64, params=blob, params_bf16=pb, want_traj=True)
+    assert np.array_equal(_np(r["traj_E"]), _np(plain.traj_E))
+
+
+@pytest.mark.parametrize("L,p,m,F,steps", [(37, 0, 3, 5, 200), (101, 8, 8, 16, 300)])
+def test_random_proposer_matches_oracle(lb, orc, L, p, m, F, steps):
+    lo, hi, seed, ps, n = L // 10, L // 5, 17, 99, 24
+    e_max = orc.e_max_for_tau(L, 4)
+    r = lb.learned_walk(L, p, steps, lo, hi, seed, n, mode=lb.PROPOSE_RANDOM, top_m=m,
+                        fallback_every=F, prop_seed=ps, e_max=e_max, want_traj=True,
+                        want_cands=True)
+    traj, moves, cands = _np(r["traj_E"]), _np(r["moves"]), _np(r["cands"])
+    hit, bestE = _np(r["hit_step"]), _np(r["best_E"])
+    for w in (0, 7, n - 1):
+        ref = ol.proposal_walk(L, p, steps, lo, hi, seed, w, F, ol.random_proposer(ps, L, w, m),
+                               e_max=e_max)
+        assert np.array_equal(traj[w], np.array(ref["traj"])), w
+        assert np.array_equal(moves[w], np.array(ref["moves"])), w
+        for t, c in enumerate(ref["cands"]):
+            got = [int(x) for x in cands[w, t] if x >= 0]
+            assert got == (c if c is not None else []), (w, t)
+        assert hit[w] == ref["hit_step"] and bestE[w] == ref["best_E"]
+    assert int(r["flip_evals"].item()) > 0
+
+
+def test_network_proposer_replay(lb, orc):
+    """Each move is the exact best of its logged set (definitional energies), and
+    each set holds the top-m admissible positions by the CPU reference logits up
+    to the 1e-2 logit tolerance."""
+    L, p, m, F, steps, n, hidden = 101, 8, 8, 16, 96, 8, 64
+    lo, hi, seed = 10, 20, 23
+    lay, P, blob, pb = _net(lb, L, hidden, 56)
+    r = lb.learned_walk(L, p, steps, lo, hi, seed, n, mode=lb.PROPOSE_MLP, top_m=m,
+                        fallback_every=F, hidden=hidden, params=blob, params_bf16=pb,
+                        want_traj=True, want_cands=True)
+    traj, moves, cands = _np(r["traj_E"]), _np(r["moves"]), _np(r["cands"])
+    for w in range(0, n, 3):
+        logged = {}
+
+        def propose(t, s, adm, w=w):
+            c = [int(x) for x in cands[w, t - 1] if x >= 0]
+            C = orc.energy(s, with_c=True)[1][1::2]
+            z, _ = omlp.forward(P, omlp.features(s[None, :], C[None, :]), exact=False)
+            z = z[0]
+            tol = 1e-2 * max(1.0, np.abs(z).max())
+            assert len(c) == min(m, len(adm)) and set(c) <= set(adm)
+            rest = [a for a in adm if a not in c]
+            if rest:
+                assert min(z[a - 1] for a in c) >= max(z[a - 1] for a in rest) - 2 * tol
+            logged[t] = c
+            return c
+
+        ref = ol.proposal_walk(L, p, steps, lo, hi, seed, w, F, propose)
+        assert np.array_equal(traj[w], np.array(ref["traj"])), w
+        assert np.array_equal(moves[w], np.array(ref["moves"])), w
+        assert len(logged) == steps - (steps + F - 1) // F
+
+
+def test_training_log_is_plain_walker_data(lb, orc):
+    L, p, lo, hi, steps, n, every = 37, 2, 3, 6, 60, 16, 4
+    r = lb.learned_walk(L, p, steps, lo, hi, 8, n, mode=lb.PROPOSE_RANDOM, top_m=1,
+                        fallback_every=1, log_every=every, want_traj=True)
+    seqs, mask, label = _np(r["log_seqs"]), _np(r["log_mask"]), _np(r["log_label"])
+    n_log = steps // every
+    for w in (0, 9):
+        ref = ol.proposal_walk(L, p, steps, lo, hi, 8, w, 1, None)
+        for q in range(n_log):
+            t = (q + 1) * every
+            rec = q * n + w
+            st = li.unpack(seqs[rec:rec + 1].view(np.uint32), L)[0]
+            assert np.array_equal(st, ref["states"][t - 1])
+            adm = [a for a in range(1, (L - 1) // 2 + 2)
+                   if (int(mask[rec, (a - 1) // 32]) >> ((a - 1) % 32)) & 1]
+            assert adm == ref["admissible"][t - 1]
+            assert label[rec] == ref["moves"][t - 1] - 1
+
+
+def test_repeat_call_reuses_graph_identically(lb):
+    L, p, lo, hi, steps, n = 101, 8, 10, 20, 200, 32
+    lay, P, blob, pb = _net(lb, L, 64, 57)
+    a = lb.learned_walk(L, p, steps, lo, hi, 3, n, mode=lb.PROPOSE_MLP, top_m=8,
+                        fallback_every=16, hidden=64, params=blob, params_bf16=pb, want_traj=True)
+    b = lb.learned_walk(L, p, steps, lo, hi, 3, n, mode=lb.PROPOSE_MLP, top_m=8,
+                        fallback_every=16, hidden=64, params=blob, params_bf16=pb, want_traj=True,
+                        workspace=a["workspace"])
+    assert np.array_equal(_np(a["traj_E"]), _np(b["traj_E"]))
