@@ -47,6 +47,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline-pass", action="store_true")
+    ap.add_argument("--no-ab", action="store_true",
+                    help="skip the learned-vs-plain comparison at equal wall budgets")
+    ap.add_argument("--ab-budget", type=float, default=8.0, help="seconds of walking per arm")
+    ap.add_argument("--ab-pairs", type=int, default=10_000_000, help="logged training pairs")
+    ap.add_argument("--ab-log-steps", type=int, default=4880, help="plain-walker steps logged")
+    ap.add_argument("--ab-epochs", type=float, default=1.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference "
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -104,6 +110,119 @@ def cpu_baseline(budget_s: float):
     return {"value": steps * nf / dt, "unit": "flip-evals/s", "cores": 1, "kind": "oracle",
             "sample": "1 walker x %d steps of the L=501 p=16 first-step walk (%d flip-evals, "
                       "%.1f s), definitional energy per neighbour" % (steps, steps * nf, dt)}
+
+
+def learned_ab(a, labs, dev):
+    """Learned proposal against the plain walker at equal wall budgets (L = 501,
+    p = 16, the bench's walker count): log plain-walker pairs (seed 5), train the
+    network (init seed 55, Adam lr 1e-3, batch 4096), fix tau* from a plain run of
+    half the budget (seed 999, best F rounded down to 0.05), then run each arm for
+    the budget from seed 1001: the plain walker, the trained network (top-8, a
+    full scan every 64 steps), the untrained network and a random top-8.  The
+    time to reach F >= tau* is the first hit step over all walkers times the arm's
+    measured time per step (walkers advance in lockstep)."""
+    import numpy as np
+    import torch
+    import labs_inputs as li
+    from paper_2409_07222_amd import learn
+    lo, hi = L // 10, L // 5
+    n = a.walkers
+    sync = torch.cuda.synchronize
+    res = {"L": L, "p": P, "walkers": n, "top_m": 8, "fallback_every": 64, "hidden": 256,
+           "budget_s": a.ab_budget}
+    # training data and held-out states
+    log_every = max(1, (n * a.ab_log_steps) // max(1, a.ab_pairs))
+    sync()
+    t0 = time.perf_counter()
+    seqs, mask, lab = learn.log_plain(L, P, a.ab_log_steps, lo, hi, 5, n, log_every, device=dev)
+    sync()
+    res["log"] = {"pairs": int(seqs.shape[0]), "steps": a.ab_log_steps, "log_every": log_every,
+                  "seconds": time.perf_counter() - t0}
+    hs, hm, hl = learn.log_plain(L, P, 2000, lo, hi, 6, 1024, 100, device=dev)
+    lay = labs.mlp_layout(L, 256)
+    net = learn.Network(L, li.mlp_init(55, lay.d_in, 256, lay.d_out), 256, device=dev)
+    untrained = net.clone()
+    sync()
+    t0 = time.perf_counter()
+    hist = learn.train(net, seqs, mask, lab, batch=4096, epochs=a.ab_epochs, lr=1e-3)
+    sync()
+    t_train = time.perf_counter() - t0
+    res["train"] = {"steps": net.t, "seconds": t_train, "loss_first": hist[0][1],
+                    "loss_last": hist[-1][1],
+                    "samples_per_s": net.t * 4096 / t_train,
+                    "tflops": net.t * 4096 * 3 * 644096 / t_train / 1e12}
+    del seqs, mask, lab
+    # recall of the logged move among the top-8 admissible scores, held-out states
+    mk = hm.cpu().numpy().view(np.uint32)
+    adm = np.zeros((mk.shape[0], lay.d_out), bool)
+    for j in range(lay.d_out):
+        adm[:, j] = (mk[:, j // 32] >> np.uint32(j % 32)) & 1
+    labels = hl.cpu().numpy()
+
+    def recall(z):
+        z = np.where(adm, z[:, :lay.d_out], -np.inf)
+        top = np.argsort(-z, axis=1, kind="stable")[:, :8]
+        return float(np.mean([labels[i] in top[i] for i in range(len(labels))]))
+    res["recall_at_8"] = {"trained": recall(net.logits(hs).cpu().numpy()),
+                          "untrained": recall(untrained.logits(hs).cpu().numpy()),
+                          "random": recall(np.random.default_rng(0).random(adm.shape))}
+
+    def plain_run(steps, seed, e_max):
+        pool = labs.PoolBuffers.empty(L, 1 << 20, device=dev)
+        sync()
+        t0 = time.perf_counter()
+        r = labs.walk_step1(L, P, steps, lo, hi, seed, n, e_max=e_max, pool=pool, device=dev)
+        sync()
+        dt = time.perf_counter() - t0
+        c = int(pool.count.item())
+        hit = int(pool.step[:c].min().item()) if c else None
+        return {"seconds": dt, "steps": steps, "best_E": int(r.best_E.min().item()), "hit_step": hit,
+                "flip_evals": int(r.flip_evals.item()), "pool_dropped": int(pool.dropped.item())}
+
+    def learned_run(steps, seed, e_max, kw):
+        sync()
+        t0 = time.perf_counter()
+        r = labs.learned_walk(L, P, steps, lo, hi, seed, n, top_m=8, fallback_every=64, e_max=e_max,
+                              device=dev, **kw)
+        sync()
+        dt = time.perf_counter() - t0
+        h = r["hit_step"]
+        h = h[h >= 0]
+        return {"seconds": dt, "steps": steps, "best_E": int(r["best_E"].min().item()),
+                "hit_step": int(h.min().item()) if h.numel() else None,
+                "flip_evals": int(r["flip_evals"].item())}
+
+    arms = {"learned": net.proposer_args(), "untrained": untrained.proposer_args(),
+            "random_top8": dict(mode=labs.PROPOSE_RANDOM, prop_seed=7)}
+    # time per step of each arm from short probes (graph capture included in a warm call)
+    plain_run(64, 11, -1)
+    pr = plain_run(2048, 12, -1)
+    rate = {"plain": pr["steps"] / pr["seconds"]}
+    for name, kw in arms.items():
+        learned_run(128, 11, -1, kw)
+        q = learned_run(1024, 12, -1, kw)
+        rate[name] = q["steps"] / q["seconds"]
+    # tau* from a plain run of half the budget
+    cal = plain_run(max(64, int(rate["plain"] * a.ab_budget / 2)), 999, -1)
+    tau = np.floor(L * L / (2.0 * cal["best_E"]) / 0.05) * 0.05
+    e_max = int(np.floor(L * L / (2.0 * tau)))
+    res["tau_star"] = float(round(tau, 2))
+    res["e_max"] = e_max
+    out = {}
+    steps = max(64, int(rate["plain"] * a.ab_budget))
+    out["plain"] = plain_run(steps, 1001, e_max)
+    for name, kw in arms.items():
+        steps = max(64, int(rate[name] * a.ab_budget))
+        steps -= steps % 64
+        out[name] = learned_run(steps, 1001, e_max, kw)
+    for name, o in out.items():
+        o["best_F"] = L * L / (2.0 * o["best_E"])
+        o["time_to_tau_s"] = (o["hit_step"] / o["steps"] * o["seconds"]
+                              if o["hit_step"] is not None else None)
+        o["walker_steps_per_s"] = n * o["steps"] / o["seconds"]
+        o["flip_evals_per_s"] = o["flip_evals"] / o["seconds"]
+    res["arms"] = out
+    return res
 
 
 def main():
@@ -206,6 +325,11 @@ def main():
                                     "ops_per_neighbour_eval": W2_OPS,
                                     "kernel_share_of_pass": ms2 / 1e3 / t_pass}
 
+    ab = None
+    if not a.no_ab:
+        s2_ws = None
+        torch.cuda.empty_cache()
+        ab = learned_ab(a, labs, dev)
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.cpu_seconds)
     value = evals / dt
     line = {
@@ -226,7 +350,9 @@ def main():
         "best_F": (L * L / (2.0 * best_E)) if best_E else None,
         "best_F_step1": (L * L / (2.0 * best1_E)) if best1_E else None,
         "step1_flip_evals_per_s": evals1 / dt, "step2_neighbour_evals_per_s": evals2 / dt,
-        "time_to_tau_s": None,
+        "time_to_tau_s": ({k: v["time_to_tau_s"] for k, v in ab["arms"].items()} if ab else None),
+        "tau_star": ab["tau_star"] if ab else None,
+        "learned_ab": ab,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

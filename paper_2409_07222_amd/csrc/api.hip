@@ -464,6 +464,8 @@ static labs_status check_step2_cfg(const labs_step2_cfg& c, int64_t n_cand) {
         return invalid("max_expansions must be in [0, 2^30]");
     if (c.T_u < 1) return invalid("T_u must be >= 1");
     if (n_cand < 1 || n_cand > (int64_t)1 << 28) return invalid("n_cand must be in [1, 2^28]");
+    if (!step2_fits(c, n_cand))
+        return invalid("max_expansions + pq_capacity + batch*L too large: the hash set would exceed 2^31 slots");
     return LABS_OK;
 }
 

@@ -126,6 +126,7 @@ struct WalkArgs {
 };
 bool walk_shape_supported(int L, int p);
 size_t step2_workspace_bytes(const labs_step2_cfg& c, long long n_cand);
+bool step2_fits(const labs_step2_cfg& c, long long n_cand);   // hash-set slots fit int32 indices
 labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_t* cand_seqs,
                       const labs_step2_out& out, void* ws, size_t ws_bytes, hipStream_t st,
                       labs_status (*tb)(void*, hipStream_t), labs_status (*te)(void*, hipStream_t),

@@ -154,6 +154,112 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
         }
 }
 
+// Forward products (both operands K-contiguous) on 128x128x32 tiles: each of
+// the four waves owns a 64x64 quarter as 4x4 MFMA blocks; LDS is double
+// buffered and the next K slice is fetched into registers while the current
+// one is multiplied, so one barrier per K step suffices.
+constexpr int BT = 128;
+
+__device__ __forceinline__ void fetch_rows(uint4 (&r)[2], const uint16_t* __restrict__ P, int64_t ld, int rows,
+                                           int K, int r0, int k0) {
+    const int t = threadIdx.x;
+    for (int h = 0; h < 2; ++h) {
+        const int rr = (t >> 2) + 64 * h, kc = (t & 3) * 8;
+        const int gr = r0 + rr, gk = k0 + kc;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gr < rows) {
+            const uint16_t* src = P + (int64_t)gr * ld + gk;
+            if (gk + 8 <= K) {
+                v = *(const uint4*)src;
+            } else {
+                uint16_t e[8];
+                for (int j = 0; j < 8; ++j) e[j] = (gk + j < K) ? src[j] : (uint16_t)0;
+                v.x = e[0] | ((uint32_t)e[1] << 16);
+                v.y = e[2] | ((uint32_t)e[3] << 16);
+                v.z = e[4] | ((uint32_t)e[5] << 16);
+                v.w = e[6] | ((uint32_t)e[7] << 16);
+            }
+        }
+        r[h] = v;
+    }
+}
+
+__device__ __forceinline__ void put_rows(uint16_t (*S)[GK + GPAD], const uint4 (&r)[2]) {
+    const int t = threadIdx.x;
+    for (int h = 0; h < 2; ++h) *(uint4*)&S[(t >> 2) + 64 * h][(t & 3) * 8] = r[h];
+}
+
+__device__ __forceinline__ void epilogue(const Epi& epi, int m, int n, float v) {
+    switch (epi.kind) {
+        case EPI_F32: epi.out_f[(int64_t)m * epi.ldf + n] = v; break;
+        case EPI_BIAS_F32: epi.out_f[(int64_t)m * epi.ldf + n] = v + epi.bias[n]; break;
+        case EPI_BIAS_GELU: {
+            const float a = v + epi.bias[n];
+            if (epi.pre) epi.pre[(int64_t)m * epi.ldp + n] = a;
+            epi.out_b[(int64_t)m * epi.ldb + n] = f2bf(gelu_f(a));
+            break;
+        }
+        default: {
+            const float d = v * gelu_grad_f(epi.pre[(int64_t)m * epi.ldp + n]);
+            epi.out_f[(int64_t)m * epi.ldf + n] = d;
+            epi.out_b[(int64_t)m * epi.ldb + n] = f2bf(d);
+            break;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_nt128(int M, int N, int K, const uint16_t* __restrict__ A,
+                                                    int64_t lda, const uint16_t* __restrict__ B, int64_t ldb,
+                                                    Epi epi) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][BT][GK + GPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BT][GK + GPAD];
+    const int m0 = blockIdx.y * BT, n0 = blockIdx.x * BT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+
+    f32x4 acc[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    uint4 ra[2], rb[2];
+    fetch_rows(ra, A, lda, M, K, m0, 0);
+    fetch_rows(rb, B, ldb, N, K, n0, 0);
+    put_rows(As[0], ra);
+    put_rows(Bs[0], rb);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < K; k0 += GK) {
+        const bool more = k0 + GK < K;
+        if (more) {
+            fetch_rows(ra, A, lda, M, K, m0, k0 + GK);
+            fetch_rows(rb, B, ldb, N, K, n0, k0 + GK);
+        }
+        bf16x8 a[4], b[4];
+        for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8*)&As[cur][wm + 16 * i + fr][fk];
+        for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8*)&Bs[cur][wn + 16 * j + fr][fk];
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (more) {
+            put_rows(As[cur ^ 1], ra);
+            put_rows(Bs[cur ^ 1], rb);
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            const int n = n0 + wn + 16 * j + fr;
+            if (n >= N) continue;
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * i + (lane >> 4) * 4 + r;
+                if (m < M) epilogue(epi, m, n, acc[i][j][r]);
+            }
+        }
+}
+
 static bool al16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 labs_status gemm(bool a_k, bool b_k, int M, int N, int K, const uint16_t* A, int64_t lda,
@@ -161,6 +267,12 @@ labs_status gemm(bool a_k, bool b_k, int M, int N, int K, const uint16_t* A, int
     if (M <= 0 || N <= 0) return LABS_OK;
     if ((lda & 7) || (ldb & 7) || !al16(A) || !al16(B))
         return invalid("internal: GEMM operands must be 16-byte aligned with strides of 8 elements");
+    if (a_k && b_k && M >= 4 * BT) {
+        dim3 g2((N + BT - 1) / BT, (M + BT - 1) / BT);
+        hipLaunchKernelGGL(k_gemm_nt128, g2, dim3(256), 0, st, M, N, K, A, lda, B, ldb, epi);
+        LABS_LAUNCHED("k_gemm_nt128");
+        return LABS_OK;
+    }
     dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
     if (a_k && b_k)
         hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, epi);

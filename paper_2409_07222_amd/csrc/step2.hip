@@ -91,6 +91,7 @@ struct Params {
     Ctl* ctl;
     int32_t* oE[2];
     int32_t* oS[2];
+    unsigned long long* oZ[2];   // Zobrist key of each Open entry (tie order without table reads)
     uint32_t* flag;        // [cap_o]
     int32_t* cand[2];      // [cap_o] each
     int32_t* piv;          // [B]
@@ -177,13 +178,15 @@ __device__ int claim_or_pend(const Params& P, unsigned long long key, int src, i
     return INS_NONE;
 }
 
-__device__ __forceinline__ void push_open(const Params& P, bool take, int32_t E, int slot) {
+__device__ __forceinline__ void push_open(const Params& P, bool take, int32_t E, int slot,
+                                          unsigned long long key) {
     Ctl* c = P.ctl;
     const long long o = block_append(&c->n_tot, take);
     if (take && o >= P.cap_o) atomicExch(&c->error, 4);
     if (take && o < P.cap_o) {
         P.oE[c->which][o] = E;
         P.oS[c->which][o] = slot;
+        P.oZ[c->which][o] = key;
     }
     atomic_min_batch(c, take, E);
 }
@@ -220,7 +223,7 @@ __global__ __launch_bounds__(64) void k_seed(Params P, long long n_cand) {
     const unsigned long long key = h | 1ull;
     int slot = -1, res = INS_NONE;
     if (lane == 0) res = claim_or_pend(P, key, (int)(-j - 1), 0, e, &slot);
-    push_open(P, res == INS_CLAIMED, e, slot);
+    push_open(P, res == INS_CLAIMED, e, slot, key);
     Pend pd{slot, (int)(-j - 1), 0, e};
     push_pending(P, res == INS_PENDING, pd);
 }
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(512) void k_resolve(Params P) {
                      atomicCAS(&P.H.state[pd.slot], ST_EVICTED, ST_OPEN) == ST_EVICTED)
                 pushed = true;
         }
-        push_open(P, pushed, pd.E, pd.slot);
+        push_open(P, pushed, pd.E, pd.slot, pushed ? P.H.hkey[pd.slot] : 0ull);
         const long long o = block_append(&c->n_slow, coll);
         if (coll && o < P.cap_pend) P.slow[o] = pd;
     }
@@ -274,6 +277,7 @@ __global__ void k_slow(Params P) {
                 if (o < P.cap_o) {
                     P.oE[c->which][o] = pd.E;
                     P.oS[c->which][o] = (int)s;
+                    P.oZ[c->which][o] = key;
                 }
                 if (pd.E < c->batch_minE) c->batch_minE = pd.E;
                 break;
@@ -289,6 +293,7 @@ __global__ void k_slow(Params P) {
                 if (o < P.cap_o) {
                     P.oE[c->which][o] = pd.E;
                     P.oS[c->which][o] = (int)s;
+                    P.oZ[c->which][o] = key;
                 }
                 if (pd.E < c->batch_minE) c->batch_minE = pd.E;
             }
@@ -478,18 +483,20 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
     }
 }
 
-// Tie digits of a slot: bytes 0..7 are the Zobrist key (most significant first),
-// bytes 8.. the packed sequence.
-__device__ __forceinline__ int tie_digit(const Table& H, int slot, int pos) {
-    if (pos < 8) return (int)((H.hkey[slot] >> (56 - 8 * pos)) & 255ull);
+// Tie digits of an Open entry (Zobrist key z, table slot): bytes 0..7 are the
+// key (most significant first), bytes 8.. the packed sequence.
+__device__ __forceinline__ int tie_digit(const Table& H, unsigned long long z, int slot, int pos) {
+    if (pos < 8) return (int)((z >> (56 - 8 * pos)) & 255ull);
     const int q = pos - 8;
     return (int)((H.seq[(size_t)slot * H.W + (q >> 2)] >> (24 - 8 * (q & 3))) & 255u);
 }
 
-// First tie-digit position >= pos at which slots a and b differ (npos if none).
-__device__ __forceinline__ int first_diff(const Table& H, int a, int b, int pos, int npos) {
+// First tie-digit position >= pos at which entries (za, a) and (zb, b) differ
+// (npos if none).
+__device__ __forceinline__ int first_diff(const Table& H, unsigned long long za, int a, unsigned long long zb,
+                                          int b, int pos, int npos) {
     if (pos < 8) {
-        unsigned long long x = H.hkey[a] ^ H.hkey[b];
+        unsigned long long x = za ^ zb;
         x &= ~0ull >> (8 * pos);
         if (x) return __clzll((long long)x) >> 3;
         pos = 8;
@@ -523,10 +530,13 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
     while (pos < npos && r > 0 && r < m) {
         if (t == 0) s_pos = npos;
         __syncthreads();
-        const int ref = P.oS[cur][P.cand[src][0]];
+        const int ref_i = P.cand[src][0];
+        const int ref = P.oS[cur][ref_i];
+        const unsigned long long zref = P.oZ[cur][ref_i];
         int first = npos;
         for (int q = t; q < m; q += blockDim.x) {
-            const int d = first_diff(P.H, P.oS[cur][P.cand[src][q]], ref, pos, npos);
+            const int idx = P.cand[src][q];
+            const int d = first_diff(P.H, P.oZ[cur][idx], P.oS[cur][idx], zref, ref, pos, npos);
             first = d < first ? d : first;
         }
         first = __ockl_wfred_min_i32(first);
@@ -538,7 +548,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         if (t == 0) s_m2 = 0;
         __syncthreads();
         for (int q = t; q < m; q += blockDim.x)
-            atomicAdd(&h[tie_digit(P.H, P.oS[cur][P.cand[src][q]], pos)], 1u);
+            atomicAdd(&h[tie_digit(P.H, P.oZ[cur][P.cand[src][q]], P.oS[cur][P.cand[src][q]], pos)], 1u);
         __syncthreads();
         if (t == 0) {
             long long cum = 0;
@@ -554,7 +564,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         const int v = s_v;
         for (int q = t; q < m; q += blockDim.x) {
             const int idx = P.cand[src][q];
-            const int dgt = tie_digit(P.H, P.oS[cur][idx], pos);
+            const int dgt = tie_digit(P.H, P.oZ[cur][idx], P.oS[cur][idx], pos);
             if (dgt < v) P.flag[idx] = 1;
             else if (dgt == v) P.cand[1 - src][atomicAdd(&s_m2, 1)] = idx;
         }
@@ -620,6 +630,7 @@ __global__ __launch_bounds__(64) void k_expand_direct(Params P) {
         const bool valid = i <= L;
         int slot = -1, res = INS_NONE;
         int32_t En = 0;
+        unsigned long long key = 0;
         if (valid) {
             const int si = sv[kPad + i];
             int g = 0, q = 0;
@@ -629,9 +640,10 @@ __global__ __launch_bounds__(64) void k_expand_direct(Params P) {
                 q += t * t;
             }
             En = Ep - 4 * si * g + 4 * q;
-            res = claim_or_pend(P, (hp ^ zob(i - 1)) | 1ull, ps, i, En, &slot);
+            key = (hp ^ zob(i - 1)) | 1ull;
+            res = claim_or_pend(P, key, ps, i, En, &slot);
         }
-        push_open(P, res == INS_CLAIMED, En, slot);
+        push_open(P, res == INS_CLAIMED, En, slot, key);
         Pend pd{slot, ps, i, En};
         push_pending(P, res == INS_PENDING, pd);
     }
@@ -771,8 +783,9 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
         const int Q = (L - 1) + 2 * (M - 2 * dis);
         const int32_t En = Ep - 4 * si * G + 4 * Q;
         int slot = -1, res = INS_NONE;
-        if (valid) res = claim_or_pend(P, (hp ^ zob(i - 1)) | 1ull, ps, i, En, &slot);
-        push_open(P, res == INS_CLAIMED, En, slot);
+        const unsigned long long key = (hp ^ zob(i - 1)) | 1ull;
+        if (valid) res = claim_or_pend(P, key, ps, i, En, &slot);
+        push_open(P, res == INS_CLAIMED, En, slot, key);
         Pend pd{slot, ps, i, En};
         push_pending(P, res == INS_PENDING, pd);
     }
@@ -868,6 +881,7 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
         if (keep) {
             P.oE[1 - cur][o] = P.oE[cur][i];
             P.oS[1 - cur][o] = P.oS[cur][i];
+            P.oZ[1 - cur][o] = P.oZ[cur][i];
         }
     }
 }
@@ -1011,9 +1025,16 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     lo.cap_o = base + BL + 1024;
     lo.cap_pend = (BL > n_cand ? BL : n_cand) + 1024;
     // live slots never exceed n_cand + X + Q + BL; the table is rebuilt when half
-    // of it is claimed, with kCheck rounds of claims as headroom.
+    // of it is claimed, with kCheck rounds of claims as headroom.  Evicted
+    // sequences keep their slots until a rebuild, and a rebuild costs about one
+    // random insertion per live entry whatever the table size, so the table is
+    // made large (16x the bound: 43 GB for two tables at 10^7 expansions of
+    // L = 501) to make rebuilds rare.
     const long long live = n_cand + c.max_expansions + c.pq_capacity + BL;
-    lo.cap_ht = next_pow2((uint64_t)(4 * (live + (long long)kCheck * BL) + 1024));
+    for (int f = 16; f >= 4; f >>= 1) {   // slots are int32 indices: at most 2^31
+        lo.cap_ht = next_pow2((uint64_t)(f * (live + (long long)kCheck * BL) + 1024));
+        if (lo.cap_ht <= (1ull << 31)) break;
+    }
     size_t t = 0;
     for (int tb = 0; tb < 2; ++tb) {
         t += align_up(sizeof(unsigned long long) * lo.cap_ht, 256);
@@ -1025,6 +1046,7 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     t += align_up(sizeof(Ctl), 256);
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // oE
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // oS
+    t += 2 * align_up(sizeof(unsigned long long) * lo.cap_o, 256);     // oZ
     t += align_up(sizeof(uint32_t) * lo.cap_o, 256);                   // flag
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // cand
     t += align_up(sizeof(int32_t) * c.batch, 256);                     // piv
@@ -1039,6 +1061,10 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
 
 size_t step2_workspace_bytes(const labs_step2_cfg& c, long long n_cand) {
     return s2_layout(c, n_cand).total;
+}
+
+bool step2_fits(const labs_step2_cfg& c, long long n_cand) {
+    return s2_layout(c, n_cand).cap_ht <= (1ull << 31);
 }
 
 // The host loop.  `tb`/`te` bracket every expansion launch (launch timing).
@@ -1076,6 +1102,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.ctl = cv.take<Ctl>(1);
     for (int b = 0; b < 2; ++b) P.oE[b] = cv.take<int32_t>(lo.cap_o);
     for (int b = 0; b < 2; ++b) P.oS[b] = cv.take<int32_t>(lo.cap_o);
+    for (int b = 0; b < 2; ++b) P.oZ[b] = cv.take<unsigned long long>(lo.cap_o);
     P.flag = cv.take<uint32_t>(lo.cap_o);
     for (int b = 0; b < 2; ++b) P.cand[b] = cv.take<int32_t>(lo.cap_o);
     P.piv = cv.take<int32_t>(cfg.batch);

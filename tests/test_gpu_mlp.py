@@ -66,7 +66,7 @@ def test_features_bit_exact(lb, orc, L):
     assert np.all(got[:, lay.d_in:] == 0)
 
 
-@pytest.mark.parametrize("L,hidden,n", [(37, 64, 1), (101, 128, 300), (501, 256, 257)])
+@pytest.mark.parametrize("L,hidden,n", [(37, 64, 1), (101, 128, 300), (501, 256, 257), (501, 256, 1000), (101, 64, 700)])
 def test_forward_logits(lb, orc, L, hidden, n):
     lay, P, blob, pb = _params(lb, L, hidden, 55)
     S = li.random_skew(11 * L, n, L, 0)
