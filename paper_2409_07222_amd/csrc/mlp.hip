@@ -50,19 +50,22 @@ struct Epi {
     const float* bias;   // [N] (EPI_BIAS_*)
     float* pre;          // EPI_BIAS_GELU: pre-activation out (nullable); EPI_DGELU: read
     int64_t ldp;
+    int64_t zstride;     // split-K: FP32 output offset per split
 };
 
 constexpr int GT = 64, GK = 32, GPAD = 8;
 
+// One thread's share of a 64-row x 32-k operand slice (8 bf16 values).
+// K-contiguous operand: row t/4, k chunk 8*(t%4); row-contiguous operand
+// (element (r, k) at k*ld + r): k row t/8, rows 8*(t%8) .. +7.  Reads past
+// `rows` or `K` give zeros.
 template <bool A_K>
-__device__ __forceinline__ void stage_operand(uint16_t (*S)[GK + GPAD], const uint16_t* __restrict__ P,
-                                              int64_t ld, int rows, int K, int r0, int k0) {
+__device__ __forceinline__ uint4 fetch64(const uint16_t* __restrict__ P, int64_t ld, int rows, int K, int r0,
+                                         int k0) {
     const int t = threadIdx.x;
+    uint4 v = make_uint4(0, 0, 0, 0);
     if (A_K) {
-        // 64 rows x 32 k: thread -> row t/4, k chunk 8*(t%4)
-        const int r = t >> 2, kc = (t & 3) * 8;
-        const int gr = r0 + r, gk = k0 + kc;
-        uint4 v = make_uint4(0, 0, 0, 0);
+        const int gr = r0 + (t >> 2), gk = k0 + (t & 3) * 8;
         if (gr < rows) {
             const uint16_t* src = P + (int64_t)gr * ld + gk;
             if (gk + 8 <= K) {
@@ -76,54 +79,92 @@ __device__ __forceinline__ void stage_operand(uint16_t (*S)[GK + GPAD], const ui
                 v.w = e[6] | ((uint32_t)e[7] << 16);
             }
         }
-        *(uint4*)&S[r][kc] = v;
     } else {
-        // 32 k-rows x 64 contiguous rows-of-C: thread -> k row t/8, chunk 8*(t%8)
-        const int kr = t >> 3, rc = (t & 7) * 8;
-        const int gk = k0 + kr, gr = r0 + rc;
-        uint16_t e[8];
+        const int gk = k0 + (t >> 3), gr = r0 + (t & 7) * 8;
         if (gk < K) {
             const uint16_t* src = P + (int64_t)gk * ld + gr;
             if (gr + 8 <= rows) {
-                uint4 v = *(const uint4*)src;
-                e[0] = v.x & 0xFFFF; e[1] = v.x >> 16; e[2] = v.y & 0xFFFF; e[3] = v.y >> 16;
-                e[4] = v.z & 0xFFFF; e[5] = v.z >> 16; e[6] = v.w & 0xFFFF; e[7] = v.w >> 16;
+                v = *(const uint4*)src;
             } else {
+                uint16_t e[8];
                 for (int j = 0; j < 8; ++j) e[j] = (gr + j < rows) ? src[j] : (uint16_t)0;
+                v.x = e[0] | ((uint32_t)e[1] << 16);
+                v.y = e[2] | ((uint32_t)e[3] << 16);
+                v.z = e[4] | ((uint32_t)e[5] << 16);
+                v.w = e[6] | ((uint32_t)e[7] << 16);
             }
-        } else {
-            for (int j = 0; j < 8; ++j) e[j] = 0;
         }
-        for (int j = 0; j < 8; ++j) S[rc + j][kr] = e[j];
+    }
+    return v;
+}
+
+// Stores a fetched share into the [row][k] LDS tile (transposing row-contiguous data).
+template <bool A_K>
+__device__ __forceinline__ void put64(uint16_t (*S)[GK + GPAD], uint4 v) {
+    const int t = threadIdx.x;
+    if (A_K) {
+        *(uint4*)&S[t >> 2][(t & 3) * 8] = v;
+    } else {
+        const int kr = t >> 3, rc = (t & 7) * 8;
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        for (int j = 0; j < 4; ++j) {
+            S[rc + 2 * j][kr] = (uint16_t)(w[j] & 0xFFFF);
+            S[rc + 2 * j + 1][kr] = (uint16_t)(w[j] >> 16);
+        }
     }
 }
 
+__device__ __forceinline__ void epilogue(const Epi& epi, int m, int n, float v);
+
+// 64x64x32 tiles, four waves each owning a 32x32 quarter as 2x2 MFMA blocks;
+// the next K slice is fetched into registers while the current one is
+// multiplied (double-buffered LDS, one barrier per K step).  blockIdx.z selects
+// a K range of `kchunk` for split-K products; the epilogue's FP32 output then
+// advances by epi.zstride per split.
 template <bool A_K, bool B_K>
-__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_t* __restrict__ A,
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, int kchunk, const uint16_t* __restrict__ A,
                                               int64_t lda, const uint16_t* __restrict__ B, int64_t ldb,
                                               Epi epi) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[GT][GK + GPAD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[GT][GK + GPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][GT][GK + GPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][GT][GK + GPAD];
     const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int fr = lane & 15, fk = (lane >> 4) * 8;
+    const int klo = blockIdx.z * kchunk;
+    const int khi = (klo + kchunk < K) ? klo + kchunk : K;
+    if (epi.out_f) epi.out_f += (int64_t)blockIdx.z * epi.zstride;
 
     f32x4 acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < K; k0 += GK) {
-        stage_operand<A_K>(As, A, lda, M, K, m0, k0);
-        stage_operand<B_K>(Bs, B, ldb, N, K, n0, k0);
+    if (klo < khi) {
+        uint4 ra = fetch64<A_K>(A, lda, M, khi, m0, klo);
+        uint4 rb = fetch64<B_K>(B, ldb, N, khi, n0, klo);
+        put64<A_K>(As[0], ra);
+        put64<B_K>(Bs[0], rb);
         __syncthreads();
-        bf16x8 a[2], b[2];
-        for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8*)&As[wm + 16 * i + fr][fk];
-        for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8*)&Bs[wn + 16 * j + fr][fk];
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        __syncthreads();
+        int cur = 0;
+        for (int k0 = klo; k0 < khi; k0 += GK) {
+            const bool more = k0 + GK < khi;
+            if (more) {
+                ra = fetch64<A_K>(A, lda, M, khi, m0, k0 + GK);
+                rb = fetch64<B_K>(B, ldb, N, khi, n0, k0 + GK);
+            }
+            bf16x8 a[2], b[2];
+            for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8*)&As[cur][wm + 16 * i + fr][fk];
+            for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8*)&Bs[cur][wn + 16 * j + fr][fk];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            if (more) {
+                put64<A_K>(As[cur ^ 1], ra);
+                put64<B_K>(Bs[cur ^ 1], rb);
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
     }
 
     for (int i = 0; i < 2; ++i)
@@ -132,26 +173,20 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
             if (n >= N) continue;
             for (int r = 0; r < 4; ++r) {
                 const int m = m0 + wm + 16 * i + (lane >> 4) * 4 + r;
-                if (m >= M) continue;
-                const float v = acc[i][j][r];
-                switch (epi.kind) {
-                    case EPI_F32: epi.out_f[(int64_t)m * epi.ldf + n] = v; break;
-                    case EPI_BIAS_F32: epi.out_f[(int64_t)m * epi.ldf + n] = v + epi.bias[n]; break;
-                    case EPI_BIAS_GELU: {
-                        const float a = v + epi.bias[n];
-                        if (epi.pre) epi.pre[(int64_t)m * epi.ldp + n] = a;
-                        epi.out_b[(int64_t)m * epi.ldb + n] = f2bf(gelu_f(a));
-                        break;
-                    }
-                    default: {
-                        const float d = v * gelu_grad_f(epi.pre[(int64_t)m * epi.ldp + n]);
-                        epi.out_f[(int64_t)m * epi.ldf + n] = d;
-                        epi.out_b[(int64_t)m * epi.ldb + n] = f2bf(d);
-                        break;
-                    }
-                }
+                if (m < M) epilogue(epi, m, n, acc[i][j][r]);
             }
         }
+}
+
+// Sum of `splits` FP32 partial products [splits][M][N] into out (row stride ldo),
+// in split order.
+__global__ __launch_bounds__(256) void k_sum_splits(int M, int N, int splits, const float* __restrict__ part,
+                                                    float* __restrict__ out, int64_t ldo) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)M * N) return;
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + i];
+    out[(i / N) * ldo + (i % N)] = s;
 }
 
 // Forward products (both operands K-contiguous) on 128x128x32 tiles: each of
@@ -163,6 +198,7 @@ constexpr int BT = 128;
 __device__ __forceinline__ void fetch_rows(uint4 (&r)[2], const uint16_t* __restrict__ P, int64_t ld, int rows,
                                            int K, int r0, int k0) {
     const int t = threadIdx.x;
+    #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int rr = (t >> 2) + 64 * h, kc = (t & 3) * 8;
         const int gr = r0 + rr, gk = k0 + kc;
@@ -186,6 +222,7 @@ __device__ __forceinline__ void fetch_rows(uint4 (&r)[2], const uint16_t* __rest
 
 __device__ __forceinline__ void put_rows(uint16_t (*S)[GK + GPAD], const uint4 (&r)[2]) {
     const int t = threadIdx.x;
+    #pragma unroll
     for (int h = 0; h < 2; ++h) *(uint4*)&S[(t >> 2) + 64 * h][(t & 3) * 8] = r[h];
 }
 
@@ -219,7 +256,9 @@ __global__ __launch_bounds__(256) void k_gemm_nt128(int M, int N, int K, const u
     const int fr = lane & 15, fk = (lane >> 4) * 8;
 
     f32x4 acc[4][4];
+    #pragma unroll
     for (int i = 0; i < 4; ++i)
+        #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     uint4 ra[2], rb[2];
@@ -236,9 +275,13 @@ __global__ __launch_bounds__(256) void k_gemm_nt128(int M, int N, int K, const u
             fetch_rows(rb, B, ldb, N, K, n0, k0 + GK);
         }
         bf16x8 a[4], b[4];
+        #pragma unroll
         for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8*)&As[cur][wm + 16 * i + fr][fk];
+        #pragma unroll
         for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8*)&Bs[cur][wn + 16 * j + fr][fk];
+        #pragma unroll
         for (int i = 0; i < 4; ++i)
+            #pragma unroll
             for (int j = 0; j < 4; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         if (more) {
@@ -249,10 +292,14 @@ __global__ __launch_bounds__(256) void k_gemm_nt128(int M, int N, int K, const u
         cur ^= 1;
     }
 
+    #pragma unroll
+
     for (int i = 0; i < 4; ++i)
+        #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int n = n0 + wn + 16 * j + fr;
             if (n >= N) continue;
+            #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int m = m0 + wm + 16 * i + (lane >> 4) * 4 + r;
                 if (m < M) epilogue(epi, m, n, acc[i][j][r]);
@@ -262,27 +309,53 @@ __global__ __launch_bounds__(256) void k_gemm_nt128(int M, int N, int K, const u
 
 static bool al16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
+constexpr int kMaxSplits = 16;
+
+// C = A B with the epilogue `epi`.  128x128 tiles when the grid still holds two
+// workgroups per CU, else 64x64 tiles; plain FP32 products over a long K whose
+// grid is small (weight gradients: K is the batch) are split over K into
+// `split_ws` (kMaxSplits * M * N floats) and summed in split order.
 labs_status gemm(bool a_k, bool b_k, int M, int N, int K, const uint16_t* A, int64_t lda,
-                 const uint16_t* B, int64_t ldb, const Epi& epi, hipStream_t st) {
+                 const uint16_t* B, int64_t ldb, const Epi& epi, hipStream_t st, float* split_ws = nullptr) {
     if (M <= 0 || N <= 0) return LABS_OK;
     if ((lda & 7) || (ldb & 7) || !al16(A) || !al16(B))
         return invalid("internal: GEMM operands must be 16-byte aligned with strides of 8 elements");
-    if (a_k && b_k && M >= 4 * BT) {
+    const long long t128 = (long long)((M + BT - 1) / BT) * ((N + BT - 1) / BT);
+    if (a_k && b_k && t128 >= 512) {
         dim3 g2((N + BT - 1) / BT, (M + BT - 1) / BT);
         hipLaunchKernelGGL(k_gemm_nt128, g2, dim3(256), 0, st, M, N, K, A, lda, B, ldb, epi);
         LABS_LAUNCHED("k_gemm_nt128");
         return LABS_OK;
     }
-    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+    const long long tiles = (long long)((M + GT - 1) / GT) * ((N + GT - 1) / GT);
+    int splits = 1, kchunk = (K + GK - 1) / GK * GK;
+    Epi e = epi;
+    if (epi.kind == EPI_F32 && split_ws && tiles < 512 && K >= 2 * 256) {
+        splits = (int)((512 + tiles - 1) / tiles);
+        if (splits > kMaxSplits) splits = kMaxSplits;
+        if (splits > K / 256) splits = K / 256;
+        kchunk = ((K + splits - 1) / splits + GK - 1) / GK * GK;
+        splits = (K + kchunk - 1) / kchunk;
+        e.out_f = split_ws;
+        e.ldf = N;
+        e.zstride = (int64_t)M * N;
+    }
+    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, splits);
     if (a_k && b_k)
-        hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, epi);
+        hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, M, N, K, kchunk, A, lda, B, ldb, e);
     else if (a_k && !b_k)
-        hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, epi);
+        hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, M, N, K, kchunk, A, lda, B, ldb, e);
     else if (!a_k && !b_k)
-        hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, epi);
+        hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, M, N, K, kchunk, A, lda, B, ldb, e);
     else
-        hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, epi);
+        hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, M, N, K, kchunk, A, lda, B, ldb, e);
     LABS_LAUNCHED("k_gemm");
+    if (splits > 1) {
+        const int64_t total = (int64_t)M * N;
+        hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, M, N, splits,
+                           split_ws, epi.out_f, epi.ldf);
+        LABS_LAUNCHED("k_sum_splits");
+    }
     return LABS_OK;
 }
 
@@ -528,6 +601,7 @@ size_t mlp_grads_ws(const labs_mlp_layout& y, int64_t n) {
     add(H * 4); add(H * 2); add(H * 4); add(H * 2);   // da2_f da2_b da1_f da1_b
     add((size_t)n * 4);                               // row losses
     add((size_t)kColChunks * (y.hidden > y.ld_out ? y.hidden : y.ld_out) * 4);
+    add((size_t)kMaxSplits * y.hidden * (y.ld_in > y.hidden ? y.ld_in : y.hidden) * 4);   // split-K partials
     return b + 256;
 }
 
@@ -558,7 +632,8 @@ labs_status mlp_grads(const labs_mlp_layout& y, const float* P, const uint16_t* 
     uint16_t* d1b = cv.take<uint16_t>(H);
     float* rl = cv.take<float>((size_t)n);
     float* part = cv.take<float>((size_t)kColChunks * (y.hidden > y.ld_out ? y.hidden : y.ld_out));
-    if (!cv.ok() || !part) return LABS_E_NOMEM;
+    float* splitw = cv.take<float>((size_t)kMaxSplits * y.hidden * (y.ld_in > y.hidden ? y.ld_in : y.hidden));
+    if (!cv.ok() || !splitw) return LABS_E_NOMEM;
 
     hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(y.n_params)), dim3(256), 0, st, y.n_params, G, 0.f);
     LABS_LAUNCHED("k_fill_f32");
@@ -588,20 +663,20 @@ labs_status mlp_grads(const labs_mlp_layout& y, const float* P, const uint16_t* 
     // layer 3: dW3 = dz^T h2, db3 = colsum dz, dh2 = dz W3 -> da2 = dh2 * gelu'(a2)
     Epi g{};
     g.kind = EPI_F32; g.out_f = G + y.off_W3; g.ldf = Hd;
-    if ((s = gemm(false, false, y.d_out, Hd, (int)n, dzb, y.ld_out, h2, Hd, g, st))) return s;
+    if ((s = gemm(false, false, y.d_out, Hd, (int)n, dzb, y.ld_out, h2, Hd, g, st, splitw))) return s;
     if ((s = colsum(n, y.d_out, y.ld_out, dzf, part, G + y.off_b3, st))) return s;
     Epi d{};
     d.kind = EPI_DGELU; d.out_f = d2f; d.ldf = Hd; d.out_b = d2b; d.ldb = Hd; d.pre = a2; d.ldp = Hd;
     if ((s = gemm(true, false, (int)n, Hd, y.d_out, dzb, y.ld_out, Pb + y.off_W3, Hd, d, st))) return s;
     // layer 2
     g.out_f = G + y.off_W2; g.ldf = Hd;
-    if ((s = gemm(false, false, Hd, Hd, (int)n, d2b, Hd, h1, Hd, g, st))) return s;
+    if ((s = gemm(false, false, Hd, Hd, (int)n, d2b, Hd, h1, Hd, g, st, splitw))) return s;
     if ((s = colsum(n, Hd, Hd, d2f, part, G + y.off_b2, st))) return s;
     d.out_f = d1f; d.out_b = d1b; d.pre = a1;
     if ((s = gemm(true, false, (int)n, Hd, Hd, d2b, Hd, Pb + y.off_W2, Hd, d, st))) return s;
     // layer 1
     g.out_f = G + y.off_W1; g.ldf = y.ld_in;
-    if ((s = gemm(false, false, Hd, y.d_in, (int)n, d1b, Hd, X, y.ld_in, g, st))) return s;
+    if ((s = gemm(false, false, Hd, y.d_in, (int)n, d1b, Hd, X, y.ld_in, g, st, splitw))) return s;
     return colsum(n, Hd, Hd, d1f, part, G + y.off_b1, st);
 }
 
