@@ -234,8 +234,8 @@ labs_status labs_pool_topk(const labs_pool* pool, int32_t L, int32_t k, uint32_t
  *   - cuts Open to the pq_capacity smallest (evicted sequences are forgotten
  *     and may be pushed again later).
  * Results do not depend on scheduling.  The call synchronises `stream`.
- * Memory: the workspace holds two hash tables of up to 16 x (n_cand +
- * max_expansions + pq_capacity + 9 batch L) slots of 16 + 4W bytes (43 GB at
+ * Memory: the workspace holds two hash tables of next_pow2(4 x (n_cand +
+ * max_expansions + pq_capacity + 9 batch L)) slots of 16 + 4W bytes (10.7 GB at
  * 10^7 expansions of L = 501); configurations whose table would pass 2^31 slots
  * are rejected (LABS_E_INVALID).
  */

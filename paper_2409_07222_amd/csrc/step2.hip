@@ -19,13 +19,22 @@
 //    Zobrist key and the sequence among the entries tied at the threshold energy,
 //    skipping digit positions on which they all agree.
 //
-// Insertion is exact and uses no fences: in phase 1 a candidate walks its probe
-// sequence with 64-bit CAS on the key word; an empty slot is claimed (the claimer
-// writes the sequence with plain stores), a slot already holding its key makes
-// the candidate "pending".  After the kernel boundary, phase 2 compares each
-// pending candidate with the slot's sequence (a duplicate, or a re-push of an
-// evicted sequence); a mismatch is a true 64-bit key collision and goes to
-// phase 3, which finishes those insertions one at a time in a single thread.
+// A round's neighbours do not enter H when they are generated.  The expansion
+// only reads H (no writer runs beside it): a neighbour whose sequence H holds as
+// OPEN or CLOSED is a duplicate; any other neighbour is appended to the Open
+// list as a "new" entry (source pivot, flip position, and the slot of its
+// evicted tombstone if H has one) and entered into a per-round table R keyed by
+// the Zobrist key, which finds the neighbours produced twice in the round.  The
+// capacity cut then runs over old and new entries alike, and only the new
+// entries that survive it are written into H (the tombstone re-opened, or an
+// empty slot claimed by CAS).  Neighbours cut in their own round never touch H,
+// so H holds little more than Closed U Open and rarely needs a rebuild.
+// Insertions into R and the seeding insertions into H are exact and use no
+// fences: a candidate walks its probe sequence with 64-bit CAS on the key word;
+// an empty slot is claimed, a slot already holding its key makes the candidate
+// "pending".  After the kernel boundary the pending candidates are compared with
+// the slot's sequence; a mismatch is a true 64-bit key collision, finished one at
+// a time by a single thread.
 #include "labs_internal.h"
 
 #include <climits>
@@ -75,6 +84,7 @@ struct Ctl {
     // table occupancy (claimed slots, tombstones included) and rebuild scratch
     long long claimed, claimed_new;
     long long out_count;
+    long long n_dup_new;   // new entries found to repeat another new entry of the round
 };
 
 // A pending insertion: the slot whose key matched, the source of the sequence
@@ -100,6 +110,14 @@ struct Params {
     Pend* pend;            // [cap_pend]
     Pend* slow;            // [cap_pend]
     const uint32_t* cands; // seeding input
+    // this round's new Open entries, by position minus batch_begin
+    int32_t* nsrc;         // pivot slot
+    int32_t* nflip;        // flipped position (1-based)
+    int32_t* ntomb;        // slot of the sequence's evicted tombstone, or -1
+    // per-round dedupe table: Zobrist key -> Open position of the first holder
+    unsigned long long* rkey;
+    int32_t* ridx;
+    uint64_t rmask;
 };
 
 __device__ __forceinline__ uint64_t zob(int i) { return sm64_at(ZKEY, (uint64_t)i); }
@@ -152,6 +170,20 @@ __device__ __forceinline__ uint32_t src_word(const Params& P, int src, int flip,
     return x;
 }
 
+// Word w of the sequence of Open entry o (table slot `slot`, or a new entry of
+// this round when slot < 0).
+__device__ __forceinline__ uint32_t entry_word(const Params& P, int slot, long long o, int w) {
+    if (slot >= 0) return P.H.seq[(size_t)slot * P.W + w];
+    const long long j = o - P.ctl->batch_begin;
+    return src_word(P, P.nsrc[j], P.nflip[j], w);
+}
+
+__device__ __forceinline__ bool entries_equal(const Params& P, int sa, long long a, int sb, long long b) {
+    for (int w = 0; w < P.W; ++w)
+        if (entry_word(P, sa, a, w) != entry_word(P, sb, b, w)) return false;
+    return true;
+}
+
 enum { INS_NONE = 0, INS_CLAIMED = 1, INS_PENDING = 2 };
 
 // Phase 1: claim an empty slot or stop at a slot holding the same key.
@@ -196,6 +228,65 @@ __device__ __forceinline__ void push_pending(const Params& P, bool take, const P
     const long long o = block_append(&c->n_pend, take);
     if (take && o >= P.cap_pend) atomicExch(&c->error, 5);
     if (take && o < P.cap_pend) P.pend[o] = pd;
+}
+
+// A generated neighbour (pivot slot ps, flip position, energy En, Zobrist key):
+// dropped when H holds its sequence as OPEN or CLOSED, else appended to the Open
+// list as a new entry and entered into R.  Every thread of the block calls it.
+__device__ void stage_neighbour(const Params& P, bool valid, unsigned long long key, int ps, int flip,
+                                int32_t En) {
+    Ctl* c = P.ctl;
+    int tomb = -1;
+    bool take = false;
+    if (valid) {
+        take = true;
+        const Table& H = P.H;
+        uint64_t s = key & H.mask;
+        for (uint64_t probe = 0; probe <= H.mask; ++probe, s = (s + 1) & H.mask) {
+            const unsigned long long k = H.hkey[s];
+            if (k == 0ull) break;
+            if (k != key) continue;
+            bool eq = true;
+            for (int w = 0; w < H.W; ++w)
+                if (H.seq[s * H.W + w] != src_word(P, ps, flip, w)) {
+                    eq = false;
+                    break;
+                }
+            if (!eq) continue;
+            if (H.state[s] == ST_EVICTED) tomb = (int)s;
+            else take = false;
+            break;
+        }
+    }
+    const long long o = block_append(&c->n_tot, take);
+    if (take && o >= P.cap_o) atomicExch(&c->error, 4);
+    bool pend = false;
+    Pend pd{0, 0, 0, 0};
+    if (take && o < P.cap_o) {
+        const int cur = c->which;
+        P.oE[cur][o] = En;
+        P.oS[cur][o] = -1;
+        P.oZ[cur][o] = key;
+        const long long j = o - c->batch_begin;
+        P.nsrc[j] = ps;
+        P.nflip[j] = flip;
+        P.ntomb[j] = tomb;
+        uint64_t r = key & P.rmask;
+        for (uint64_t probe = 0; probe <= P.rmask; ++probe, r = (r + 1) & P.rmask) {
+            const unsigned long long prev = atomicCAS(&P.rkey[r], 0ull, key);
+            if (prev == 0ull) {
+                P.ridx[r] = (int32_t)o;
+                break;
+            }
+            if (prev == key) {
+                pend = true;
+                pd = Pend{(int32_t)r, (int32_t)o, 0, En};
+                break;
+            }
+        }
+    }
+    atomic_min_batch(c, take, En);
+    push_pending(P, pend, pd);
 }
 
 // ---------------------------------------------------------------- seeding
@@ -302,6 +393,65 @@ __global__ void k_slow(Params P) {
     }
 }
 
+// Pending entries of R: a new entry whose key was already in R repeats that
+// holder's sequence (dropped) or collides with it (finished in k_rslow).
+__global__ __launch_bounds__(512) void k_rresolve(Params P) {
+    Ctl* c = P.ctl;
+    if (c->stop) return;
+    const int cur = c->which;
+    const long long n = c->n_pend < P.cap_pend ? c->n_pend : P.cap_pend;
+    long long dups = 0;
+    for (long long base = (long long)blockIdx.x * blockDim.x; base < n;
+         base += (long long)gridDim.x * blockDim.x) {
+        const long long q = base + threadIdx.x;
+        bool coll = false;
+        Pend pd{0, 0, 0, 0};
+        if (q < n) {
+            pd = P.pend[q];
+            const long long holder = P.ridx[pd.slot];
+            if (entries_equal(P, -1, pd.src, -1, holder)) {
+                P.oE[cur][pd.src] = DEAD;
+                ++dups;
+            } else {
+                coll = true;
+            }
+        }
+        const long long o = block_append(&c->n_slow, coll);
+        if (coll && o < P.cap_pend) P.slow[o] = pd;
+    }
+    if (dups) atomicAdd((unsigned long long*)&c->n_dup_new, (unsigned long long)dups);
+}
+
+// Key collisions in R, one at a time (no concurrency, so plain accesses).
+__global__ void k_rslow(Params P) {
+    Ctl* c = P.ctl;
+    if (c->stop || c->n_slow == 0) return;
+    const int cur = c->which;
+    const long long n = c->n_slow < P.cap_pend ? c->n_slow : P.cap_pend;
+    for (long long q = 0; q < n; ++q) {
+        const Pend pd = P.slow[q];
+        const unsigned long long key = P.rkey[pd.slot];
+        uint64_t r = (pd.slot + 1) & P.rmask;
+        for (uint64_t probe = 0; probe <= P.rmask; ++probe, r = (r + 1) & P.rmask) {
+            if (P.rkey[r] == 0ull) {
+                P.rkey[r] = key;
+                P.ridx[r] = pd.src;
+                break;
+            }
+            if (P.rkey[r] != key) continue;
+            if (!entries_equal(P, -1, pd.src, -1, P.ridx[r])) continue;
+            P.oE[cur][pd.src] = DEAD;
+            c->n_dup_new += 1;
+            break;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_clear_u64(unsigned long long* p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
 // ---------------------------------------------------------------- round control
 __global__ void k_round_begin(Params P) {
     Ctl* c = P.ctl;
@@ -318,6 +468,7 @@ __global__ void k_round_begin(Params P) {
     c->n_piv = 0;
     c->n_pend = 0;
     c->n_slow = 0;
+    c->n_dup_new = 0;
     c->batch_begin = c->n_tot;
     c->batch_minE = INT32_MAX;
     c->improved = 0;
@@ -483,27 +634,26 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
     }
 }
 
-// Tie digits of an Open entry (Zobrist key z, table slot): bytes 0..7 are the
-// key (most significant first), bytes 8.. the packed sequence.
-__device__ __forceinline__ int tie_digit(const Table& H, unsigned long long z, int slot, int pos) {
-    if (pos < 8) return (int)((z >> (56 - 8 * pos)) & 255ull);
+// Tie digits of Open entry o: bytes 0..7 are its Zobrist key (most significant
+// first), bytes 8.. its packed sequence.
+__device__ __forceinline__ int tie_digit(const Params& P, int cur, long long o, int pos) {
+    if (pos < 8) return (int)((P.oZ[cur][o] >> (56 - 8 * pos)) & 255ull);
     const int q = pos - 8;
-    return (int)((H.seq[(size_t)slot * H.W + (q >> 2)] >> (24 - 8 * (q & 3))) & 255u);
+    return (int)((entry_word(P, P.oS[cur][o], o, q >> 2) >> (24 - 8 * (q & 3))) & 255u);
 }
 
-// First tie-digit position >= pos at which entries (za, a) and (zb, b) differ
-// (npos if none).
-__device__ __forceinline__ int first_diff(const Table& H, unsigned long long za, int a, unsigned long long zb,
-                                          int b, int pos, int npos) {
+// First tie-digit position >= pos at which Open entries a and b differ (npos if none).
+__device__ __forceinline__ int first_diff(const Params& P, int cur, long long a, long long b, int pos, int npos) {
     if (pos < 8) {
-        unsigned long long x = za ^ zb;
+        unsigned long long x = P.oZ[cur][a] ^ P.oZ[cur][b];
         x &= ~0ull >> (8 * pos);
         if (x) return __clzll((long long)x) >> 3;
         pos = 8;
     }
     const int q0 = pos - 8;
-    for (int w = q0 >> 2; w < H.W; ++w) {
-        uint32_t x = H.seq[(size_t)a * H.W + w] ^ H.seq[(size_t)b * H.W + w];
+    const int sa = P.oS[cur][a], sb = P.oS[cur][b];
+    for (int w = q0 >> 2; w < P.W; ++w) {
+        uint32_t x = entry_word(P, sa, a, w) ^ entry_word(P, sb, b, w);
         if (w == (q0 >> 2)) x &= 0xffffffffu >> (8 * (q0 & 3));
         if (x) return 8 + 4 * w + (__clz((int)x) >> 3);
     }
@@ -531,12 +681,9 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         if (t == 0) s_pos = npos;
         __syncthreads();
         const int ref_i = P.cand[src][0];
-        const int ref = P.oS[cur][ref_i];
-        const unsigned long long zref = P.oZ[cur][ref_i];
         int first = npos;
         for (int q = t; q < m; q += blockDim.x) {
-            const int idx = P.cand[src][q];
-            const int d = first_diff(P.H, P.oZ[cur][idx], P.oS[cur][idx], zref, ref, pos, npos);
+            const int d = first_diff(P, cur, P.cand[src][q], ref_i, pos, npos);
             first = d < first ? d : first;
         }
         first = __ockl_wfred_min_i32(first);
@@ -548,7 +695,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         if (t == 0) s_m2 = 0;
         __syncthreads();
         for (int q = t; q < m; q += blockDim.x)
-            atomicAdd(&h[tie_digit(P.H, P.oZ[cur][P.cand[src][q]], P.oS[cur][P.cand[src][q]], pos)], 1u);
+            atomicAdd(&h[tie_digit(P, cur, P.cand[src][q], pos)], 1u);
         __syncthreads();
         if (t == 0) {
             long long cum = 0;
@@ -564,7 +711,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         const int v = s_v;
         for (int q = t; q < m; q += blockDim.x) {
             const int idx = P.cand[src][q];
-            const int dgt = tie_digit(P.H, P.oZ[cur][idx], P.oS[cur][idx], pos);
+            const int dgt = tie_digit(P, cur, idx, pos);
             if (dgt < v) P.flag[idx] = 1;
             else if (dgt == v) P.cand[1 - src][atomicAdd(&s_m2, 1)] = idx;
         }
@@ -628,7 +775,6 @@ __global__ __launch_bounds__(64) void k_expand_direct(Params P) {
     for (int r0 = 0; r0 < L; r0 += 64) {
         const int i = 1 + r0 + lane;
         const bool valid = i <= L;
-        int slot = -1, res = INS_NONE;
         int32_t En = 0;
         unsigned long long key = 0;
         if (valid) {
@@ -641,11 +787,8 @@ __global__ __launch_bounds__(64) void k_expand_direct(Params P) {
             }
             En = Ep - 4 * si * g + 4 * q;
             key = (hp ^ zob(i - 1)) | 1ull;
-            res = claim_or_pend(P, key, ps, i, En, &slot);
         }
-        push_open(P, res == INS_CLAIMED, En, slot, key);
-        Pend pd{slot, ps, i, En};
-        push_pending(P, res == INS_PENDING, pd);
+        stage_neighbour(P, valid, key, ps, i, En);
     }
 }
 
@@ -782,12 +925,8 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
         const int G = 2 * H[r] - PC[Mf] - PC[Mb];
         const int Q = (L - 1) + 2 * (M - 2 * dis);
         const int32_t En = Ep - 4 * si * G + 4 * Q;
-        int slot = -1, res = INS_NONE;
         const unsigned long long key = (hp ^ zob(i - 1)) | 1ull;
-        if (valid) res = claim_or_pend(P, key, ps, i, En, &slot);
-        push_open(P, res == INS_CLAIMED, En, slot, key);
-        Pend pd{slot, ps, i, En};
-        push_pending(P, res == INS_PENDING, pd);
+        stage_neighbour(P, valid, key, ps, i, En);
     }
 }
 
@@ -809,11 +948,10 @@ __global__ void k_expand_fin(Params P) {
     if (c->stop) return;
     c->expansions += c->n_piv;
     c->n_live -= c->n_piv;
-    const long long n_new = c->n_tot - c->batch_begin;
+    const long long n_new = c->n_tot - c->batch_begin - c->n_dup_new;
     c->pushes += n_new;
     c->dups += c->n_piv * P.L - n_new;
     c->n_live += n_new;
-    c->claimed += n_new;   // re-pushes claim nothing: an over-count, so rebuilds come early
     if (c->batch_minE < c->best_E) c->improved = 1;
     else c->u += c->n_piv;
     // capacity cut setup
@@ -826,34 +964,46 @@ __global__ void k_expand_fin(Params P) {
     c->out_count = 0;
 }
 
-// best = smallest key among live entries in [batch_begin, n_tot) with E == batch_minE.
+// best = smallest (z, sequence) among live entries in [batch_begin, n_tot) with
+// E == batch_minE.
+__device__ __forceinline__ bool entry_less(const Params& P, int cur, long long a, long long b) {
+    const unsigned long long za = P.oZ[cur][a], zb = P.oZ[cur][b];
+    if (za != zb) return za < zb;
+    const int sa = P.oS[cur][a], sb = P.oS[cur][b];
+    for (int w = 0; w < P.W; ++w) {
+        const uint32_t x = entry_word(P, sa, a, w), y = entry_word(P, sb, b, w);
+        if (x != y) return x < y;
+    }
+    return false;
+}
+
 __global__ __launch_bounds__(1024) void k_best(Params P, int initial) {
     Ctl* c = P.ctl;
     if (c->stop) return;
     if (!initial && !c->improved) return;
-    __shared__ int best[1024];
+    __shared__ long long best[1024];
     const int cur = c->which;
     const long long lo = c->batch_begin;
     const int32_t target = c->batch_minE;
-    int mine = -1;
+    long long mine = -1;
     for (long long i = lo + threadIdx.x; i < c->n_tot; i += blockDim.x) {
         if (P.oE[cur][i] != target) continue;
-        const int s = P.oS[cur][i];
-        if (mine < 0 || key_less(P.H, s, mine)) mine = s;
+        if (mine < 0 || entry_less(P, cur, i, mine)) mine = i;
     }
     best[threadIdx.x] = mine;
     __syncthreads();
     for (int o = 512; o > 0; o >>= 1) {
         if (threadIdx.x < o) {
-            const int x = best[threadIdx.x], y = best[threadIdx.x + o];
-            if (x < 0 || (y >= 0 && key_less(P.H, y, x))) best[threadIdx.x] = y;
+            const long long x = best[threadIdx.x], y = best[threadIdx.x + o];
+            if (x < 0 || (y >= 0 && entry_less(P, cur, y, x))) best[threadIdx.x] = y;
         }
         __syncthreads();
     }
-    if (best[0] >= 0 && threadIdx.x < (unsigned)P.W)
-        P.best_seq[threadIdx.x] = P.H.seq[(size_t)best[0] * P.W + threadIdx.x];
-    if (threadIdx.x == 0 && best[0] >= 0) {
-        c->best_slot = best[0];
+    const long long b = best[0];
+    if (b >= 0 && threadIdx.x < (unsigned)P.W)
+        P.best_seq[threadIdx.x] = entry_word(P, P.oS[cur][b], b, threadIdx.x);
+    if (threadIdx.x == 0 && b >= 0) {
+        c->best_slot = 1;   // a best sequence has been recorded
         c->best_E = target;
         if (!initial) {
             c->best_round = (int32_t)c->rounds;
@@ -869,21 +1019,56 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
     if (c->stop) return;
     const int cur = c->which;
     const bool cut = c->sel_enabled;
+    const Table& H = P.H;
+    long long claims = 0;
     for (long long base = (long long)blockIdx.x * blockDim.x; base < c->n_tot;
          base += (long long)gridDim.x * blockDim.x) {
         const long long i = base + threadIdx.x;
         bool keep = false;
+        int slot = -1;
         if (i < c->n_tot && P.oE[cur][i] != DEAD) {
             keep = !cut || P.flag[i];
-            if (!keep) P.H.state[P.oS[cur][i]] = ST_EVICTED;
+            slot = P.oS[cur][i];
+            if (slot >= 0) {
+                if (!keep) H.state[slot] = ST_EVICTED;
+            } else if (keep) {
+                // A surviving new entry enters H: its tombstone is re-opened, or an
+                // empty slot is claimed.  A slot already holding its key holds
+                // another sequence (an equal sequence would have been found by the
+                // expansion's probe, and surviving new entries are distinct).
+                const long long j = i - c->batch_begin;
+                const unsigned long long key = P.oZ[cur][i];
+                if (P.ntomb[j] >= 0) {
+                    slot = P.ntomb[j];
+                    H.state[slot] = ST_OPEN;
+                } else {
+                    uint64_t s2 = key & H.mask;
+                    for (uint64_t probe = 0; probe <= H.mask; ++probe, s2 = (s2 + 1) & H.mask)
+                        if (atomicCAS(&H.hkey[s2], 0ull, key) == 0ull) {
+                            slot = (int)s2;
+                            break;
+                        }
+                    if (slot < 0) {
+                        atomicExch(&c->error, 2);
+                        keep = false;
+                    } else {
+                        for (int w = 0; w < H.W; ++w)
+                            H.seq[(size_t)slot * H.W + w] = src_word(P, P.nsrc[j], P.nflip[j], w);
+                        H.E[slot] = P.oE[cur][i];
+                        H.state[slot] = ST_OPEN;
+                        ++claims;
+                    }
+                }
+            }
         }
         const long long o = block_append(&c->survivors, keep);
         if (keep) {
             P.oE[1 - cur][o] = P.oE[cur][i];
-            P.oS[1 - cur][o] = P.oS[cur][i];
+            P.oS[1 - cur][o] = slot;
             P.oZ[1 - cur][o] = P.oZ[cur][i];
         }
     }
+    if (claims) atomicAdd((unsigned long long*)&c->claimed, (unsigned long long)claims);
 }
 
 __global__ void k_round_end(Params P, int count_round) {
@@ -957,7 +1142,6 @@ __global__ void k_remap(Params P, const uint32_t* remap) {
 }
 
 __global__ void k_rebuild_fin(Ctl* c, const uint32_t* remap) {
-    if (c->best_slot >= 0) c->best_slot = (int32_t)remap[c->best_slot];
     c->claimed = c->claimed_new;
     c->claimed_new = 0;
 }
@@ -1012,8 +1196,8 @@ uint64_t next_pow2(uint64_t x) {
 constexpr int kCheck = 8;    // rounds between host looks at the control block
 
 struct S2Layout {
-    uint64_t cap_ht;
-    long long cap_o, cap_pend;
+    uint64_t cap_ht, cap_r;
+    long long cap_o, cap_pend, cap_new;
     size_t total;
 };
 
@@ -1025,16 +1209,12 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     lo.cap_o = base + BL + 1024;
     lo.cap_pend = (BL > n_cand ? BL : n_cand) + 1024;
     // live slots never exceed n_cand + X + Q + BL; the table is rebuilt when half
-    // of it is claimed, with kCheck rounds of claims as headroom.  Evicted
-    // sequences keep their slots until a rebuild, and a rebuild costs about one
-    // random insertion per live entry whatever the table size, so the table is
-    // made large (16x the bound: 43 GB for two tables at 10^7 expansions of
-    // L = 501) to make rebuilds rare.
+    // of it is claimed (claims: seeds, and new entries surviving their round's
+    // cut), with kCheck rounds of claims as headroom.
     const long long live = n_cand + c.max_expansions + c.pq_capacity + BL;
-    for (int f = 16; f >= 4; f >>= 1) {   // slots are int32 indices: at most 2^31
-        lo.cap_ht = next_pow2((uint64_t)(f * (live + (long long)kCheck * BL) + 1024));
-        if (lo.cap_ht <= (1ull << 31)) break;
-    }
+    lo.cap_ht = next_pow2((uint64_t)(4 * (live + (long long)kCheck * BL) + 1024));
+    lo.cap_new = BL + 1024;
+    lo.cap_r = next_pow2((uint64_t)(2 * lo.cap_new));
     size_t t = 0;
     for (int tb = 0; tb < 2; ++tb) {
         t += align_up(sizeof(unsigned long long) * lo.cap_ht, 256);
@@ -1043,6 +1223,9 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
         t += align_up(sizeof(uint32_t) * lo.cap_ht * W, 256);
     }
     t += align_up(sizeof(uint32_t) * lo.cap_ht, 256);                  // remap
+    t += 3 * align_up(sizeof(int32_t) * lo.cap_new, 256);              // nsrc, nflip, ntomb
+    t += align_up(sizeof(unsigned long long) * lo.cap_r, 256);         // rkey
+    t += align_up(sizeof(int32_t) * lo.cap_r, 256);                    // ridx
     t += align_up(sizeof(Ctl), 256);
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // oE
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // oS
@@ -1097,6 +1280,12 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
         tabs[tb2].W = P.W;
     }
     uint32_t* remap = cv.take<uint32_t>(lo.cap_ht);
+    P.nsrc = cv.take<int32_t>(lo.cap_new);
+    P.nflip = cv.take<int32_t>(lo.cap_new);
+    P.ntomb = cv.take<int32_t>(lo.cap_new);
+    P.rkey = cv.take<unsigned long long>(lo.cap_r);
+    P.ridx = cv.take<int32_t>(lo.cap_r);
+    P.rmask = lo.cap_r - 1;
     int tcur = 0;
     P.H = tabs[0];
     P.ctl = cv.take<Ctl>(1);
@@ -1148,11 +1337,12 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
         hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, P);
         select();
         hipLaunchKernelGGL(k_pop, gS, tS, 0, st, P);
+        hipLaunchKernelGGL(k_clear_u64, dim3(1024), dim3(256), 0, st, P.rkey, (uint64_t)lo.cap_r);
         if (tb && (s = tb(tctx, st)) != LABS_OK) return s;
         hipLaunchKernelGGL(ek, dim3((unsigned)cfg.batch), dim3(eth), 0, st, P);
         if (te && (s = te(tctx, st)) != LABS_OK) return s;
-        hipLaunchKernelGGL(k_resolve, gS, tS, 0, st, P);
-        hipLaunchKernelGGL(k_slow, dim3(1), dim3(1), 0, st, P);
+        hipLaunchKernelGGL(k_rresolve, gS, tS, 0, st, P);
+        hipLaunchKernelGGL(k_rslow, dim3(1), dim3(1), 0, st, P);
         hipLaunchKernelGGL(k_expand_fin, dim3(1), dim3(1), 0, st, P);
         hipLaunchKernelGGL(k_best, dim3(1), dim3(1024), 0, st, P, 0);
         select();
