@@ -46,7 +46,7 @@ namespace {
 constexpr int32_t DEAD = INT32_MAX;
 constexpr uint32_t ST_OPEN = 1, ST_CLOSED = 2, ST_EVICTED = 3;
 constexpr uint64_t ZKEY = 0x6A09E667F3BCC909ull;   // Zobrist stream key
-constexpr int kSelBits = 11;
+constexpr int kSelBits = 14;   // radix digit of the energy select (one level covers a 16384-wide range)
 constexpr int kSelBins = 1 << kSelBits;
 constexpr int kSelBlocks = 128;
 constexpr int kSelThreads = 512;
@@ -105,7 +105,7 @@ struct Params {
     uint32_t* flag;        // [cap_o]
     int32_t* cand[2];      // [cap_o] each
     int32_t* piv;          // [B]
-    uint32_t* ghist;       // [kSelBlocks][kSelBins]
+    uint32_t* ghist;       // [kSelBins], zero between selection levels
     uint32_t* best_seq;    // [W] copy of the best sequence
     Pend* pend;            // [cap_pend]
     Pend* slow;            // [cap_pend]
@@ -549,8 +549,8 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_hist(Params P, int level) {
         atomicAdd(&h[(D >> ls) & dmask], 1u);
     }
     __syncthreads();
-    uint32_t* row = P.ghist + (size_t)blockIdx.x * kSelBins;
-    for (int b = threadIdx.x; b < kSelBins; b += blockDim.x) row[b] = h[b];
+    for (int b = threadIdx.x; b < kSelBins; b += blockDim.x)
+        if (h[b]) atomicAdd(&P.ghist[b], h[b]);
 }
 
 __global__ __launch_bounds__(1024) void k_sel_find(Params P, int level) {
@@ -566,17 +566,20 @@ __global__ __launch_bounds__(1024) void k_sel_find(Params P, int level) {
         }
         return;
     }
+    constexpr int PER = kSelBins / 1024;
     __shared__ uint32_t part[1024];
     int hs, ls;
     uint32_t prefix;
     level_shifts(c, level, &hs, &ls, &prefix);
     const long long c_lt = level == 0 ? 0 : c->c_lt;
-    uint32_t a = 0, b = 0;
-    for (int r = 0; r < kSelBlocks; ++r) {
-        a += P.ghist[(size_t)r * kSelBins + 2 * t];
-        b += P.ghist[(size_t)r * kSelBins + 2 * t + 1];
+    uint32_t cnt[PER];
+    uint32_t a = 0;
+    for (int k = 0; k < PER; ++k) {
+        cnt[k] = P.ghist[PER * t + k];
+        P.ghist[PER * t + k] = 0;   // the histogram is empty for the next level
+        a += cnt[k];
     }
-    part[t] = a + b;
+    part[t] = a;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
         uint32_t x = t >= o ? part[t - o] : 0;
@@ -585,18 +588,17 @@ __global__ __launch_bounds__(1024) void k_sel_find(Params P, int level) {
         __syncthreads();
     }
     const long long need = c->T - c_lt;
-    const long long before = (long long)part[t] - (a + b);
-    int v = -1;
-    long long below = 0;
+    long long before = (long long)part[t] - a;
     if (before < need && need <= before + a) {
-        v = 2 * t;
-        below = before;
-    } else if (before + a < need && need <= before + a + b) {
-        v = 2 * t + 1;
-        below = before + a;
-    }
-    if (v >= 0) {
-        c->c_lt = c_lt + below;
+        int v = PER * t;
+        for (int k = 0; k < PER; ++k) {
+            if (before + cnt[k] >= need) {
+                v = PER * t + k;
+                break;
+            }
+            before += cnt[k];
+        }
+        c->c_lt = c_lt + before;
         const uint32_t np = (prefix << (hs - ls)) | (uint32_t)v;
         c->prefix = np;
         if (ls == 0) {
@@ -664,12 +666,16 @@ __device__ __forceinline__ int first_diff(const Params& P, int cur, long long a,
 // byte-wise radix select over the tie digits.  Each iteration first finds, in one
 // pass, the first digit position (from `pos` on) at which any candidate differs
 // from the first one, then partitions the candidates on that digit.
+constexpr int kTieLds = 2048;   // ties resolved on Zobrist bytes in LDS up to this count
+
 __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
     Ctl* c = P.ctl;
     if (c->stop || !c->sel_enabled || c->sel_all) return;
     __shared__ uint32_t h[256];
     __shared__ int s_pos, s_v, s_m2;
     __shared__ long long s_r;
+    __shared__ unsigned long long zs[2][kTieLds];
+    __shared__ int32_t is[2][kTieLds];
     const int cur = c->which;
     const int t = threadIdx.x;
     const int npos = 8 + 4 * P.W;
@@ -677,6 +683,125 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
     long long r = c->T - c->c_lt;
     int src = 0;
     int pos = 0;
+    // Large tie sets: partition on key bytes read from the Open list until the
+    // remaining set fits in LDS (keys are pseudo-random, so one byte divides
+    // the set by about 256).
+    while (m > kTieLds && pos < 8 && r > 0 && r < m) {
+        const int sh = 56 - 8 * pos;
+        if (t < 256) h[t] = 0;
+        if (t == 0) s_m2 = 0;
+        __syncthreads();
+        for (int q = t; q < m; q += blockDim.x)
+            atomicAdd(&h[(P.oZ[cur][P.cand[src][q]] >> sh) & 255ull], 1u);
+        __syncthreads();
+        if (t < 64) {
+            const uint32_t c0 = h[4 * t], c1 = h[4 * t + 1], c2 = h[4 * t + 2], c3 = h[4 * t + 3];
+            uint32_t inc = c0 + c1 + c2 + c3;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(inc, o, 64);
+                if (t >= o) inc += y;
+            }
+            long long cum = (long long)inc - (c0 + c1 + c2 + c3);
+            const uint32_t cs[4] = {c0, c1, c2, c3};
+            for (int k = 0; k < 4; ++k) {
+                if (cum < r && r <= cum + cs[k]) {
+                    s_v = 4 * t + k;
+                    s_r = r - cum;
+                }
+                cum += cs[k];
+            }
+        }
+        __syncthreads();
+        const int v = s_v;
+        for (int q = t; q < m; q += blockDim.x) {
+            const int idx = P.cand[src][q];
+            const int dgt = (int)((P.oZ[cur][idx] >> sh) & 255ull);
+            if (dgt < v) P.flag[idx] = 1;
+            else if (dgt == v) P.cand[1 - src][atomicAdd(&s_m2, 1)] = idx;
+        }
+        __syncthreads();
+        m = s_m2;
+        r = s_r;
+        src = 1 - src;
+        pos += 1;
+        __syncthreads();
+    }
+    if (m <= kTieLds && pos < 8 && r > 0 && r < m) {
+        // Fast path: the tied entries' keys in LDS, one byte of the key per pass.
+        int b = 0;
+        for (int q = t; q < m; q += blockDim.x) {
+            const int idx = P.cand[src][q];
+            is[0][q] = idx;
+            zs[0][q] = P.oZ[cur][idx];
+        }
+        __syncthreads();
+        while (pos < 8 && r > 0 && r < m) {
+            if (t == 0) s_pos = 8;
+            __syncthreads();
+            const unsigned long long z0 = zs[b][0], keep_mask = ~0ull >> (8 * pos);
+            int first = 8;
+            for (int q = t; q < m; q += blockDim.x) {
+                const unsigned long long x = (zs[b][q] ^ z0) & keep_mask;
+                const int d = x ? (__clzll((long long)x) >> 3) : 8;
+                first = d < first ? d : first;
+            }
+            first = __ockl_wfred_min_i32(first);
+            if ((t & 63) == 0) atomicMin(&s_pos, first);
+            if (t < 256) h[t] = 0;
+            if (t == 0) s_m2 = 0;
+            __syncthreads();
+            pos = s_pos;
+            if (pos >= 8) break;   // equal keys: finish on the sequences below
+            const int sh = 56 - 8 * pos;
+            for (int q = t; q < m; q += blockDim.x) atomicAdd(&h[(zs[b][q] >> sh) & 255ull], 1u);
+            __syncthreads();
+            if (t < 64) {   // one wave scans the 256 counts (4 per lane)
+                const uint32_t c0 = h[4 * t], c1 = h[4 * t + 1], c2 = h[4 * t + 2], c3 = h[4 * t + 3];
+                uint32_t inc = c0 + c1 + c2 + c3;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = __shfl_up(inc, o, 64);
+                    if (t >= o) inc += y;
+                }
+                long long cum = (long long)inc - (c0 + c1 + c2 + c3);
+                const uint32_t cs[4] = {c0, c1, c2, c3};
+                for (int k = 0; k < 4; ++k) {
+                    if (cum < r && r <= cum + cs[k]) {
+                        s_v = 4 * t + k;
+                        s_r = r - cum;
+                    }
+                    cum += cs[k];
+                }
+            }
+            __syncthreads();
+            const int v = s_v;
+            for (int q = t; q < m; q += blockDim.x) {
+                const int dgt = (int)((zs[b][q] >> sh) & 255ull);
+                if (dgt < v) P.flag[is[b][q]] = 1;
+                else if (dgt == v) {
+                    const int o2 = atomicAdd(&s_m2, 1);
+                    zs[1 - b][o2] = zs[b][q];
+                    is[1 - b][o2] = is[b][q];
+                }
+            }
+            __syncthreads();
+            m = s_m2;
+            r = s_r;
+            b = 1 - b;
+            pos += 1;
+            __syncthreads();
+        }
+        if (pos < 8 || r <= 0 || r >= m) {
+            if (r > 0)
+                for (int q = t; q < m; q += blockDim.x) P.flag[is[b][q]] = 1;
+            return;
+        }
+        // the remaining m entries share their whole key: continue on the sequences
+        __syncthreads();
+        for (int q = t; q < m; q += blockDim.x) P.cand[1 - src][q] = is[b][q];
+        __syncthreads();
+        src = 1 - src;
+        pos = 8;
+    }
     while (pos < npos && r > 0 && r < m) {
         if (t == 0) s_pos = npos;
         __syncthreads();
@@ -1233,7 +1358,7 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     t += align_up(sizeof(uint32_t) * lo.cap_o, 256);                   // flag
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // cand
     t += align_up(sizeof(int32_t) * c.batch, 256);                     // piv
-    t += align_up(sizeof(uint32_t) * kSelBins * kSelBlocks, 256);      // histograms
+    t += align_up(sizeof(uint32_t) * kSelBins, 256);                   // select histogram
     t += align_up(sizeof(uint32_t) * 32, 256);                         // best sequence
     t += 2 * align_up(sizeof(Pend) * lo.cap_pend, 256);                // pending, collisions
     lo.total = t + 4096;
@@ -1295,7 +1420,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.flag = cv.take<uint32_t>(lo.cap_o);
     for (int b = 0; b < 2; ++b) P.cand[b] = cv.take<int32_t>(lo.cap_o);
     P.piv = cv.take<int32_t>(cfg.batch);
-    P.ghist = cv.take<uint32_t>((size_t)kSelBins * kSelBlocks);
+    P.ghist = cv.take<uint32_t>((size_t)kSelBins);
     P.best_seq = cv.take<uint32_t>(32);
     P.pend = cv.take<Pend>(lo.cap_pend);
     P.slow = cv.take<Pend>(lo.cap_pend);
@@ -1305,6 +1430,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     LABS_HIP(hipMemsetAsync(P.H.hkey, 0, sizeof(unsigned long long) * lo.cap_ht, st));
     LABS_HIP(hipMemsetAsync(P.H.state, 0, sizeof(uint32_t) * lo.cap_ht, st));
     LABS_HIP(hipMemsetAsync(P.best_seq, 0, sizeof(uint32_t) * 32, st));
+    LABS_HIP(hipMemsetAsync(P.ghist, 0, sizeof(uint32_t) * kSelBins, st));
     const dim3 gS(kGridBlocks), tS(kSelThreads);
     auto select = [&]() {
         hipLaunchKernelGGL(k_sel_minmax, dim3(kSelBlocks), tS, 0, st, P);
