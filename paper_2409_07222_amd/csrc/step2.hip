@@ -55,6 +55,7 @@ constexpr int kMaxL = 1023;
 constexpr int kPad = 1024;
 constexpr int kSv = kMaxL + 2 * kPad + 2;
 constexpr int kExThreads = 256;
+constexpr int kItems = 8;                            // list entries per thread per pass (filters)
 
 struct Table {
     unsigned long long* hkey;
@@ -110,10 +111,11 @@ struct Params {
     Pend* pend;            // [cap_pend]
     Pend* slow;            // [cap_pend]
     const uint32_t* cands; // seeding input
-    // this round's new Open entries, by position minus batch_begin
-    int32_t* nsrc;         // pivot slot
-    int32_t* nflip;        // flipped position (1-based)
+    // This round's neighbours occupy Open positions batch_begin + b*L + (i-1) for
+    // pivot b and flip position i (DEAD when not pushed); by that offset:
     int32_t* ntomb;        // slot of the sequence's evicted tombstone, or -1
+    int32_t* bcnt;         // [B] neighbours pushed by pivot b
+    int32_t* bmin;         // [B] their least energy
     // per-round dedupe table: Zobrist key -> Open position of the first holder
     unsigned long long* rkey;
     int32_t* ridx;
@@ -147,6 +149,35 @@ __device__ long long block_append(long long* counter, bool take) {
     return take ? idx : -1;
 }
 
+// Block-aggregated append of n >= 0 items per thread (one atomic per block);
+// every thread of the block must call it.  Returns the thread's first index.
+__device__ long long block_append_n(long long* counter, int n) {
+    __shared__ int wsum[16];
+    __shared__ long long bbase;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    int x = n;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int k = 0; k < nw; ++k) {
+            const int t = wsum[k];
+            wsum[k] = run;
+            run += t;
+        }
+        bbase = run ? (long long)atomicAdd((unsigned long long*)counter, (unsigned long long)run) : 0;
+    }
+    __syncthreads();
+    const long long r = bbase + wsum[wv] + (x - n);
+    __syncthreads();
+    return r;
+}
+
 __device__ __forceinline__ void atomic_min_batch(Ctl* c, bool take, int32_t E) {
     const int mn = __ockl_wfred_min_i32(take ? E : INT32_MAX);
     if ((threadIdx.x & 63) == 0 && mn != INT32_MAX) atomicMin(&c->batch_minE, mn);
@@ -175,7 +206,7 @@ __device__ __forceinline__ uint32_t src_word(const Params& P, int src, int flip,
 __device__ __forceinline__ uint32_t entry_word(const Params& P, int slot, long long o, int w) {
     if (slot >= 0) return P.H.seq[(size_t)slot * P.W + w];
     const long long j = o - P.ctl->batch_begin;
-    return src_word(P, P.nsrc[j], P.nflip[j], w);
+    return src_word(P, P.piv[j / P.L], (int)(j % P.L) + 1, w);
 }
 
 __device__ __forceinline__ bool entries_equal(const Params& P, int sa, long long a, int sb, long long b) {
@@ -230,11 +261,12 @@ __device__ __forceinline__ void push_pending(const Params& P, bool take, const P
     if (take && o < P.cap_pend) P.pend[o] = pd;
 }
 
-// A generated neighbour (pivot slot ps, flip position, energy En, Zobrist key):
-// dropped when H holds its sequence as OPEN or CLOSED, else appended to the Open
-// list as a new entry and entered into R.  Every thread of the block calls it.
+// A generated neighbour (flip position `flip` of the block's pivot, slot ps;
+// energy En; Zobrist key): its Open position is fixed by (pivot, flip).  It is
+// DEAD when H holds its sequence as OPEN or CLOSED, else a new entry entered into
+// R.  Every thread of the block calls it; `taken` and `mn` accumulate per thread.
 __device__ void stage_neighbour(const Params& P, bool valid, unsigned long long key, int ps, int flip,
-                                int32_t En) {
+                                int32_t En, int& taken, int32_t& mn) {
     Ctl* c = P.ctl;
     int tomb = -1;
     bool take = false;
@@ -258,35 +290,62 @@ __device__ void stage_neighbour(const Params& P, bool valid, unsigned long long 
             break;
         }
     }
-    const long long o = block_append(&c->n_tot, take);
-    if (take && o >= P.cap_o) atomicExch(&c->error, 4);
     bool pend = false;
     Pend pd{0, 0, 0, 0};
-    if (take && o < P.cap_o) {
+    if (valid) {
         const int cur = c->which;
-        P.oE[cur][o] = En;
-        P.oS[cur][o] = -1;
-        P.oZ[cur][o] = key;
-        const long long j = o - c->batch_begin;
-        P.nsrc[j] = ps;
-        P.nflip[j] = flip;
-        P.ntomb[j] = tomb;
-        uint64_t r = key & P.rmask;
-        for (uint64_t probe = 0; probe <= P.rmask; ++probe, r = (r + 1) & P.rmask) {
-            const unsigned long long prev = atomicCAS(&P.rkey[r], 0ull, key);
-            if (prev == 0ull) {
-                P.ridx[r] = (int32_t)o;
-                break;
-            }
-            if (prev == key) {
-                pend = true;
-                pd = Pend{(int32_t)r, (int32_t)o, 0, En};
-                break;
+        const long long j = (long long)blockIdx.x * P.L + (flip - 1);
+        const long long o = c->batch_begin + j;
+        if (!take) {
+            P.oE[cur][o] = DEAD;
+        } else {
+            P.oE[cur][o] = En;
+            P.oS[cur][o] = -1;
+            P.oZ[cur][o] = key;
+            P.ntomb[j] = tomb;
+            ++taken;
+            mn = En < mn ? En : mn;
+            uint64_t r = key & P.rmask;
+            for (uint64_t probe = 0; probe <= P.rmask; ++probe, r = (r + 1) & P.rmask) {
+                const unsigned long long prev = atomicCAS(&P.rkey[r], 0ull, key);
+                if (prev == 0ull) {
+                    P.ridx[r] = (int32_t)o;
+                    break;
+                }
+                if (prev == key) {
+                    pend = true;
+                    pd = Pend{(int32_t)r, (int32_t)o, 0, En};
+                    break;
+                }
             }
         }
     }
-    atomic_min_batch(c, take, En);
     push_pending(P, pend, pd);
+}
+
+// The block's pushed count and least energy (every thread calls it once).
+__device__ void stage_finish(const Params& P, int taken, int32_t mn) {
+    __shared__ int s_cnt[16];
+    __shared__ int32_t s_min[16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    taken = __ockl_wfred_add_i32(taken);
+    mn = __ockl_wfred_min_i32(mn);
+    if (lane == 0) {
+        s_cnt[wv] = taken;
+        s_min[wv] = mn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        int32_t m = INT32_MAX;
+        for (int k = 0; k < nw; ++k) {
+            t += s_cnt[k];
+            m = s_min[k] < m ? s_min[k] : m;
+        }
+        P.bcnt[blockIdx.x] = t;
+        P.bmin[blockIdx.x] = m;
+    }
 }
 
 // ---------------------------------------------------------------- seeding
@@ -618,21 +677,30 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
     const int cur = c->which;
     const bool all = c->sel_all;
     const uint32_t Et = c->emin + c->Dt;
-    for (long long base = (long long)blockIdx.x * blockDim.x; base < c->n_tot;
-         base += (long long)gridDim.x * blockDim.x) {
-        const long long i = base + threadIdx.x;
-        bool tie = false;
-        if (i < c->n_tot) {
-            const int32_t e = P.oE[cur][i];
-            uint32_t f = 0;
-            if (e != DEAD) {
-                if (all || (uint32_t)e < Et) f = 1;
-                else if ((uint32_t)e == Et) tie = true;
+    const long long n_tot = c->n_tot;
+    const long long stride = (long long)gridDim.x * blockDim.x * kItems;
+    for (long long base = (long long)blockIdx.x * blockDim.x * kItems; base < n_tot; base += stride) {
+        bool tie[kItems];
+        int cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const long long i = base + threadIdx.x + (long long)k * blockDim.x;
+            tie[k] = false;
+            if (i < n_tot) {
+                const int32_t e = P.oE[cur][i];
+                uint32_t f = 0;
+                if (e != DEAD) {
+                    if (all || (uint32_t)e < Et) f = 1;
+                    else if ((uint32_t)e == Et) tie[k] = true;
+                }
+                P.flag[i] = f;
             }
-            P.flag[i] = f;
+            cnt += tie[k] ? 1 : 0;
         }
-        const long long o = block_append(&c->out_count, tie);
-        if (tie) P.cand[0][o] = (int32_t)i;
+        long long o = block_append_n(&c->out_count, cnt);
+#pragma unroll
+        for (int k = 0; k < kItems; ++k)
+            if (tie[k]) P.cand[0][o++] = (int32_t)(base + threadIdx.x + (long long)k * blockDim.x);
     }
 }
 
@@ -856,17 +924,31 @@ __global__ __launch_bounds__(kSelThreads) void k_pop(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
     const int cur = c->which;
-    for (long long base = (long long)blockIdx.x * blockDim.x; base < c->n_tot;
-         base += (long long)gridDim.x * blockDim.x) {
-        const long long i = base + threadIdx.x;
-        const bool take = i < c->n_tot && P.flag[i] && P.oE[cur][i] != DEAD;
-        const long long o = block_append(&c->n_piv, take);
-        if (take && o >= P.B) atomicExch(&c->error, 3);
-        if (take && o < P.B) {
-            const int slot = P.oS[cur][i];
-            P.piv[o] = slot;
-            P.oE[cur][i] = DEAD;
-            P.H.state[slot] = ST_CLOSED;
+    const long long n_tot = c->n_tot;
+    const long long stride = (long long)gridDim.x * blockDim.x * kItems;
+    for (long long base = (long long)blockIdx.x * blockDim.x * kItems; base < n_tot; base += stride) {
+        bool take[kItems];
+        int cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const long long i = base + threadIdx.x + (long long)k * blockDim.x;
+            take[k] = i < n_tot && P.flag[i] && P.oE[cur][i] != DEAD;
+            cnt += take[k] ? 1 : 0;
+        }
+        long long o = block_append_n(&c->n_piv, cnt);
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (!take[k]) continue;
+            const long long i = base + threadIdx.x + (long long)k * blockDim.x;
+            if (o >= P.B) {
+                atomicExch(&c->error, 3);
+            } else {
+                const int slot = P.oS[cur][i];
+                P.piv[o] = slot;
+                P.oE[cur][i] = DEAD;
+                P.H.state[slot] = ST_CLOSED;
+            }
+            ++o;
         }
     }
 }
@@ -897,6 +979,8 @@ __global__ __launch_bounds__(64) void k_expand_direct(Params P) {
     for (int x = 1 + lane; x <= L; x += 64)
         if (sv[kPad + x] > 0) hp ^= zob(x - 1);
     for (int o = 32; o > 0; o >>= 1) hp ^= __shfl_xor(hp, o, 64);
+    int taken = 0;
+    int32_t mn = INT32_MAX;
     for (int r0 = 0; r0 < L; r0 += 64) {
         const int i = 1 + r0 + lane;
         const bool valid = i <= L;
@@ -913,8 +997,9 @@ __global__ __launch_bounds__(64) void k_expand_direct(Params P) {
             En = Ep - 4 * si * g + 4 * q;
             key = (hp ^ zob(i - 1)) | 1ull;
         }
-        stage_neighbour(P, valid, key, ps, i, En);
+        stage_neighbour(P, valid, key, ps, i, En, taken, mn);
     }
+    stage_finish(P, taken, mn);
 }
 
 // Bit-sliced expansion, 4 wavefronts per pivot.  For the single flip of s_i:
@@ -1033,6 +1118,8 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
 #pragma unroll
         for (int r = 0; r < R2; ++r) H[r] += wgt * (int)acc[r];
     }
+    int taken = 0;
+    int32_t mn = INT32_MAX;
 #pragma unroll
     for (int r = 0; r < R2; ++r) {
         const int i0 = 1 + lane + 64 * (wv + 4 * r);
@@ -1051,8 +1138,9 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
         const int Q = (L - 1) + 2 * (M - 2 * dis);
         const int32_t En = Ep - 4 * si * G + 4 * Q;
         const unsigned long long key = (hp ^ zob(i - 1)) | 1ull;
-        stage_neighbour(P, valid, key, ps, i, En);
+        stage_neighbour(P, valid, key, ps, i, En, taken, mn);
     }
+    stage_finish(P, taken, mn);
 }
 
 typedef void (*expand_kernel_t)(Params);
@@ -1068,12 +1156,37 @@ expand_kernel_t pick_expand(int L, unsigned* threads) {
     return k_expand_direct;
 }
 
-__global__ void k_expand_fin(Params P) {
+__global__ __launch_bounds__(1024) void k_expand_fin(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
+    __shared__ long long s_cnt[16];
+    __shared__ int32_t s_min[16];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    long long cnt = 0;
+    int32_t mn = INT32_MAX;
+    for (long long b = t; b < c->n_piv; b += blockDim.x) {
+        cnt += P.bcnt[b];
+        mn = P.bmin[b] < mn ? P.bmin[b] : mn;
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    mn = __ockl_wfred_min_i32(mn);
+    if (lane == 0) {
+        s_cnt[wv] = cnt;
+        s_min[wv] = mn;
+    }
+    __syncthreads();
+    if (t != 0) return;
+    cnt = s_cnt[0];
+    mn = s_min[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+        cnt += s_cnt[k];
+        mn = s_min[k] < mn ? s_min[k] : mn;
+    }
+    c->n_tot = c->batch_begin + c->n_piv * P.L;
+    c->batch_minE = mn;
     c->expansions += c->n_piv;
     c->n_live -= c->n_piv;
-    const long long n_new = c->n_tot - c->batch_begin - c->n_dup_new;
+    const long long n_new = cnt - c->n_dup_new;
     c->pushes += n_new;
     c->dups += c->n_piv * P.L - n_new;
     c->n_live += n_new;
@@ -1138,59 +1251,74 @@ __global__ __launch_bounds__(1024) void k_best(Params P, int initial) {
 }
 
 // Keep the flagged live entries (all live entries when no cut is needed) in the
-// other buffer; the rest become EVICTED.
+// other buffer; the rest become EVICTED (or, new entries, are never written to
+// H).  Each thread handles kItems entries per pass, one atomic per block pass.
+
 __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
     const int cur = c->which;
     const bool cut = c->sel_enabled;
     const Table& H = P.H;
+    const long long n_tot = c->n_tot, bb = c->batch_begin;
     long long claims = 0;
-    for (long long base = (long long)blockIdx.x * blockDim.x; base < c->n_tot;
-         base += (long long)gridDim.x * blockDim.x) {
-        const long long i = base + threadIdx.x;
-        bool keep = false;
-        int slot = -1;
-        if (i < c->n_tot && P.oE[cur][i] != DEAD) {
-            keep = !cut || P.flag[i];
-            slot = P.oS[cur][i];
-            if (slot >= 0) {
-                if (!keep) H.state[slot] = ST_EVICTED;
-            } else if (keep) {
-                // A surviving new entry enters H: its tombstone is re-opened, or an
-                // empty slot is claimed.  A slot already holding its key holds
-                // another sequence (an equal sequence would have been found by the
-                // expansion's probe, and surviving new entries are distinct).
-                const long long j = i - c->batch_begin;
-                const unsigned long long key = P.oZ[cur][i];
-                if (P.ntomb[j] >= 0) {
-                    slot = P.ntomb[j];
-                    H.state[slot] = ST_OPEN;
-                } else {
-                    uint64_t s2 = key & H.mask;
-                    for (uint64_t probe = 0; probe <= H.mask; ++probe, s2 = (s2 + 1) & H.mask)
-                        if (atomicCAS(&H.hkey[s2], 0ull, key) == 0ull) {
-                            slot = (int)s2;
-                            break;
-                        }
-                    if (slot < 0) {
-                        atomicExch(&c->error, 2);
-                        keep = false;
+    const long long stride = (long long)gridDim.x * blockDim.x * kItems;
+    for (long long base = (long long)blockIdx.x * blockDim.x * kItems; base < n_tot; base += stride) {
+        int slot[kItems];
+        bool keep[kItems];
+        int cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const long long i = base + threadIdx.x + (long long)k * blockDim.x;
+            keep[k] = false;
+            slot[k] = -1;
+            if (i < n_tot && P.oE[cur][i] != DEAD) {
+                keep[k] = !cut || P.flag[i];
+                slot[k] = P.oS[cur][i];
+                if (slot[k] >= 0) {
+                    if (!keep[k]) H.state[slot[k]] = ST_EVICTED;
+                } else if (keep[k]) {
+                    // A surviving new entry enters H: its tombstone is re-opened, or
+                    // an empty slot is claimed.  A slot already holding its key holds
+                    // another sequence (an equal sequence would have been found by
+                    // the expansion's probe, and surviving new entries are distinct).
+                    const long long j = i - bb;
+                    const unsigned long long key = P.oZ[cur][i];
+                    if (P.ntomb[j] >= 0) {
+                        slot[k] = P.ntomb[j];
+                        H.state[slot[k]] = ST_OPEN;
                     } else {
-                        for (int w = 0; w < H.W; ++w)
-                            H.seq[(size_t)slot * H.W + w] = src_word(P, P.nsrc[j], P.nflip[j], w);
-                        H.E[slot] = P.oE[cur][i];
-                        H.state[slot] = ST_OPEN;
-                        ++claims;
+                        uint64_t s2 = key & H.mask;
+                        for (uint64_t probe = 0; probe <= H.mask; ++probe, s2 = (s2 + 1) & H.mask)
+                            if (atomicCAS(&H.hkey[s2], 0ull, key) == 0ull) {
+                                slot[k] = (int)s2;
+                                break;
+                            }
+                        if (slot[k] < 0) {
+                            atomicExch(&c->error, 2);
+                            keep[k] = false;
+                        } else {
+                            const int ps = P.piv[j / P.L], fl = (int)(j % P.L) + 1;
+                            for (int w = 0; w < H.W; ++w)
+                                H.seq[(size_t)slot[k] * H.W + w] = src_word(P, ps, fl, w);
+                            H.E[slot[k]] = P.oE[cur][i];
+                            H.state[slot[k]] = ST_OPEN;
+                            ++claims;
+                        }
                     }
                 }
             }
+            cnt += keep[k] ? 1 : 0;
         }
-        const long long o = block_append(&c->survivors, keep);
-        if (keep) {
+        long long o = block_append_n(&c->survivors, cnt);
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (!keep[k]) continue;
+            const long long i = base + threadIdx.x + (long long)k * blockDim.x;
             P.oE[1 - cur][o] = P.oE[cur][i];
-            P.oS[1 - cur][o] = slot;
+            P.oS[1 - cur][o] = slot[k];
             P.oZ[1 - cur][o] = P.oZ[cur][i];
+            ++o;
         }
     }
     if (claims) atomicAdd((unsigned long long*)&c->claimed, (unsigned long long)claims);
@@ -1348,7 +1476,8 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
         t += align_up(sizeof(uint32_t) * lo.cap_ht * W, 256);
     }
     t += align_up(sizeof(uint32_t) * lo.cap_ht, 256);                  // remap
-    t += 3 * align_up(sizeof(int32_t) * lo.cap_new, 256);              // nsrc, nflip, ntomb
+    t += align_up(sizeof(int32_t) * lo.cap_new, 256);                  // ntomb
+    t += 2 * align_up(sizeof(int32_t) * c.batch, 256);                 // bcnt, bmin
     t += align_up(sizeof(unsigned long long) * lo.cap_r, 256);         // rkey
     t += align_up(sizeof(int32_t) * lo.cap_r, 256);                    // ridx
     t += align_up(sizeof(Ctl), 256);
@@ -1405,9 +1534,9 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
         tabs[tb2].W = P.W;
     }
     uint32_t* remap = cv.take<uint32_t>(lo.cap_ht);
-    P.nsrc = cv.take<int32_t>(lo.cap_new);
-    P.nflip = cv.take<int32_t>(lo.cap_new);
     P.ntomb = cv.take<int32_t>(lo.cap_new);
+    P.bcnt = cv.take<int32_t>(cfg.batch);
+    P.bmin = cv.take<int32_t>(cfg.batch);
     P.rkey = cv.take<unsigned long long>(lo.cap_r);
     P.ridx = cv.take<int32_t>(lo.cap_r);
     P.rmask = lo.cap_r - 1;
@@ -1469,7 +1598,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
         if (te && (s = te(tctx, st)) != LABS_OK) return s;
         hipLaunchKernelGGL(k_rresolve, gS, tS, 0, st, P);
         hipLaunchKernelGGL(k_rslow, dim3(1), dim3(1), 0, st, P);
-        hipLaunchKernelGGL(k_expand_fin, dim3(1), dim3(1), 0, st, P);
+        hipLaunchKernelGGL(k_expand_fin, dim3(1), dim3(1024), 0, st, P);
         hipLaunchKernelGGL(k_best, dim3(1), dim3(1024), 0, st, P, 0);
         select();
         hipLaunchKernelGGL(k_keep, gS, tS, 0, st, P);
