@@ -46,7 +46,13 @@ namespace {
 constexpr int32_t DEAD = INT32_MAX;
 constexpr uint32_t ST_OPEN = 1, ST_CLOSED = 2, ST_EVICTED = 3;
 constexpr uint64_t ZKEY = 0x6A09E667F3BCC909ull;   // Zobrist stream key
-constexpr int kSelBits = 14;   // radix digit of the energy select (one level covers a 16384-wide range)
+// Radix digit of the energy select.  All energies of one length L are congruent
+// mod 4 (C_k has the parity of L-k, so C_k^2 is 0 mod 4 or 1 mod 8), so the
+// select works on (E - emin)/4.  E <= sum_{j<L} j^2 = (L-1)L(2L-1)/6 < 2^29 for
+// L <= 1023, so (E - emin)/4 < 2^27 and two 14-bit levels always suffice.
+constexpr int kSelBits = 14;
+constexpr int kSelLevels = 2;
+static_assert(2 * kSelBits >= 27, "two select levels must cover (E - emin)/4 for L <= 1023");
 constexpr int kSelBins = 1 << kSelBits;
 constexpr int kSelBlocks = 128;
 constexpr int kSelThreads = 512;
@@ -481,8 +487,8 @@ __global__ __launch_bounds__(512) void k_rresolve(Params P) {
     if (dups) atomicAdd((unsigned long long*)&c->n_dup_new, (unsigned long long)dups);
 }
 
-// Key collisions in R, one at a time (no concurrency, so plain accesses).
-__global__ void k_rslow(Params P) {
+// Key collisions in R, one at a time (a single thread; plain accesses).
+__device__ void rslow(const Params& P) {
     Ctl* c = P.ctl;
     if (c->stop || c->n_slow == 0) return;
     const int cur = c->which;
@@ -506,13 +512,9 @@ __global__ void k_rslow(Params P) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_clear_u64(unsigned long long* p, uint64_t n) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = 0ull;
-}
 
 // ---------------------------------------------------------------- round control
-__global__ void k_round_begin(Params P) {
+__device__ void round_begin(const Params& P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
     if (c->n_live == 0 || c->expansions >= P.X || c->u >= P.T_u) {
@@ -535,6 +537,8 @@ __global__ void k_round_begin(Params P) {
     c->emax = 0;
     c->out_count = 0;
 }
+
+__global__ void k_round_begin(Params P) { round_begin(P); }
 
 // ---------------------------------------------------------------- selection
 // Selects the T smallest live Open entries in key order into flag[].
@@ -573,7 +577,7 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_minmax(Params P) {
 // Level 0 derives the digit layout from [emin, emax]; later levels read it back.
 __device__ __forceinline__ void level_shifts(const Ctl* c, int level, int* hs, int* ls, uint32_t* prefix) {
     if (level == 0) {
-        const uint32_t R = c->emax - c->emin;
+        const uint32_t R = (c->emax - c->emin) >> 2;
         const int nbits = R ? 32 - __clz((int)R) : 0;
         *hs = nbits;
         *ls = nbits > kSelBits ? nbits - kSelBits : 0;
@@ -603,7 +607,7 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_hist(Params P, int level) {
          i += (long long)gridDim.x * blockDim.x) {
         const int32_t e = P.oE[cur][i];
         if (e == DEAD) continue;
-        const uint32_t D = (uint32_t)e - emin;
+        const uint32_t D = ((uint32_t)e - emin) >> 2;
         if (hs < 32 && (D >> hs) != prefix) continue;
         atomicAdd(&h[(D >> ls) & dmask], 1u);
     }
@@ -676,7 +680,7 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
     if (c->stop || !c->sel_enabled) return;
     const int cur = c->which;
     const bool all = c->sel_all;
-    const uint32_t Et = c->emin + c->Dt;
+    const uint32_t Et = c->emin + (c->Dt << 2);
     const long long n_tot = c->n_tot;
     const long long stride = (long long)gridDim.x * blockDim.x * kItems;
     for (long long base = (long long)blockIdx.x * blockDim.x * kItems; base < n_tot; base += stride) {
@@ -923,6 +927,10 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
 __global__ __launch_bounds__(kSelThreads) void k_pop(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
+    // the round table starts empty (its last readers ran in the previous round)
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= P.rmask;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        P.rkey[i] = 0ull;
     const int cur = c->which;
     const long long n_tot = c->n_tot;
     const long long stride = (long long)gridDim.x * blockDim.x * kItems;
@@ -1156,12 +1164,19 @@ expand_kernel_t pick_expand(int L, unsigned* threads) {
     return k_expand_direct;
 }
 
-__global__ __launch_bounds__(1024) void k_expand_fin(Params P) {
+__device__ void best_scan(const Params& P, int initial);
+
+// After the expansion: the key collisions of R (one thread), the pushed count
+// and least energy over the pivots' blocks, the statistics, the capacity-cut
+// setup, and the new best when the round improved it.
+__global__ __launch_bounds__(1024) void k_round_mid(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
     __shared__ long long s_cnt[16];
     __shared__ int32_t s_min[16];
+    __shared__ int s_improved;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t == 0) rslow(P);
     long long cnt = 0;
     int32_t mn = INT32_MAX;
     for (long long b = t; b < c->n_piv; b += blockDim.x) {
@@ -1175,31 +1190,35 @@ __global__ __launch_bounds__(1024) void k_expand_fin(Params P) {
         s_min[wv] = mn;
     }
     __syncthreads();
-    if (t != 0) return;
-    cnt = s_cnt[0];
-    mn = s_min[0];
-    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
-        cnt += s_cnt[k];
-        mn = s_min[k] < mn ? s_min[k] : mn;
+    if (t == 0) {
+        cnt = s_cnt[0];
+        mn = s_min[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            cnt += s_cnt[k];
+            mn = s_min[k] < mn ? s_min[k] : mn;
+        }
+        c->n_tot = c->batch_begin + c->n_piv * P.L;
+        c->batch_minE = mn;
+        c->expansions += c->n_piv;
+        c->n_live -= c->n_piv;
+        const long long n_new = cnt - c->n_dup_new;
+        c->pushes += n_new;
+        c->dups += c->n_piv * P.L - n_new;
+        c->n_live += n_new;
+        if (c->batch_minE < c->best_E) c->improved = 1;
+        else c->u += c->n_piv;
+        // capacity cut setup
+        c->T = P.Q;
+        c->sel_enabled = c->n_live > P.Q ? 1 : 0;
+        c->sel_all = 0;
+        c->emin = UINT32_MAX;
+        c->emax = 0;
+        c->survivors = 0;
+        c->out_count = 0;
+        s_improved = c->improved;
     }
-    c->n_tot = c->batch_begin + c->n_piv * P.L;
-    c->batch_minE = mn;
-    c->expansions += c->n_piv;
-    c->n_live -= c->n_piv;
-    const long long n_new = cnt - c->n_dup_new;
-    c->pushes += n_new;
-    c->dups += c->n_piv * P.L - n_new;
-    c->n_live += n_new;
-    if (c->batch_minE < c->best_E) c->improved = 1;
-    else c->u += c->n_piv;
-    // capacity cut setup
-    c->T = P.Q;
-    c->sel_enabled = c->n_live > P.Q ? 1 : 0;
-    c->sel_all = 0;
-    c->emin = UINT32_MAX;
-    c->emax = 0;
-    c->survivors = 0;
-    c->out_count = 0;
+    __syncthreads();
+    if (s_improved) best_scan(P, 0);
 }
 
 // best = smallest (z, sequence) among live entries in [batch_begin, n_tot) with
@@ -1215,10 +1234,8 @@ __device__ __forceinline__ bool entry_less(const Params& P, int cur, long long a
     return false;
 }
 
-__global__ __launch_bounds__(1024) void k_best(Params P, int initial) {
+__device__ void best_scan(const Params& P, int initial) {
     Ctl* c = P.ctl;
-    if (c->stop) return;
-    if (!initial && !c->improved) return;
     __shared__ long long best[1024];
     const int cur = c->which;
     const long long lo = c->batch_begin;
@@ -1248,6 +1265,13 @@ __global__ __launch_bounds__(1024) void k_best(Params P, int initial) {
             c->u = 0;
         }
     }
+}
+
+__global__ __launch_bounds__(1024) void k_best(Params P, int initial) {
+    Ctl* c = P.ctl;
+    if (c->stop) return;
+    if (!initial && !c->improved) return;
+    best_scan(P, initial);
 }
 
 // Keep the flagged live entries (all live entries when no cut is needed) in the
@@ -1324,7 +1348,7 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
     if (claims) atomicAdd((unsigned long long*)&c->claimed, (unsigned long long)claims);
 }
 
-__global__ void k_round_end(Params P, int count_round) {
+__device__ void round_end(const Params& P, int count_round) {
     Ctl* c = P.ctl;
     if (c->stop) return;
     if (c->sel_enabled) c->evictions += c->n_live - c->survivors;
@@ -1333,6 +1357,14 @@ __global__ void k_round_end(Params P, int count_round) {
     c->which ^= 1;
     c->sel_enabled = 0;
     if (count_round) c->rounds += 1;
+}
+
+__global__ void k_round_end(Params P, int count_round) { round_end(P, count_round); }
+
+// The end of a round and the start of the next in one launch.
+__global__ void k_round_next(Params P) {
+    round_end(P, 1);
+    round_begin(P);
 }
 
 __global__ void k_outputs(Params P, uint32_t* best_seq, int32_t* best_E, labs_step2_stats* st,
@@ -1563,7 +1595,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     const dim3 gS(kGridBlocks), tS(kSelThreads);
     auto select = [&]() {
         hipLaunchKernelGGL(k_sel_minmax, dim3(kSelBlocks), tS, 0, st, P);
-        for (int lv = 0; lv < 3; ++lv) {
+        for (int lv = 0; lv < kSelLevels; ++lv) {
             hipLaunchKernelGGL(k_sel_hist, dim3(kSelBlocks), tS, 0, st, P, lv);
             hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(1024), 0, st, P, lv);
         }
@@ -1588,21 +1620,21 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     labs_status s;
     unsigned eth = 64;
     const expand_kernel_t ek = pick_expand(cfg.L, &eth);
+    // A round: pop selection, pop (also clears R), expansion, R's pending
+    // entries, counts / statistics / best, cut selection, cut, then the end of
+    // the round together with the start of the next.
+    hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, P);
     for (long long r = 0;; ++r) {
-        hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, P);
         select();
         hipLaunchKernelGGL(k_pop, gS, tS, 0, st, P);
-        hipLaunchKernelGGL(k_clear_u64, dim3(1024), dim3(256), 0, st, P.rkey, (uint64_t)lo.cap_r);
         if (tb && (s = tb(tctx, st)) != LABS_OK) return s;
         hipLaunchKernelGGL(ek, dim3((unsigned)cfg.batch), dim3(eth), 0, st, P);
         if (te && (s = te(tctx, st)) != LABS_OK) return s;
         hipLaunchKernelGGL(k_rresolve, gS, tS, 0, st, P);
-        hipLaunchKernelGGL(k_rslow, dim3(1), dim3(1), 0, st, P);
-        hipLaunchKernelGGL(k_expand_fin, dim3(1), dim3(1024), 0, st, P);
-        hipLaunchKernelGGL(k_best, dim3(1), dim3(1024), 0, st, P, 0);
+        hipLaunchKernelGGL(k_round_mid, dim3(1), dim3(1024), 0, st, P);
         select();
         hipLaunchKernelGGL(k_keep, gS, tS, 0, st, P);
-        hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, P, 1);
+        hipLaunchKernelGGL(k_round_next, dim3(1), dim3(1), 0, st, P);
         LABS_LAUNCHED("step2 round");
         if ((r + 1) % kCheck == 0) {
             int32_t flags[2];
