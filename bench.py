@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline-pass", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the uneven-length batched launch measurement")
+    ap.add_argument("--batched-steps", type=int, default=20000)
     ap.add_argument("--no-ab", action="store_true",
                     help="skip the learned-vs-plain comparison at equal wall budgets")
     ap.add_argument("--ab-budget", type=float, default=8.0, help="seconds of walking per arm")
@@ -110,6 +113,46 @@ def cpu_baseline(budget_s: float):
     return {"value": steps * nf / dt, "unit": "flip-evals/s", "cores": 1, "kind": "oracle",
             "sample": "1 walker x %d steps of the L=501 p=16 first-step walk (%d flip-evals, "
                       "%.1f s), definitional energy per neighbour" % (steps, steps * nf, dt)}
+
+
+def batched_measure(a, labs, dev):
+    """Uneven lengths in one launch: every odd L in [301, 449] (75 lengths), 4096
+    walkers each, p = 12, tenure [L/10, L/5], seed 3.  Tiles come from the
+    autotuner (short trials first); the batched call (hipGraph capture included)
+    is timed against one walk_step1 launch per length."""
+    import torch
+    sync = torch.cuda.synchronize
+    Ls = list(range(301, 450, 2))
+    cfgs = [dict(L=x, p=12, steps=a.batched_steps, tenure_lo=x // 10, tenure_hi=x // 5, seed=3,
+                 n_walkers=4096) for x in Ls]
+    sync()
+    t0 = time.perf_counter()
+    labs.autotune_step1(Ls, 12, 4096, 1000, device=dev)
+    sync()
+    t_tune = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res, ws = labs.walk_step1_batch(cfgs, device=dev)
+    sync()
+    t_b = time.perf_counter() - t0
+    evals = sum(int(r.flip_evals.item()) for r in res)
+    del res, ws
+    per_L = {}
+    t_s = 0.0
+    for c in cfgs:
+        sync()
+        t0 = time.perf_counter()
+        r = labs.walk_step1(c["L"], c["p"], c["steps"], c["tenure_lo"], c["tenure_hi"], c["seed"],
+                            c["n_walkers"], device=dev)
+        sync()
+        dt = time.perf_counter() - t0
+        t_s += dt
+        per_L[c["L"]] = int(r.flip_evals.item()) / dt
+    return {"lengths": len(Ls), "L_range": [Ls[0], Ls[-1]], "walkers_per_L": 4096, "p": 12,
+            "steps": a.batched_steps, "flip_evals": evals, "autotune_s": t_tune,
+            "batched_s": t_b, "batched_flip_evals_per_s": evals / t_b,
+            "per_length_launches_s": t_s, "per_length_flip_evals_per_s": evals / t_s,
+            "speedup": t_s / t_b,
+            "per_L_flip_evals_per_s": {str(k): round(v, -6) for k, v in per_L.items()}}
 
 
 def learned_ab(a, labs, dev):
@@ -325,6 +368,7 @@ def main():
                                     "ops_per_neighbour_eval": W2_OPS,
                                     "kernel_share_of_pass": ms2 / 1e3 / t_pass}
 
+    batched = None if a.no_batched else batched_measure(a, labs, dev)
     ab = None
     if not a.no_ab:
         s2_ws = None
@@ -353,6 +397,7 @@ def main():
         "time_to_tau_s": ({k: v["time_to_tau_s"] for k, v in ab["arms"].items()} if ab else None),
         "tau_star": ab["tau_star"] if ab else None,
         "learned_ab": ab,
+        "batched_uneven_L": batched,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -46,6 +46,8 @@ def _run_both(lb, orc, L, cands, B, Q, X, T_u):
     (33, 5, 3, 64, 150, 12),               # dynamic depth stop
     (101, 6, 64, 3000, 1500, 300),         # second configuration's length
     (200, 2, 32, 500, 400, 1 << 40),
+    (701, 2, 4, 200, 16, 1 << 40),         # direct expansion (lags beyond the bit-sliced kernels)
+    (1023, 2, 2, 100, 8, 1 << 40),         # longest accepted length
 ])
 def test_step2_parity(lb, orc, L, n, B, Q, X, T_u):
     cands = li.random_pm1(L * 7 + n, n, L)
