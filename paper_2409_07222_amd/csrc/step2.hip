@@ -62,6 +62,7 @@ constexpr int kPad = 1024;
 constexpr int kSv = kMaxL + 2 * kPad + 2;
 constexpr int kExThreads = 256;
 constexpr int kItems = 8;                            // list entries per thread per pass (filters)
+constexpr int kKeepItems = 2;                        // the cut: fewer, so inserts overlap across threads
 
 struct Table {
     unsigned long long* hkey;
@@ -92,6 +93,7 @@ struct Ctl {
     long long claimed, claimed_new;
     long long out_count;
     long long n_dup_new;   // new entries found to repeat another new entry of the round
+    uint32_t blo, bhi;     // bounds of the live Open energies (blo is one of them)
 };
 
 // A pending insertion: the slot whose key matched, the source of the sequence
@@ -122,6 +124,7 @@ struct Params {
     int32_t* ntomb;        // slot of the sequence's evicted tombstone, or -1
     int32_t* bcnt;         // [B] neighbours pushed by pivot b
     int32_t* bmin;         // [B] their least energy
+    int32_t* bmax;         // [B] their greatest energy
     // per-round dedupe table: Zobrist key -> Open position of the first holder
     unsigned long long* rkey;
     int32_t* ridx;
@@ -272,7 +275,7 @@ __device__ __forceinline__ void push_pending(const Params& P, bool take, const P
 // DEAD when H holds its sequence as OPEN or CLOSED, else a new entry entered into
 // R.  Every thread of the block calls it; `taken` and `mn` accumulate per thread.
 __device__ void stage_neighbour(const Params& P, bool valid, unsigned long long key, int ps, int flip,
-                                int32_t En, int& taken, int32_t& mn) {
+                                int32_t En, int& taken, int32_t& mn, int32_t& mx) {
     Ctl* c = P.ctl;
     int tomb = -1;
     bool take = false;
@@ -311,6 +314,7 @@ __device__ void stage_neighbour(const Params& P, bool valid, unsigned long long 
             P.ntomb[j] = tomb;
             ++taken;
             mn = En < mn ? En : mn;
+            mx = En > mx ? En : mx;
             uint64_t r = key & P.rmask;
             for (uint64_t probe = 0; probe <= P.rmask; ++probe, r = (r + 1) & P.rmask) {
                 const unsigned long long prev = atomicCAS(&P.rkey[r], 0ull, key);
@@ -330,27 +334,31 @@ __device__ void stage_neighbour(const Params& P, bool valid, unsigned long long 
 }
 
 // The block's pushed count and least energy (every thread calls it once).
-__device__ void stage_finish(const Params& P, int taken, int32_t mn) {
+__device__ void stage_finish(const Params& P, int taken, int32_t mn, int32_t mx) {
     __shared__ int s_cnt[16];
-    __shared__ int32_t s_min[16];
+    __shared__ int32_t s_min[16], s_max[16];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
     taken = __ockl_wfred_add_i32(taken);
     mn = __ockl_wfred_min_i32(mn);
+    mx = (int32_t)__ockl_wfred_max_u32((uint32_t)mx);   // energies are >= 0
     if (lane == 0) {
         s_cnt[wv] = taken;
         s_min[wv] = mn;
+        s_max[wv] = mx;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         int t = 0;
-        int32_t m = INT32_MAX;
+        int32_t m = INT32_MAX, x = 0;
         for (int k = 0; k < nw; ++k) {
             t += s_cnt[k];
             m = s_min[k] < m ? s_min[k] : m;
+            x = s_max[k] > x ? s_max[k] : x;
         }
         P.bcnt[blockIdx.x] = t;
         P.bmin[blockIdx.x] = m;
+        P.bmax[blockIdx.x] = x;
     }
 }
 
@@ -533,8 +541,8 @@ __device__ void round_begin(const Params& P) {
     c->batch_begin = c->n_tot;
     c->batch_minE = INT32_MAX;
     c->improved = 0;
-    c->emin = UINT32_MAX;
-    c->emax = 0;
+    c->emin = c->blo;   // the live entries are a subset of the last cut's survivors
+    c->emax = c->bhi;
     c->out_count = 0;
 }
 
@@ -988,7 +996,7 @@ __global__ __launch_bounds__(64) void k_expand_direct(Params P) {
         if (sv[kPad + x] > 0) hp ^= zob(x - 1);
     for (int o = 32; o > 0; o >>= 1) hp ^= __shfl_xor(hp, o, 64);
     int taken = 0;
-    int32_t mn = INT32_MAX;
+    int32_t mn = INT32_MAX, mx = 0;
     for (int r0 = 0; r0 < L; r0 += 64) {
         const int i = 1 + r0 + lane;
         const bool valid = i <= L;
@@ -1005,9 +1013,9 @@ __global__ __launch_bounds__(64) void k_expand_direct(Params P) {
             En = Ep - 4 * si * g + 4 * q;
             key = (hp ^ zob(i - 1)) | 1ull;
         }
-        stage_neighbour(P, valid, key, ps, i, En, taken, mn);
+        stage_neighbour(P, valid, key, ps, i, En, taken, mn, mx);
     }
-    stage_finish(P, taken, mn);
+    stage_finish(P, taken, mn, mx);
 }
 
 // Bit-sliced expansion, 4 wavefronts per pivot.  For the single flip of s_i:
@@ -1127,7 +1135,7 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
         for (int r = 0; r < R2; ++r) H[r] += wgt * (int)acc[r];
     }
     int taken = 0;
-    int32_t mn = INT32_MAX;
+    int32_t mn = INT32_MAX, mx = 0;
 #pragma unroll
     for (int r = 0; r < R2; ++r) {
         const int i0 = 1 + lane + 64 * (wv + 4 * r);
@@ -1146,9 +1154,9 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
         const int Q = (L - 1) + 2 * (M - 2 * dis);
         const int32_t En = Ep - 4 * si * G + 4 * Q;
         const unsigned long long key = (hp ^ zob(i - 1)) | 1ull;
-        stage_neighbour(P, valid, key, ps, i, En, taken, mn);
+        stage_neighbour(P, valid, key, ps, i, En, taken, mn, mx);
     }
-    stage_finish(P, taken, mn);
+    stage_finish(P, taken, mn, mx);
 }
 
 typedef void (*expand_kernel_t)(Params);
@@ -1173,29 +1181,34 @@ __global__ __launch_bounds__(1024) void k_round_mid(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
     __shared__ long long s_cnt[16];
-    __shared__ int32_t s_min[16];
+    __shared__ int32_t s_min[16], s_max[16];
     __shared__ int s_improved;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     if (t == 0) rslow(P);
     long long cnt = 0;
-    int32_t mn = INT32_MAX;
+    int32_t mn = INT32_MAX, mx = 0;
     for (long long b = t; b < c->n_piv; b += blockDim.x) {
         cnt += P.bcnt[b];
         mn = P.bmin[b] < mn ? P.bmin[b] : mn;
+        mx = P.bmax[b] > mx ? P.bmax[b] : mx;
     }
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
     mn = __ockl_wfred_min_i32(mn);
+    mx = (int32_t)__ockl_wfred_max_u32((uint32_t)mx);
     if (lane == 0) {
         s_cnt[wv] = cnt;
         s_min[wv] = mn;
+        s_max[wv] = mx;
     }
     __syncthreads();
     if (t == 0) {
         cnt = s_cnt[0];
         mn = s_min[0];
+        mx = s_max[0];
         for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
             cnt += s_cnt[k];
             mn = s_min[k] < mn ? s_min[k] : mn;
+            mx = s_max[k] > mx ? s_max[k] : mx;
         }
         c->n_tot = c->batch_begin + c->n_piv * P.L;
         c->batch_minE = mn;
@@ -1207,12 +1220,13 @@ __global__ __launch_bounds__(1024) void k_round_mid(Params P) {
         c->n_live += n_new;
         if (c->batch_minE < c->best_E) c->improved = 1;
         else c->u += c->n_piv;
-        // capacity cut setup
+        // capacity cut setup; energy bounds: the live entries before the round
+        // and this round's pushes
         c->T = P.Q;
         c->sel_enabled = c->n_live > P.Q ? 1 : 0;
         c->sel_all = 0;
-        c->emin = UINT32_MAX;
-        c->emax = 0;
+        c->emin = (uint32_t)mn < c->blo ? (uint32_t)mn : c->blo;
+        c->emax = (uint32_t)mx > c->bhi ? (uint32_t)mx : c->bhi;
         c->survivors = 0;
         c->out_count = 0;
         s_improved = c->improved;
@@ -1286,13 +1300,13 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
     const Table& H = P.H;
     const long long n_tot = c->n_tot, bb = c->batch_begin;
     long long claims = 0;
-    const long long stride = (long long)gridDim.x * blockDim.x * kItems;
-    for (long long base = (long long)blockIdx.x * blockDim.x * kItems; base < n_tot; base += stride) {
-        int slot[kItems];
-        bool keep[kItems];
+    const long long stride = (long long)gridDim.x * blockDim.x * kKeepItems;
+    for (long long base = (long long)blockIdx.x * blockDim.x * kKeepItems; base < n_tot; base += stride) {
+        int slot[kKeepItems];
+        bool keep[kKeepItems];
         int cnt = 0;
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
+        for (int k = 0; k < kKeepItems; ++k) {
             const long long i = base + threadIdx.x + (long long)k * blockDim.x;
             keep[k] = false;
             slot[k] = -1;
@@ -1336,7 +1350,7 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
         }
         long long o = block_append_n(&c->survivors, cnt);
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
+        for (int k = 0; k < kKeepItems; ++k) {
             if (!keep[k]) continue;
             const long long i = base + threadIdx.x + (long long)k * blockDim.x;
             P.oE[1 - cur][o] = P.oE[cur][i];
@@ -1351,7 +1365,14 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
 __device__ void round_end(const Params& P, int count_round) {
     Ctl* c = P.ctl;
     if (c->stop) return;
-    if (c->sel_enabled) c->evictions += c->n_live - c->survivors;
+    if (c->sel_enabled) {
+        c->evictions += c->n_live - c->survivors;
+        c->blo = c->emin;
+        c->bhi = c->emin + (c->Dt << 2);   // survivors lie at or below the cut's energy
+    } else {
+        c->blo = c->emin < c->blo ? c->emin : c->blo;
+        c->bhi = c->emax > c->bhi ? c->emax : c->bhi;
+    }
     c->n_live = c->survivors;
     c->n_tot = c->survivors;
     c->which ^= 1;
@@ -1458,6 +1479,28 @@ __global__ void k_seed_fin(Params P) {
 __global__ void k_seed_best_setup(Ctl* c) {
     c->batch_begin = 0;
     c->batch_minE = INT32_MAX;
+    c->blo = UINT32_MAX;
+    c->bhi = 0;
+}
+
+// Exact energy bounds of the live entries after seeding.
+__global__ __launch_bounds__(kSelThreads) void k_live_bounds(Params P) {
+    Ctl* c = P.ctl;
+    const int cur = c->which;
+    uint32_t mn = UINT32_MAX, mx = 0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < c->n_tot;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int32_t e = P.oE[cur][i];
+        if (e == DEAD) continue;
+        mn = (uint32_t)e < mn ? (uint32_t)e : mn;
+        mx = (uint32_t)e > mx ? (uint32_t)e : mx;
+    }
+    mn = (uint32_t)__ockl_wfred_min_i32((int)(mn > (uint32_t)INT32_MAX ? (uint32_t)INT32_MAX : mn));
+    mx = __ockl_wfred_max_u32(mx);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&c->blo, mn);
+        atomicMax(&c->bhi, mx);
+    }
 }
 
 // Minimum E over live entries into batch_minE (the initial best's energy).
@@ -1509,7 +1552,7 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     }
     t += align_up(sizeof(uint32_t) * lo.cap_ht, 256);                  // remap
     t += align_up(sizeof(int32_t) * lo.cap_new, 256);                  // ntomb
-    t += 2 * align_up(sizeof(int32_t) * c.batch, 256);                 // bcnt, bmin
+    t += 3 * align_up(sizeof(int32_t) * c.batch, 256);                 // bcnt, bmin, bmax
     t += align_up(sizeof(unsigned long long) * lo.cap_r, 256);         // rkey
     t += align_up(sizeof(int32_t) * lo.cap_r, 256);                    // ridx
     t += align_up(sizeof(Ctl), 256);
@@ -1569,6 +1612,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.ntomb = cv.take<int32_t>(lo.cap_new);
     P.bcnt = cv.take<int32_t>(cfg.batch);
     P.bmin = cv.take<int32_t>(cfg.batch);
+    P.bmax = cv.take<int32_t>(cfg.batch);
     P.rkey = cv.take<unsigned long long>(lo.cap_r);
     P.ridx = cv.take<int32_t>(lo.cap_r);
     P.rmask = lo.cap_r - 1;
@@ -1593,8 +1637,10 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     LABS_HIP(hipMemsetAsync(P.best_seq, 0, sizeof(uint32_t) * 32, st));
     LABS_HIP(hipMemsetAsync(P.ghist, 0, sizeof(uint32_t) * kSelBins, st));
     const dim3 gS(kGridBlocks), tS(kSelThreads);
-    auto select = [&]() {
-        hipLaunchKernelGGL(k_sel_minmax, dim3(kSelBlocks), tS, 0, st, P);
+    // Selection; rounds take their energy bounds from the control block instead
+    // of a min/max pass.
+    auto select = [&](bool minmax) {
+        if (minmax) hipLaunchKernelGGL(k_sel_minmax, dim3(kSelBlocks), tS, 0, st, P);
         for (int lv = 0; lv < kSelLevels; ++lv) {
             hipLaunchKernelGGL(k_sel_hist, dim3(kSelBlocks), tS, 0, st, P, lv);
             hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(1024), 0, st, P, lv);
@@ -1609,11 +1655,12 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     hipLaunchKernelGGL(k_resolve, gS, tS, 0, st, P);
     hipLaunchKernelGGL(k_slow, dim3(1), dim3(1), 0, st, P);
     hipLaunchKernelGGL(k_seed_fin, dim3(1), dim3(1), 0, st, P);
-    select();
+    select(true);
     hipLaunchKernelGGL(k_keep, gS, tS, 0, st, P);
     hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, P, 0);
     hipLaunchKernelGGL(k_seed_best_setup, dim3(1), dim3(1), 0, st, P.ctl);
     hipLaunchKernelGGL(k_min_live, gS, tS, 0, st, P);
+    hipLaunchKernelGGL(k_live_bounds, gS, tS, 0, st, P);
     hipLaunchKernelGGL(k_best, dim3(1), dim3(1024), 0, st, P, 1);
     LABS_LAUNCHED("step2 seeding");
 
@@ -1625,14 +1672,14 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     // the round together with the start of the next.
     hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, P);
     for (long long r = 0;; ++r) {
-        select();
+        select(false);
         hipLaunchKernelGGL(k_pop, gS, tS, 0, st, P);
         if (tb && (s = tb(tctx, st)) != LABS_OK) return s;
         hipLaunchKernelGGL(ek, dim3((unsigned)cfg.batch), dim3(eth), 0, st, P);
         if (te && (s = te(tctx, st)) != LABS_OK) return s;
         hipLaunchKernelGGL(k_rresolve, gS, tS, 0, st, P);
         hipLaunchKernelGGL(k_round_mid, dim3(1), dim3(1024), 0, st, P);
-        select();
+        select(false);
         hipLaunchKernelGGL(k_keep, gS, tS, 0, st, P);
         hipLaunchKernelGGL(k_round_next, dim3(1), dim3(1), 0, st, P);
         LABS_LAUNCHED("step2 round");
