@@ -66,12 +66,18 @@ constexpr int kKeepItems = 2;                        // the cut: fewer, so inser
 
 struct Table {
     unsigned long long* hkey;
+    uint8_t* tag;          // 0 for an empty slot, else tag_of(key): a byte-wide filter
     uint32_t* state;
     int32_t* E;
     uint32_t* seq;
     uint64_t mask;
     int32_t W;
 };
+
+// One byte per slot (64 MB at 2^26 slots, small enough to stay in the on-package
+// cache): read-only probes stop at an empty tag and read the 8-byte key only on
+// a tag match.  Written once, right after the slot's key is claimed.
+__device__ __forceinline__ uint8_t tag_of(unsigned long long key) { return (uint8_t)(0x80u | (key >> 57)); }
 
 struct Ctl {
     // persistent
@@ -112,7 +118,8 @@ struct Params {
     int32_t* oS[2];
     unsigned long long* oZ[2];   // Zobrist key of each Open entry (tie order without table reads)
     uint32_t* flag;        // [cap_o]
-    int32_t* cand[2];      // [cap_o] each
+    int32_t* cand[2];      // [cap_o] each: Open positions of tied entries
+    unsigned long long* candz[2];   // [cap_o] each: their Zobrist keys
     int32_t* piv;          // [B]
     uint32_t* ghist;       // [kSelBins], zero between selection levels
     uint32_t* best_seq;    // [W] copy of the best sequence
@@ -234,6 +241,7 @@ __device__ int claim_or_pend(const Params& P, unsigned long long key, int src, i
     for (uint64_t probe = 0; probe <= H.mask; ++probe) {
         const unsigned long long prev = atomicCAS(&H.hkey[s], 0ull, key);
         if (prev == 0ull) {
+            H.tag[s] = tag_of(key);
             for (int w = 0; w < H.W; ++w) H.seq[s * H.W + w] = src_word(P, src, flip, w);
             H.E[s] = E;
             H.state[s] = ST_OPEN;
@@ -282,11 +290,12 @@ __device__ void stage_neighbour(const Params& P, bool valid, unsigned long long 
     if (valid) {
         take = true;
         const Table& H = P.H;
+        const uint8_t tg = tag_of(key);
         uint64_t s = key & H.mask;
         for (uint64_t probe = 0; probe <= H.mask; ++probe, s = (s + 1) & H.mask) {
-            const unsigned long long k = H.hkey[s];
-            if (k == 0ull) break;
-            if (k != key) continue;
+            const uint8_t ts = H.tag[s];
+            if (ts == 0) break;
+            if (ts != tg || H.hkey[s] != key) continue;
             bool eq = true;
             for (int w = 0; w < H.W; ++w)
                 if (H.seq[s * H.W + w] != src_word(P, ps, flip, w)) {
@@ -315,9 +324,13 @@ __device__ void stage_neighbour(const Params& P, bool valid, unsigned long long 
             ++taken;
             mn = En < mn ? En : mn;
             mx = En > mx ? En : mx;
+            // R slots only go from 0 to a key within a round, so a plain read that
+            // shows another key is final; only empty-looking slots are claimed by
+            // CAS (a stale 0 just makes the CAS report the key now there).
             uint64_t r = key & P.rmask;
             for (uint64_t probe = 0; probe <= P.rmask; ++probe, r = (r + 1) & P.rmask) {
-                const unsigned long long prev = atomicCAS(&P.rkey[r], 0ull, key);
+                unsigned long long prev = P.rkey[r];
+                if (prev == 0ull) prev = atomicCAS(&P.rkey[r], 0ull, key);
                 if (prev == 0ull) {
                     P.ridx[r] = (int32_t)o;
                     break;
@@ -434,6 +447,7 @@ __global__ void k_slow(Params P) {
         for (uint64_t probe = 0; probe <= H.mask; ++probe, s = (s + 1) & H.mask) {
             if (H.hkey[s] == 0ull) {
                 H.hkey[s] = key;
+                H.tag[s] = tag_of(key);
                 for (int w = 0; w < H.W; ++w) H.seq[s * H.W + w] = src_word(P, pd.src, pd.flip, w);
                 H.E[s] = pd.E;
                 H.state[s] = ST_OPEN;
@@ -712,7 +726,12 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
         long long o = block_append_n(&c->out_count, cnt);
 #pragma unroll
         for (int k = 0; k < kItems; ++k)
-            if (tie[k]) P.cand[0][o++] = (int32_t)(base + threadIdx.x + (long long)k * blockDim.x);
+            if (tie[k]) {
+                const long long i = base + threadIdx.x + (long long)k * blockDim.x;
+                P.cand[0][o] = (int32_t)i;
+                P.candz[0][o] = P.oZ[cur][i];
+                ++o;
+            }
     }
 }
 
@@ -772,7 +791,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         if (t == 0) s_m2 = 0;
         __syncthreads();
         for (int q = t; q < m; q += blockDim.x)
-            atomicAdd(&h[(P.oZ[cur][P.cand[src][q]] >> sh) & 255ull], 1u);
+            atomicAdd(&h[(P.candz[src][q] >> sh) & 255ull], 1u);
         __syncthreads();
         if (t < 64) {
             const uint32_t c0 = h[4 * t], c1 = h[4 * t + 1], c2 = h[4 * t + 2], c3 = h[4 * t + 3];
@@ -795,9 +814,15 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         const int v = s_v;
         for (int q = t; q < m; q += blockDim.x) {
             const int idx = P.cand[src][q];
-            const int dgt = (int)((P.oZ[cur][idx] >> sh) & 255ull);
-            if (dgt < v) P.flag[idx] = 1;
-            else if (dgt == v) P.cand[1 - src][atomicAdd(&s_m2, 1)] = idx;
+            const unsigned long long z = P.candz[src][q];
+            const int dgt = (int)((z >> sh) & 255ull);
+            if (dgt < v) {
+                P.flag[idx] = 1;
+            } else if (dgt == v) {
+                const int o2 = atomicAdd(&s_m2, 1);
+                P.cand[1 - src][o2] = idx;
+                P.candz[1 - src][o2] = z;
+            }
         }
         __syncthreads();
         m = s_m2;
@@ -810,9 +835,8 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         // Fast path: the tied entries' keys in LDS, one byte of the key per pass.
         int b = 0;
         for (int q = t; q < m; q += blockDim.x) {
-            const int idx = P.cand[src][q];
-            is[0][q] = idx;
-            zs[0][q] = P.oZ[cur][idx];
+            is[0][q] = P.cand[src][q];
+            zs[0][q] = P.candz[src][q];
         }
         __syncthreads();
         while (pos < 8 && r > 0 && r < m) {
@@ -1330,6 +1354,7 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
                         for (uint64_t probe = 0; probe <= H.mask; ++probe, s2 = (s2 + 1) & H.mask)
                             if (atomicCAS(&H.hkey[s2], 0ull, key) == 0ull) {
                                 slot[k] = (int)s2;
+                                H.tag[s2] = tag_of(key);
                                 break;
                             }
                         if (slot[k] < 0) {
@@ -1431,6 +1456,7 @@ __global__ void k_rebuild(Table src, Table dst, uint32_t* remap, Ctl* c) {
             if (atomicCAS(&dst.hkey[s], 0ull, key) == 0ull) break;
             s = (s + 1) & dst.mask;
         }
+        dst.tag[s] = tag_of(key);
         for (int w = 0; w < src.W; ++w) dst.seq[s * dst.W + w] = src.seq[i * src.W + w];
         dst.E[s] = src.E[i];
         dst.state[s] = st;
@@ -1542,10 +1568,11 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     const long long live = n_cand + c.max_expansions + c.pq_capacity + BL;
     lo.cap_ht = next_pow2((uint64_t)(4 * (live + (long long)kCheck * BL) + 1024));
     lo.cap_new = BL + 1024;
-    lo.cap_r = next_pow2((uint64_t)(2 * lo.cap_new));
+    lo.cap_r = next_pow2((uint64_t)(4 * lo.cap_new));   // load <= 1/4: short probe runs
     size_t t = 0;
     for (int tb = 0; tb < 2; ++tb) {
         t += align_up(sizeof(unsigned long long) * lo.cap_ht, 256);
+        t += align_up(lo.cap_ht, 256);                                   // tag
         t += align_up(sizeof(uint32_t) * lo.cap_ht, 256);
         t += align_up(sizeof(int32_t) * lo.cap_ht, 256);
         t += align_up(sizeof(uint32_t) * lo.cap_ht * W, 256);
@@ -1561,6 +1588,7 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     t += 2 * align_up(sizeof(unsigned long long) * lo.cap_o, 256);     // oZ
     t += align_up(sizeof(uint32_t) * lo.cap_o, 256);                   // flag
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // cand
+    t += 2 * align_up(sizeof(unsigned long long) * lo.cap_o, 256);     // candz
     t += align_up(sizeof(int32_t) * c.batch, 256);                     // piv
     t += align_up(sizeof(uint32_t) * kSelBins, 256);                   // select histogram
     t += align_up(sizeof(uint32_t) * 32, 256);                         // best sequence
@@ -1602,6 +1630,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     Table tabs[2];
     for (int tb2 = 0; tb2 < 2; ++tb2) {
         tabs[tb2].hkey = cv.take<unsigned long long>(lo.cap_ht);
+        tabs[tb2].tag = cv.take<uint8_t>(lo.cap_ht);
         tabs[tb2].state = cv.take<uint32_t>(lo.cap_ht);
         tabs[tb2].E = cv.take<int32_t>(lo.cap_ht);
         tabs[tb2].seq = cv.take<uint32_t>(lo.cap_ht * P.W);
@@ -1624,6 +1653,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     for (int b = 0; b < 2; ++b) P.oZ[b] = cv.take<unsigned long long>(lo.cap_o);
     P.flag = cv.take<uint32_t>(lo.cap_o);
     for (int b = 0; b < 2; ++b) P.cand[b] = cv.take<int32_t>(lo.cap_o);
+    for (int b = 0; b < 2; ++b) P.candz[b] = cv.take<unsigned long long>(lo.cap_o);
     P.piv = cv.take<int32_t>(cfg.batch);
     P.ghist = cv.take<uint32_t>((size_t)kSelBins);
     P.best_seq = cv.take<uint32_t>(32);
@@ -1633,6 +1663,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     if (!cv.ok()) return invalid("workspace layout overflow");
 
     LABS_HIP(hipMemsetAsync(P.H.hkey, 0, sizeof(unsigned long long) * lo.cap_ht, st));
+    LABS_HIP(hipMemsetAsync(P.H.tag, 0, lo.cap_ht, st));
     LABS_HIP(hipMemsetAsync(P.H.state, 0, sizeof(uint32_t) * lo.cap_ht, st));
     LABS_HIP(hipMemsetAsync(P.best_seq, 0, sizeof(uint32_t) * 32, st));
     LABS_HIP(hipMemsetAsync(P.ghist, 0, sizeof(uint32_t) * kSelBins, st));
@@ -1697,6 +1728,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
             if ((uint64_t)claimed * 2 >= lo.cap_ht) {
                 Table& dst = tabs[1 - tcur];
                 LABS_HIP(hipMemsetAsync(dst.hkey, 0, sizeof(unsigned long long) * lo.cap_ht, st));
+                LABS_HIP(hipMemsetAsync(dst.tag, 0, lo.cap_ht, st));
                 LABS_HIP(hipMemsetAsync(dst.state, 0, sizeof(uint32_t) * lo.cap_ht, st));
                 hipLaunchKernelGGL(k_rebuild, dim3(8192), dim3(256), 0, st, tabs[tcur], dst, remap, P.ctl);
                 hipLaunchKernelGGL(k_remap, gS, tS, 0, st, P, remap);
