@@ -98,7 +98,6 @@ struct Ctl {
     // table occupancy (claimed slots, tombstones included) and rebuild scratch
     long long claimed, claimed_new;
     long long out_count;
-    long long n_dup_new;   // new entries found to repeat another new entry of the round
     uint32_t blo, bhi;     // bounds of the live Open energies (blo is one of them)
 };
 
@@ -132,10 +131,8 @@ struct Params {
     int32_t* bcnt;         // [B] neighbours pushed by pivot b
     int32_t* bmin;         // [B] their least energy
     int32_t* bmax;         // [B] their greatest energy
-    // per-round dedupe table: Zobrist key -> Open position of the first holder
-    unsigned long long* rkey;
-    int32_t* ridx;
-    uint64_t rmask;
+    // [B*L] 1 when neighbour (b, i) repeats a neighbour of a lower-numbered pivot
+    uint8_t* repeat;
 };
 
 __device__ __forceinline__ uint64_t zob(int i) { return sm64_at(ZKEY, (uint64_t)i); }
@@ -280,15 +277,17 @@ __device__ __forceinline__ void push_pending(const Params& P, bool take, const P
 
 // A generated neighbour (flip position `flip` of the block's pivot, slot ps;
 // energy En; Zobrist key): its Open position is fixed by (pivot, flip).  It is
-// DEAD when H holds its sequence as OPEN or CLOSED, else a new entry entered into
-// R.  Every thread of the block calls it; `taken` and `mn` accumulate per thread.
+// DEAD when a lower-numbered pivot of the round produces the same sequence
+// (k_repeats) or when H holds its sequence as OPEN or CLOSED; otherwise it is a
+// new entry.  `taken`, `mn` and `mx` accumulate per thread.
 __device__ void stage_neighbour(const Params& P, bool valid, unsigned long long key, int ps, int flip,
                                 int32_t En, int& taken, int32_t& mn, int32_t& mx) {
+    if (!valid) return;
     Ctl* c = P.ctl;
+    const long long j = (long long)blockIdx.x * P.L + (flip - 1);
     int tomb = -1;
-    bool take = false;
-    if (valid) {
-        take = true;
+    bool take = !P.repeat[j];
+    if (take) {
         const Table& H = P.H;
         const uint8_t tg = tag_of(key);
         uint64_t s = key & H.mask;
@@ -308,42 +307,19 @@ __device__ void stage_neighbour(const Params& P, bool valid, unsigned long long 
             break;
         }
     }
-    bool pend = false;
-    Pend pd{0, 0, 0, 0};
-    if (valid) {
-        const int cur = c->which;
-        const long long j = (long long)blockIdx.x * P.L + (flip - 1);
-        const long long o = c->batch_begin + j;
-        if (!take) {
-            P.oE[cur][o] = DEAD;
-        } else {
-            P.oE[cur][o] = En;
-            P.oS[cur][o] = -1;
-            P.oZ[cur][o] = key;
-            P.ntomb[j] = tomb;
-            ++taken;
-            mn = En < mn ? En : mn;
-            mx = En > mx ? En : mx;
-            // R slots only go from 0 to a key within a round, so a plain read that
-            // shows another key is final; only empty-looking slots are claimed by
-            // CAS (a stale 0 just makes the CAS report the key now there).
-            uint64_t r = key & P.rmask;
-            for (uint64_t probe = 0; probe <= P.rmask; ++probe, r = (r + 1) & P.rmask) {
-                unsigned long long prev = P.rkey[r];
-                if (prev == 0ull) prev = atomicCAS(&P.rkey[r], 0ull, key);
-                if (prev == 0ull) {
-                    P.ridx[r] = (int32_t)o;
-                    break;
-                }
-                if (prev == key) {
-                    pend = true;
-                    pd = Pend{(int32_t)r, (int32_t)o, 0, En};
-                    break;
-                }
-            }
-        }
+    const int cur = c->which;
+    const long long o = c->batch_begin + j;
+    if (!take) {
+        P.oE[cur][o] = DEAD;
+        return;
     }
-    push_pending(P, pend, pd);
+    P.oE[cur][o] = En;
+    P.oS[cur][o] = -1;
+    P.oZ[cur][o] = key;
+    P.ntomb[j] = tomb;
+    ++taken;
+    mn = En < mn ? En : mn;
+    mx = En > mx ? En : mx;
 }
 
 // The block's pushed count and least energy (every thread calls it once).
@@ -480,60 +456,41 @@ __global__ void k_slow(Params P) {
     }
 }
 
-// Pending entries of R: a new entry whose key was already in R repeats that
-// holder's sequence (dropped) or collides with it (finished in k_rslow).
-__global__ __launch_bounds__(512) void k_rresolve(Params P) {
+// Repeats within a round: a neighbour y = p_b (+) e_i equals a neighbour of pivot
+// b' exactly when p_b (+) p_b' = e_i (+) e_i' with i != i', i.e. the two pivots
+// are at Hamming distance 2 and i is one of the two positions where they differ
+// (y equal to a pivot itself is a CLOSED entry of H).  Block b compares its pivot
+// with every lower-numbered pivot and marks its copies of the shared neighbours,
+// so of every repeated sequence exactly the copy of the lowest pivot is kept.
+__global__ __launch_bounds__(256) void k_repeats(Params P) {
     Ctl* c = P.ctl;
-    if (c->stop) return;
-    const int cur = c->which;
-    const long long n = c->n_pend < P.cap_pend ? c->n_pend : P.cap_pend;
-    long long dups = 0;
-    for (long long base = (long long)blockIdx.x * blockDim.x; base < n;
-         base += (long long)gridDim.x * blockDim.x) {
-        const long long q = base + threadIdx.x;
-        bool coll = false;
-        Pend pd{0, 0, 0, 0};
-        if (q < n) {
-            pd = P.pend[q];
-            const long long holder = P.ridx[pd.slot];
-            if (entries_equal(P, -1, pd.src, -1, holder)) {
-                P.oE[cur][pd.src] = DEAD;
-                ++dups;
-            } else {
-                coll = true;
+    const long long b = blockIdx.x;
+    if (c->stop || b >= c->n_piv) return;
+    const int L = P.L, W = P.W;
+    __shared__ uint32_t mine[32];
+    uint8_t* row = P.repeat + b * L;
+    for (int i = threadIdx.x; i < L; i += blockDim.x) row[i] = 0;
+    if (threadIdx.x < (unsigned)W) mine[threadIdx.x] = P.H.seq[(size_t)P.piv[b] * W + threadIdx.x];
+    __syncthreads();
+    for (long long q = threadIdx.x; q < b; q += blockDim.x) {
+        const uint32_t* other = P.H.seq + (size_t)P.piv[q] * W;
+        int d = 0, first = -1, second = -1;
+        for (int w = 0; w < W && d <= 2; ++w) {
+            uint32_t x = mine[w] ^ other[w];
+            while (x && d <= 2) {
+                const int pos = 32 * w + __clz((int)x) + 1;   // 1-based position, MSB first
+                if (d == 0) first = pos;
+                else if (d == 1) second = pos;
+                ++d;
+                x &= ~(0x80000000u >> (pos - 1 - 32 * w));
             }
         }
-        const long long o = block_append(&c->n_slow, coll);
-        if (coll && o < P.cap_pend) P.slow[o] = pd;
-    }
-    if (dups) atomicAdd((unsigned long long*)&c->n_dup_new, (unsigned long long)dups);
-}
-
-// Key collisions in R, one at a time (a single thread; plain accesses).
-__device__ void rslow(const Params& P) {
-    Ctl* c = P.ctl;
-    if (c->stop || c->n_slow == 0) return;
-    const int cur = c->which;
-    const long long n = c->n_slow < P.cap_pend ? c->n_slow : P.cap_pend;
-    for (long long q = 0; q < n; ++q) {
-        const Pend pd = P.slow[q];
-        const unsigned long long key = P.rkey[pd.slot];
-        uint64_t r = (pd.slot + 1) & P.rmask;
-        for (uint64_t probe = 0; probe <= P.rmask; ++probe, r = (r + 1) & P.rmask) {
-            if (P.rkey[r] == 0ull) {
-                P.rkey[r] = key;
-                P.ridx[r] = pd.src;
-                break;
-            }
-            if (P.rkey[r] != key) continue;
-            if (!entries_equal(P, -1, pd.src, -1, P.ridx[r])) continue;
-            P.oE[cur][pd.src] = DEAD;
-            c->n_dup_new += 1;
-            break;
+        if (d == 2) {
+            row[first - 1] = 1;
+            row[second - 1] = 1;
         }
     }
 }
-
 
 // ---------------------------------------------------------------- round control
 __device__ void round_begin(const Params& P) {
@@ -551,7 +508,6 @@ __device__ void round_begin(const Params& P) {
     c->n_piv = 0;
     c->n_pend = 0;
     c->n_slow = 0;
-    c->n_dup_new = 0;
     c->batch_begin = c->n_tot;
     c->batch_minE = INT32_MAX;
     c->improved = 0;
@@ -959,10 +915,6 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
 __global__ __launch_bounds__(kSelThreads) void k_pop(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
-    // the round table starts empty (its last readers ran in the previous round)
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= P.rmask;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        P.rkey[i] = 0ull;
     const int cur = c->which;
     const long long n_tot = c->n_tot;
     const long long stride = (long long)gridDim.x * blockDim.x * kItems;
@@ -1208,7 +1160,6 @@ __global__ __launch_bounds__(1024) void k_round_mid(Params P) {
     __shared__ int32_t s_min[16], s_max[16];
     __shared__ int s_improved;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    if (t == 0) rslow(P);
     long long cnt = 0;
     int32_t mn = INT32_MAX, mx = 0;
     for (long long b = t; b < c->n_piv; b += blockDim.x) {
@@ -1238,7 +1189,7 @@ __global__ __launch_bounds__(1024) void k_round_mid(Params P) {
         c->batch_minE = mn;
         c->expansions += c->n_piv;
         c->n_live -= c->n_piv;
-        const long long n_new = cnt - c->n_dup_new;
+        const long long n_new = cnt;
         c->pushes += n_new;
         c->dups += c->n_piv * P.L - n_new;
         c->n_live += n_new;
@@ -1550,7 +1501,7 @@ uint64_t next_pow2(uint64_t x) {
 constexpr int kCheck = 8;    // rounds between host looks at the control block
 
 struct S2Layout {
-    uint64_t cap_ht, cap_r;
+    uint64_t cap_ht;
     long long cap_o, cap_pend, cap_new;
     size_t total;
 };
@@ -1568,7 +1519,6 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     const long long live = n_cand + c.max_expansions + c.pq_capacity + BL;
     lo.cap_ht = next_pow2((uint64_t)(4 * (live + (long long)kCheck * BL) + 1024));
     lo.cap_new = BL + 1024;
-    lo.cap_r = next_pow2((uint64_t)(4 * lo.cap_new));   // load <= 1/4: short probe runs
     size_t t = 0;
     for (int tb = 0; tb < 2; ++tb) {
         t += align_up(sizeof(unsigned long long) * lo.cap_ht, 256);
@@ -1580,8 +1530,7 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     t += align_up(sizeof(uint32_t) * lo.cap_ht, 256);                  // remap
     t += align_up(sizeof(int32_t) * lo.cap_new, 256);                  // ntomb
     t += 3 * align_up(sizeof(int32_t) * c.batch, 256);                 // bcnt, bmin, bmax
-    t += align_up(sizeof(unsigned long long) * lo.cap_r, 256);         // rkey
-    t += align_up(sizeof(int32_t) * lo.cap_r, 256);                    // ridx
+    t += align_up(lo.cap_new, 256);                                    // repeat
     t += align_up(sizeof(Ctl), 256);
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // oE
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // oS
@@ -1642,9 +1591,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.bcnt = cv.take<int32_t>(cfg.batch);
     P.bmin = cv.take<int32_t>(cfg.batch);
     P.bmax = cv.take<int32_t>(cfg.batch);
-    P.rkey = cv.take<unsigned long long>(lo.cap_r);
-    P.ridx = cv.take<int32_t>(lo.cap_r);
-    P.rmask = lo.cap_r - 1;
+    P.repeat = cv.take<uint8_t>(lo.cap_new);
     int tcur = 0;
     P.H = tabs[0];
     P.ctl = cv.take<Ctl>(1);
@@ -1705,10 +1652,10 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     for (long long r = 0;; ++r) {
         select(false);
         hipLaunchKernelGGL(k_pop, gS, tS, 0, st, P);
+        hipLaunchKernelGGL(k_repeats, dim3((unsigned)cfg.batch), dim3(256), 0, st, P);
         if (tb && (s = tb(tctx, st)) != LABS_OK) return s;
         hipLaunchKernelGGL(ek, dim3((unsigned)cfg.batch), dim3(eth), 0, st, P);
         if (te && (s = te(tctx, st)) != LABS_OK) return s;
-        hipLaunchKernelGGL(k_rresolve, gS, tS, 0, st, P);
         hipLaunchKernelGGL(k_round_mid, dim3(1), dim3(1024), 0, st, P);
         select(false);
         hipLaunchKernelGGL(k_keep, gS, tS, 0, st, P);
