@@ -462,33 +462,44 @@ __global__ void k_slow(Params P) {
 // (y equal to a pivot itself is a CLOSED entry of H).  Block b compares its pivot
 // with every lower-numbered pivot and marks its copies of the shared neighbours,
 // so of every repeated sequence exactly the copy of the lowest pivot is kept.
+constexpr int kRepTile = 64;
+
 __global__ __launch_bounds__(256) void k_repeats(Params P) {
     Ctl* c = P.ctl;
-    const long long b = blockIdx.x;
-    if (c->stop || b >= c->n_piv) return;
+    const int tb = blockIdx.y, tq = blockIdx.x;   // pivot tiles: higher (b) and lower (q)
+    if (c->stop || tq > tb) return;
+    const long long n = c->n_piv;
+    const int b0 = tb * kRepTile, q0 = tq * kRepTile;
+    if (b0 >= n) return;
     const int L = P.L, W = P.W;
-    __shared__ uint32_t mine[32];
-    uint8_t* row = P.repeat + b * L;
-    for (int i = threadIdx.x; i < L; i += blockDim.x) row[i] = 0;
-    if (threadIdx.x < (unsigned)W) mine[threadIdx.x] = P.H.seq[(size_t)P.piv[b] * W + threadIdx.x];
+    __shared__ uint32_t sb[kRepTile][33], sq[kRepTile][33];
+    for (int e = threadIdx.x; e < kRepTile * W; e += blockDim.x) {
+        const int r = e / W, w = e % W;
+        sb[r][w] = (b0 + r < n) ? P.H.seq[(size_t)P.piv[b0 + r] * W + w] : 0u;
+        sq[r][w] = (q0 + r < n) ? P.H.seq[(size_t)P.piv[q0 + r] * W + w] : 0u;
+    }
     __syncthreads();
-    for (long long q = threadIdx.x; q < b; q += blockDim.x) {
-        const uint32_t* other = P.H.seq + (size_t)P.piv[q] * W;
-        int d = 0, first = -1, second = -1;
-        for (int w = 0; w < W && d <= 2; ++w) {
-            uint32_t x = mine[w] ^ other[w];
-            while (x && d <= 2) {
-                const int pos = 32 * w + __clz((int)x) + 1;   // 1-based position, MSB first
-                if (d == 0) first = pos;
-                else if (d == 1) second = pos;
-                ++d;
-                x &= ~(0x80000000u >> (pos - 1 - 32 * w));
+    for (int e = threadIdx.x; e < kRepTile * kRepTile; e += blockDim.x) {
+        const int rb = e / kRepTile, rq = e % kRepTile;
+        const long long bi = b0 + rb, qi = q0 + rq;
+        if (bi >= n || qi >= bi) continue;
+        int d = 0;
+        for (int w = 0; w < W; ++w) d += __popc(sb[rb][w] ^ sq[rq][w]);
+        if (d != 2) continue;
+        int first = -1, second = -1;
+        for (int w = 0; w < W; ++w) {
+            uint32_t x = sb[rb][w] ^ sq[rq][w];
+            while (x) {
+                const int k = __clz((int)x);
+                const int pos = 32 * w + k + 1;   // 1-based position, MSB first
+                if (first < 0) first = pos;
+                else second = pos;
+                x &= ~(0x80000000u >> k);
             }
         }
-        if (d == 2) {
-            row[first - 1] = 1;
-            row[second - 1] = 1;
-        }
+        uint8_t* row = P.repeat + bi * L;
+        row[first - 1] = 1;
+        row[second - 1] = 1;
     }
 }
 
@@ -915,6 +926,14 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
 __global__ __launch_bounds__(kSelThreads) void k_pop(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
+    // this round's repeat map starts clear
+    {
+        uint32_t* rw = (uint32_t*)P.repeat;
+        const long long nw = ((long long)P.B * P.L + 3) / 4;
+        for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
+             i += (long long)gridDim.x * blockDim.x)
+            rw[i] = 0u;
+    }
     const int cur = c->which;
     const long long n_tot = c->n_tot;
     const long long stride = (long long)gridDim.x * blockDim.x * kItems;
@@ -1530,7 +1549,7 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     t += align_up(sizeof(uint32_t) * lo.cap_ht, 256);                  // remap
     t += align_up(sizeof(int32_t) * lo.cap_new, 256);                  // ntomb
     t += 3 * align_up(sizeof(int32_t) * c.batch, 256);                 // bcnt, bmin, bmax
-    t += align_up(lo.cap_new, 256);                                    // repeat
+    t += align_up(lo.cap_new + 4, 256);                                // repeat
     t += align_up(sizeof(Ctl), 256);
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // oE
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // oS
@@ -1591,7 +1610,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.bcnt = cv.take<int32_t>(cfg.batch);
     P.bmin = cv.take<int32_t>(cfg.batch);
     P.bmax = cv.take<int32_t>(cfg.batch);
-    P.repeat = cv.take<uint8_t>(lo.cap_new);
+    P.repeat = cv.take<uint8_t>(lo.cap_new + 4);
     int tcur = 0;
     P.H = tabs[0];
     P.ctl = cv.take<Ctl>(1);
@@ -1652,7 +1671,10 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     for (long long r = 0;; ++r) {
         select(false);
         hipLaunchKernelGGL(k_pop, gS, tS, 0, st, P);
-        hipLaunchKernelGGL(k_repeats, dim3((unsigned)cfg.batch), dim3(256), 0, st, P);
+        {
+            const unsigned nt = (unsigned)((cfg.batch + kRepTile - 1) / kRepTile);
+            hipLaunchKernelGGL(k_repeats, dim3(nt, nt), dim3(256), 0, st, P);
+        }
         if (tb && (s = tb(tctx, st)) != LABS_OK) return s;
         hipLaunchKernelGGL(ek, dim3((unsigned)cfg.batch), dim3(eth), 0, st, P);
         if (te && (s = te(tctx, st)) != LABS_OK) return s;
