@@ -68,3 +68,65 @@ def test_mlp_layout_host_call():
         labs.mlp_layout(500, 256)
     with pytest.raises(labs.LabsError):
         labs.mlp_layout(501, 100)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_network_and_learned_walk_validation_without_a_gpu():
+    """Bad arguments to the network and learned-walk entry points are rejected
+    (LABS_E_INVALID) before anything is enqueued; workspace queries are host-only."""
+    from paper_2409_07222_amd import labs
+    L = labs.lib()
+    lay = labs.mlp_layout(101, 64)
+    sz = ctypes.c_size_t(0)
+    assert L.labs_mlp_forward_workspace(ctypes.byref(lay), 1000, ctypes.byref(sz)) == 0 and sz.value > 0
+    assert L.labs_mlp_grads_workspace(ctypes.byref(lay), 4096, ctypes.byref(sz)) == 0 and sz.value > 0
+    bad = labs.MlpLayout.from_buffer_copy(lay)
+    bad.n_params += 64
+    assert L.labs_mlp_forward_workspace(ctypes.byref(bad), 10, ctypes.byref(sz)) == -1
+    assert L.labs_mlp_forward(ctypes.byref(lay), None, None, 10, None, None, None, 0, None) == -1
+    assert L.labs_mlp_adam(ctypes.byref(lay), None, None, None, None, None, 0, 1e-3, 0.9, 0.999, 1e-8,
+                           None) == -1                                     # t counts from 1
+    assert L.labs_mlp_features(100, 4, None, None, None) == -1             # even L
+    cfg = labs.Step1Cfg(101, 8, 100, 10, 20, -1, 0, 64, 1, 0, 0)
+    pr = labs.Proposer(labs.PROPOSE_RANDOM, 8, 16, 64, None, None, 0, 0, 0)
+    assert L.labs_learned_walk_workspace(ctypes.byref(cfg), ctypes.byref(pr), ctypes.byref(sz)) == 0
+    assert sz.value > 0
+    for field, value in (("top_m", 0), ("top_m", 65), ("fallback_every", 0), ("mode", 7),
+                         ("log_every", -1), ("reserved", 1)):
+        p2 = labs.Proposer.from_buffer_copy(pr)
+        setattr(p2, field, value)
+        assert L.labs_learned_walk_workspace(ctypes.byref(cfg), ctypes.byref(p2),
+                                             ctypes.byref(sz)) == -1, field
+    pm = labs.Proposer.from_buffer_copy(pr)
+    pm.mode = labs.PROPOSE_MLP                                           # no weights given
+    assert L.labs_learned_walk_workspace(ctypes.byref(cfg), ctypes.byref(pm), ctypes.byref(sz)) == -1
+    c2 = labs.Step1Cfg.from_buffer_copy(cfg)
+    c2.flags = 1
+    assert L.labs_learned_walk_workspace(ctypes.byref(c2), ctypes.byref(pr), ctypes.byref(sz)) == -1
+    c3 = labs.Step1Cfg.from_buffer_copy(cfg)
+    c3.L = 641                                                           # beyond the walk limit
+    c3.tenure_lo, c3.tenure_hi = 10, 20
+    assert L.labs_learned_walk_workspace(ctypes.byref(c3), ctypes.byref(pr), ctypes.byref(sz)) == -1
+    out = labs.LearnedOut()
+    assert L.labs_learned_walk(ctypes.byref(cfg), ctypes.byref(pr), ctypes.byref(out), None, 0,
+                               None) == -1                               # flip_evals missing
+    assert b"flip_evals" in L.labs_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_step2_validation_without_a_gpu():
+    from paper_2409_07222_amd import labs
+    L = labs.lib()
+    sz = ctypes.c_size_t(0)
+    ok = labs.Step2Cfg(501, 1024, 0, 0, 1 << 20, 10_000_000, 1 << 62)
+    assert L.labs_refine_step2_workspace(ctypes.byref(ok), 1024, ctypes.byref(sz)) == 0
+    assert sz.value > 10 ** 9                  # the hash set is sized for 10^7 expansions
+    for field, value in (("L", 1), ("L", 1024), ("batch", 0), ("T_r", 1), ("pq_capacity", 0),
+                         ("max_expansions", -1), ("T_u", 0)):
+        c = labs.Step2Cfg.from_buffer_copy(ok)
+        setattr(c, field, value)
+        assert L.labs_refine_step2_workspace(ctypes.byref(c), 1024, ctypes.byref(sz)) == -1, field
+    huge = labs.Step2Cfg.from_buffer_copy(ok)
+    huge.max_expansions = 1 << 30              # the hash set would pass 2^31 slots
+    assert L.labs_refine_step2_workspace(ctypes.byref(huge), 1024, ctypes.byref(sz)) == -1
+    assert L.labs_refine_step2_workspace(ctypes.byref(ok), 0, ctypes.byref(sz)) == -1

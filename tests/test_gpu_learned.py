@@ -193,3 +193,16 @@ def test_trained_network_gains_over_untrained_and_random(lb):
     # log of the admissible count: the network learns little of the argmin)
     assert r_tr >= max(r_un, r_rand) + 0.03
     assert float(loss_tr.item()) < float(loss_un.item()) - 0.01
+
+
+def test_single_walker_default_steps(lb):
+    """steps = 0 means T_i = 4(L+1), as for the plain walker; one walker, top-1."""
+    L, p, lo, hi = 37, 2, 3, 6
+    plain = lb.walk_step1(L, p, 0, lo, hi, 9, 1, want_traj=True)
+    r = lb.learned_walk(L, p, 0, lo, hi, 9, 1, mode=lb.PROPOSE_RANDOM, top_m=1,
+                        fallback_every=1, want_traj=True)
+    assert r["traj_E"].shape[1] == 4 * (L + 1)
+    assert np.array_equal(_np(r["traj_E"]), _np(plain.traj_E))
+    narrow = lb.learned_walk(L, p, 0, lo, hi, 9, 1, mode=lb.PROPOSE_RANDOM, top_m=1,
+                             fallback_every=4, want_traj=True)
+    assert int(narrow["flip_evals"].item()) < int(r["flip_evals"].item())

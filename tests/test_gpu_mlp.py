@@ -167,3 +167,17 @@ def test_training_lowers_loss(lb, orc):
         if t in (1, 300):
             losses.append(float(loss.item()))
     assert losses[1] < 0.5 * losses[0], losses
+
+
+def test_empty_batch(lb):
+    import torch
+    L = 101
+    lay, P, blob, pb = _params(lb, L, 64, 59)
+    X = lb.mlp_features(L, torch.zeros((0, 4), dtype=torch.int32, device="cuda"))
+    assert tuple(X.shape) == (0, lay.ld_in)
+    z = lb.mlp_forward(lay, blob, pb, X)
+    assert tuple(z.shape) == (0, lay.ld_out)
+    G, loss = lb.mlp_grads(lay, blob, pb, X, torch.zeros((0, lay.mask_words), dtype=torch.int32,
+                                                         device="cuda"),
+                           torch.zeros(0, dtype=torch.int32, device="cuda"))
+    assert float(loss.item()) == 0.0 and not bool(G.any().item())
