@@ -34,6 +34,11 @@ W2_OPS = 4 * (L - 1)
 PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
 
 
+def log(msg: str) -> None:
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +55,10 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the uneven-length batched launch measurement")
     ap.add_argument("--batched-steps", type=int, default=20000)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the first-step rates of the L=101 and L=451/475/527 configurations")
+    ap.add_argument("--ab-seeds", type=int, default=1,
+                    help="comparison seeds 1001.. (median and IQR are reported for more than one)")
     ap.add_argument("--no-ab", action="store_true",
                     help="skip the learned-vs-plain comparison at equal wall budgets")
     ap.add_argument("--ab-budget", type=float, default=8.0, help="seconds of walking per arm")
@@ -77,22 +86,37 @@ WALK_SOURCES = ["walk_impl.h", "walk.hip", "walk_inst_a.hip", "walk_inst_b.hip",
 COUNTERS = os.path.join(ROOT, "profiles", "walk_L501_hbm_counters.txt")
 
 
-def walk_traffic():
-    """HBM bytes per walk launch from the committed counter summary, or None when
-    the walk kernel's sources have changed since the counters were taken."""
+VALU_COUNTERS = os.path.join(ROOT, "profiles", "walk_L501_valu_counters.txt")
+
+
+def _profile_value(path, key):
+    """A figure from a committed counter summary, or None when the walk kernel's
+    sources have changed since the counters were taken."""
     import hashlib
     try:
-        txt = open(COUNTERS).read()
+        txt = open(path).read()
     except OSError:
         return None
     vals = dict(line.strip().split(": ", 1) for line in txt.splitlines()
-                if line.strip().startswith(("traffic_bytes_per_launch:", "kernel_sources_sha256:")))
+                if line.strip().startswith((key + ":", "kernel_sources_sha256:")))
     h = hashlib.sha256()
     for f in WALK_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_2409_07222_amd", "csrc", f), "rb").read())
-    if vals.get("kernel_sources_sha256") != h.hexdigest():
+    if vals.get("kernel_sources_sha256") != h.hexdigest() or key not in vals:
         return None
-    return int(vals["traffic_bytes_per_launch"])
+    return vals[key]
+
+
+def walk_traffic():
+    """HBM bytes per walk launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)."""
+    v = _profile_value(COUNTERS, "traffic_bytes_per_launch")
+    return int(v) if v is not None else None
+
+
+def walk_valu_utilisation():
+    """Fraction of the VALU peak the walk kernel issues (SQ_INSTS_VALU x 4 cycles)."""
+    v = _profile_value(VALU_COUNTERS, "valu_utilisation")
+    return float(v) if v is not None else None
 
 
 def cpu_baseline(budget_s: float):
@@ -113,6 +137,34 @@ def cpu_baseline(budget_s: float):
     return {"value": steps * nf / dt, "unit": "flip-evals/s", "cores": 1, "kind": "oracle",
             "sample": "1 walker x %d steps of the L=501 p=16 first-step walk (%d flip-evals, "
                       "%.1f s), definitional energy per neighbour" % (steps, steps * nf, dt)}
+
+
+def step1_configs(a, labs, dev):
+    """First-step rates of the other single-length configurations: L = 101 (p = 8,
+    65,536 walkers x 10,000 steps, tenure [10, 20], F >= 6 sieve into a 2^20 pool,
+    seed 2) and L = 451 / 475 / 527 (p = 16, 16,384 walkers x 50,000 steps, F >= 8,
+    walker bests offered, seed 4; L = 501 is the headline run)."""
+    import torch
+    out = {}
+    runs = [(101, 8, 65536, 10000, 6, 2, False)] + [(x, 16, 16384, 50000, 8, 4, True)
+                                                    for x in (451, 475, 527)]
+    for (Lx, px, n, steps, tau, seed, wb) in runs:
+        log("first step at L=%d" % Lx)
+        pool = labs.PoolBuffers.empty(Lx, 1 << 20, device=dev)
+        e_max = (Lx * Lx) // (2 * tau)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = labs.walk_step1(Lx, px, steps, Lx // 10, Lx // 5, seed, n, e_max=e_max, pool=pool,
+                            pool_walker_best=wb, device=dev)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        fe = int(r.flip_evals.item())
+        out[str(Lx)] = {"p": px, "walkers": n, "steps": steps, "tau": tau, "flip_evals": fe,
+                        "seconds": dt, "flip_evals_per_s": fe / dt,
+                        "pool_count": int(pool.count.item()),
+                        "best_F": Lx * Lx / (2.0 * int(r.best_E.min().item()))}
+        del pool, r
+    return out
 
 
 def batched_measure(a, labs, dev):
@@ -185,6 +237,7 @@ def learned_ab(a, labs, dev):
     lay = labs.mlp_layout(L, 256)
     net = learn.Network(L, li.mlp_init(55, lay.d_in, 256, lay.d_out), 256, device=dev)
     untrained = net.clone()
+    log("comparison: %d logged pairs" % int(seqs.shape[0]))
     sync()
     t0 = time.perf_counter()
     hist = learn.train(net, seqs, mask, lab, batch=4096, epochs=a.ab_epochs, lr=1e-3)
@@ -210,16 +263,28 @@ def learned_ab(a, labs, dev):
                           "untrained": recall(untrained.logits(hs).cpu().numpy()),
                           "random": recall(np.random.default_rng(0).random(adm.shape))}
 
-    def plain_run(steps, seed, e_max):
+    ladder = [5.2, 5.3, 5.4, 6.0, 6.5, 7.0, 7.5, 8.0]
+
+    def plain_run(steps, seed, e_max, tau_star=None):
+        # the pool sieves at the lowest ladder level; each level's first hit is the
+        # least step among the pooled sequences at or below its energy
+        e_pool = max(e_max, int(np.floor(L * L / (2.0 * ladder[0])))) if e_max >= 0 else -1
         pool = labs.PoolBuffers.empty(L, 1 << 20, device=dev)
         sync()
         t0 = time.perf_counter()
-        r = labs.walk_step1(L, P, steps, lo, hi, seed, n, e_max=e_max, pool=pool, device=dev)
+        r = labs.walk_step1(L, P, steps, lo, hi, seed, n, e_max=e_pool, pool=pool, device=dev)
         sync()
         dt = time.perf_counter() - t0
         c = int(pool.count.item())
-        hit = int(pool.step[:c].min().item()) if c else None
-        return {"seconds": dt, "steps": steps, "best_E": int(r.best_E.min().item()), "hit_step": hit,
+        pE = pool.E[:c].cpu().numpy()
+        pS = pool.step[:c].cpu().numpy()
+
+        def first(em):
+            sel = pS[pE <= em]
+            return int(sel.min()) if sel.size else None
+        hits = {str(tl): first(int(np.floor(L * L / (2.0 * tl)))) for tl in ladder}
+        return {"seconds": dt, "steps": steps, "best_E": int(r.best_E.min().item()),
+                "hit_step": first(e_max) if e_max >= 0 else None, "ladder_hit_steps": hits,
                 "flip_evals": int(r.flip_evals.item()), "pool_dropped": int(pool.dropped.item())}
 
     def learned_run(steps, seed, e_max, kw):
@@ -251,20 +316,44 @@ def learned_ab(a, labs, dev):
     e_max = int(np.floor(L * L / (2.0 * tau)))
     res["tau_star"] = float(round(tau, 2))
     res["e_max"] = e_max
-    out = {}
-    steps = max(64, int(rate["plain"] * a.ab_budget))
-    out["plain"] = plain_run(steps, 1001, e_max)
-    for name, kw in arms.items():
-        steps = max(64, int(rate[name] * a.ab_budget))
-        steps -= steps % 64
-        out[name] = learned_run(steps, 1001, e_max, kw)
-    for name, o in out.items():
-        o["best_F"] = L * L / (2.0 * o["best_E"])
-        o["time_to_tau_s"] = (o["hit_step"] / o["steps"] * o["seconds"]
-                              if o["hit_step"] is not None else None)
-        o["walker_steps_per_s"] = n * o["steps"] / o["seconds"]
-        o["flip_evals_per_s"] = o["flip_evals"] / o["seconds"]
-    res["arms"] = out
+    log("comparison: tau* = %.2f, %d seed(s) of %.1f s per arm" % (tau, max(1, a.ab_seeds), a.ab_budget))
+    per_seed = []
+    for seed in range(1001, 1001 + max(1, a.ab_seeds)):
+        out = {}
+        steps = max(64, int(rate["plain"] * a.ab_budget))
+        out["plain"] = plain_run(steps, seed, e_max)
+        log("seed %d plain: best E %d" % (seed, out["plain"]["best_E"]))
+        for name, kw in arms.items():
+            steps = max(64, int(rate[name] * a.ab_budget))
+            steps -= steps % 64
+            out[name] = learned_run(steps, seed, e_max, kw)
+            log("seed %d %s: best E %d" % (seed, name, out[name]["best_E"]))
+        for name, o in out.items():
+            o["best_F"] = L * L / (2.0 * o["best_E"])
+            o["time_to_tau_s"] = (o["hit_step"] / o["steps"] * o["seconds"]
+                                  if o["hit_step"] is not None else None)
+            o["walker_steps_per_s"] = n * o["steps"] / o["seconds"]
+            o["flip_evals_per_s"] = o["flip_evals"] / o["seconds"]
+        o = out["plain"]
+        o["ladder_time_s"] = {k: (v / o["steps"] * o["seconds"] if v is not None else None)
+                              for k, v in o["ladder_hit_steps"].items()}
+        per_seed.append(out)
+    res["arms"] = per_seed[0]
+    if len(per_seed) > 1:
+        # time to tau* per seed; runs that never reach it count as censored at the budget
+        summary = {}
+        for name in per_seed[0]:
+            tt = [s[name]["time_to_tau_s"] for s in per_seed]
+            vals = np.array([x if x is not None else a.ab_budget for x in tt])
+            bf = np.array([s[name]["best_F"] for s in per_seed])
+            summary[name] = {"time_to_tau_median_s": float(np.median(vals)),
+                             "time_to_tau_iqr_s": [float(np.percentile(vals, 25)),
+                                                   float(np.percentile(vals, 75))],
+                             "censored": int(sum(x is None for x in tt)),
+                             "best_F_median": float(np.median(bf)),
+                             "best_F_iqr": [float(np.percentile(bf, 25)), float(np.percentile(bf, 75))]}
+        res["seeds"] = [1001, 1000 + len(per_seed)]
+        res["summary"] = summary
     return res
 
 
@@ -359,6 +448,7 @@ def main():
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
                 "frac": achieved / peak, "traffic": walk_traffic(),
                 "kernel": "walk", "launches": launches, "avg_launch_ms": ms / max(launches, 1),
+                "valu_utilisation_from_counters": walk_valu_utilisation(),
                 "ops_per_flip_eval": W_OPS, "kernel_share_of_pass": ms / 1e3 / t_pass}
         if launches2:
             ops2 = int(r2["expansions"]) * L * W2_OPS
@@ -368,7 +458,9 @@ def main():
                                     "ops_per_neighbour_eval": W2_OPS,
                                     "kernel_share_of_pass": ms2 / 1e3 / t_pass}
 
+    log("dual-step passes done: %.3e flip-evals/s" % (evals / dt))
     batched = None if a.no_batched else batched_measure(a, labs, dev)
+    configs = None if a.no_configs else step1_configs(a, labs, dev)
     ab = None
     if not a.no_ab:
         s2_ws = None
@@ -398,6 +490,7 @@ def main():
         "tau_star": ab["tau_star"] if ab else None,
         "learned_ab": ab,
         "batched_uneven_L": batched,
+        "step1_configs": configs,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
