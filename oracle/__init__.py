@@ -8,7 +8,8 @@ product library: the two share no code.
 Layers:
   * ``labs_oracle.c`` (built to ``liblabs_oracle.so`` with gcc): definitional
     energy, skew completion, skew flips, the first-step walker (Algorithm 1 with
-    a tabu tenure), exhaustive enumeration, SplitMix64.  Every energy change is
+    a tabu tenure, and with its Bloom filter), exhaustive enumeration,
+    SplitMix64.  Every energy change is
     recomputed from the definition of E; no incremental formula is used.
   * this module: ctypes bindings, the candidate pool (set semantics, kept in
     (E, key) order), and the second step (Algorithm 2) as a batch-synchronous
@@ -94,6 +95,23 @@ def lib():
                                       ctypes.c_int64, ctypes.c_int32,
                                       _i32p, _i32p, _i8p, _i64p, _i8p, _i64p, _i32p,
                                       ctypes.c_int64, _i64p, _i8p, _i32p]
+            _u8p = ctypes.POINTER(ctypes.c_uint8)
+            L.or_zobrist_key.restype = ctypes.c_uint64
+            L.or_zobrist_key.argtypes = [ctypes.c_int32]
+            L.or_seq_hash.restype = ctypes.c_uint64
+            L.or_seq_hash.argtypes = [ctypes.c_int32, _i8p]
+            L.or_bloom_index.restype = ctypes.c_uint32
+            L.or_bloom_index.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32]
+            L.or_bloom_insert.restype = None
+            L.or_bloom_insert.argtypes = [_u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64]
+            L.or_bloom_member.restype = ctypes.c_int32
+            L.or_bloom_member.argtypes = [_u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64]
+            L.or_walk_bloom_one.restype = ctypes.c_int64
+            L.or_walk_bloom_one.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                            ctypes.c_int64, ctypes.c_int32,
+                                            _i32p, _i32p, _i8p, _i64p, _i8p, _i64p, _i32p,
+                                            ctypes.c_int64, _i64p, _i8p, _i32p]
             L.or_skew_exhaustive.restype = ctypes.c_int64
             L.or_skew_exhaustive.argtypes = [ctypes.c_int32, ctypes.c_int32, _i8p, _i64p]
             L.or_exhaustive_min.restype = ctypes.c_int64
@@ -221,6 +239,54 @@ def walk(L: int, p: int, steps: int, tenure_lo: int, tenure_hi: int, seed: int,
     tabu tenure; see or_walk_one).  Returns a dict of numpy arrays plus the list
     of sieve emissions (E, seq, walker, t)."""
     lb = lib()
+
+    def one(w, *rest):
+        return lb.or_walk_one(L, p, steps, tenure_lo, tenure_hi, seed, w, e_max, *rest)
+    return _walks(L, steps, walkers, e_max, want_traj, emit_cap, one)
+
+
+def walk_bloom(L: int, p: int, steps: int, log2_bits: int, n_hash: int, seed: int, walkers,
+               e_max: int = -1, want_traj: bool = True, emit_cap: int = 1 << 16):
+    """Run the first-step walker with the Bloom filter of Algorithm 1 for each id
+    in ``walkers`` (see or_walk_bloom_one): same outputs as :func:`walk`."""
+    lb = lib()
+
+    def one(w, *rest):
+        return lb.or_walk_bloom_one(L, p, steps, log2_bits, n_hash, seed, w, e_max, *rest)
+    return _walks(L, steps, walkers, e_max, want_traj, emit_cap, one)
+
+
+def walk_hash(L: int, s) -> int:
+    """Key of a skew sequence in the first step's Bloom filter: the Zobrist hash
+    of its first k+1 elements (or_seq_hash)."""
+    a = np.ascontiguousarray(np.asarray(s, dtype=np.int8))
+    return int(lib().or_seq_hash(L, _p(a, _i8p)))
+
+
+def walk_zobrist(i: int) -> int:
+    """Z_i of the first step's key (1-based position), or_zobrist_key."""
+    return int(lib().or_zobrist_key(i))
+
+
+class Bloom:
+    """The oracle's Bloom filter of 2^log2_bits bits probed n_hash times."""
+
+    def __init__(self, log2_bits: int, n_hash: int):
+        self.log2_bits, self.n_hash = log2_bits, n_hash
+        self.bits = np.zeros(max(1, (1 << log2_bits) // 8), dtype=np.uint8)
+        self._p = self.bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+    def index(self, h: int, j: int) -> int:
+        return int(lib().or_bloom_index(h, self.log2_bits, j))
+
+    def insert(self, h: int) -> None:
+        lib().or_bloom_insert(self._p, self.log2_bits, self.n_hash, h)
+
+    def __contains__(self, h: int) -> bool:
+        return bool(lib().or_bloom_member(self._p, self.log2_bits, self.n_hash, h))
+
+
+def _walks(L, steps, walkers, e_max, want_traj, emit_cap, one):
     ids = list(walkers)
     n = len(ids)
     traj = np.zeros((n, steps), dtype=np.int32)
@@ -241,12 +307,11 @@ def walk(L: int, p: int, steps: int, tenure_lo: int, tenure_hi: int, seed: int,
             b_t = ctypes.c_int32(0)
             f_e = np.zeros(1, dtype=np.int64)
             b_e = np.zeros(1, dtype=np.int64)
-            cnt = lb.or_walk_one(L, p, steps, tenure_lo, tenure_hi, seed, w, e_max,
-                                 _p(tr, _i32p) if want_traj else None,
-                                 _p(moves[j], _i32p) if want_traj else None,
-                                 _p(fin[j], _i8p), _p(f_e, _i64p),
-                                 _p(best[j], _i8p), _p(b_e, _i64p), ctypes.byref(b_t),
-                                 cap, _p(eE, _i64p), _p(eS, _i8p), _p(eT, _i32p))
+            cnt = one(w, _p(tr, _i32p) if want_traj else None,
+                      _p(moves[j], _i32p) if want_traj else None,
+                      _p(fin[j], _i8p), _p(f_e, _i64p),
+                      _p(best[j], _i8p), _p(b_e, _i64p), ctypes.byref(b_t),
+                      cap, _p(eE, _i64p), _p(eS, _i8p), _p(eT, _i32p))
             if cnt <= cap:
                 break
             cap = int(cnt)

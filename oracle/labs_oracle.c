@@ -11,7 +11,8 @@
  * Sequences with High Merit Factors", arXiv 2409.07222):
  *   - Sec. 1, the autocorrelation C_k and energy E definitions and Eq. (1), merit factor;
  *   - Sec. 1, Eq. (2), skew-symmetry; Eq. (3), restriction-class prefix layout;
- *   - Sec. 3, Algorithm 1 (first step) and the neighbourhood it searches;
+ *   - Sec. 3, Algorithm 1 (first step) and the neighbourhood it searches, with a
+ *     tabu tenure and with the Bloom filter the algorithm names;
  *   - Sec. 3, Algorithm 2 (second step) -- its queue bookkeeping lives in
  *     oracle/__init__.py, this file only provides the energies it needs.
  * No incremental formula is used anywhere: every energy change is computed as
@@ -293,4 +294,144 @@ int64_t or_exhaustive_min(int32_t L, int64_t* count_out)
     free(s);
     if (count_out) *count_out = cnt;
     return best;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bloom-filter self-avoidance (Sec. 3, Algorithm 1 with its Bloom filter,
+ * Bloom 1970).  The paper fixes neither the hash nor the filter's size, so the
+ * following are readings of ours:
+ *   - a sequence is keyed by the 64-bit Zobrist hash (Zobrist 1970) of its first
+ *     k+1 elements, which fix the rest under Eq. (2), with the table of the
+ *     second step's keys:
+ *       h(S) = XOR of Z_i over i = 1..k+1 with s_i = +1,
+ *     Z_i = draw number i-1 of the SplitMix64 stream started at OR_ZOBRIST_STATE;
+ *   - the filter holds m = 2^log2_bits bits; a key h sets / tests the bits
+ *       (g1 + j*g2) mod m,  j = 0..n_hash-1,  g1 = low 32 bits of h,
+ *       g2 = (high 32 bits of h) | 1
+ *     (double hashing, Kirsch and Mitzenmacher 2006), arithmetic on 32 bits;
+ *     a key is a member when all its bits are set. */
+static const uint64_t OR_ZOBRIST_STATE = 0x6A09E667F3BCC909ull;
+
+uint64_t or_zobrist_key(int32_t i)
+{
+    uint64_t st = OR_ZOBRIST_STATE;
+    uint64_t z = 0;
+    for (int32_t q = 1; q <= i; ++q) z = or_splitmix64_next(&st);
+    return z;
+}
+
+uint64_t or_seq_hash(int32_t L, const int8_t* s)
+{
+    int32_t k = (L - 1) / 2;
+    uint64_t st = OR_ZOBRIST_STATE;
+    uint64_t h = 0;
+    for (int32_t i = 1; i <= k + 1; ++i) {
+        uint64_t z = or_splitmix64_next(&st);
+        if (s[i - 1] > 0) h ^= z;
+    }
+    return h;
+}
+
+/* Bit index j of key h in a filter of 2^log2_bits bits. */
+uint32_t or_bloom_index(uint64_t h, int32_t log2_bits, int32_t j)
+{
+    uint32_t g1 = (uint32_t)h;
+    uint32_t g2 = (uint32_t)(h >> 32) | 1u;
+    uint32_t v = g1 + (uint32_t)j * g2;
+    return v & (uint32_t)((1ull << log2_bits) - 1ull);
+}
+
+/* bits: (2^log2_bits)/8 bytes, bit x at byte x/8, bit x%8. */
+void or_bloom_insert(uint8_t* bits, int32_t log2_bits, int32_t n_hash, uint64_t h)
+{
+    for (int32_t j = 0; j < n_hash; ++j) {
+        uint32_t x = or_bloom_index(h, log2_bits, j);
+        bits[x >> 3] |= (uint8_t)(1u << (x & 7));
+    }
+}
+
+int32_t or_bloom_member(const uint8_t* bits, int32_t log2_bits, int32_t n_hash, uint64_t h)
+{
+    for (int32_t j = 0; j < n_hash; ++j) {
+        uint32_t x = or_bloom_index(h, log2_bits, j);
+        if (!(bits[x >> 3] & (1u << (x & 7)))) return 0;
+    }
+    return 1;
+}
+
+/* One first-step walker of Algorithm 1 with the Bloom filter: the initial
+ * sequence (or_walker_init; its tenure draw is unused) is inserted; for
+ * t = 1..steps every free skew neighbour a = p+1..k+1 is evaluated, an
+ * "unexplored" neighbour is one whose hash the filter does not hold, the walker
+ * takes the unexplored a with the lowest (delta_a, a), uphill included, and
+ * inserts the new sequence; with no unexplored neighbour the walk stops (its
+ * remaining trajectory is -1).  Every hash is computed from the whole sequence
+ * (no incremental update).  Sieve and outputs as in or_walk_one. */
+int64_t or_walk_bloom_one(int32_t L, int32_t p, int32_t steps, int32_t log2_bits, int32_t n_hash,
+                          uint64_t seed, int64_t walker, int32_t e_max,
+                          int32_t* traj, int32_t* moves, int8_t* final_s, int64_t* final_E,
+                          int8_t* best_s, int64_t* best_E, int32_t* best_step,
+                          int64_t emit_cap, int64_t* emit_E, int8_t* emit_s, int32_t* emit_t)
+{
+    int32_t k = (L - 1) / 2;
+    int32_t nfree = k + 1 - p;
+    int8_t* s = (int8_t*)malloc((size_t)L);
+    uint8_t* bits = (uint8_t*)calloc((size_t)1 << (log2_bits > 3 ? log2_bits - 3 : 0), 1);
+    int64_t* delta = (int64_t*)malloc((size_t)nfree * sizeof(int64_t));
+    int32_t* fresh = (int32_t*)malloc((size_t)nfree * sizeof(int32_t));
+    int32_t unused_tenure = 0;
+    int64_t n_emit = 0;
+
+    or_walker_init(seed, L, p, walker, 0, 0, s, &unused_tenure);
+    or_bloom_insert(bits, log2_bits, n_hash, or_seq_hash(L, s));
+    int64_t e = or_energy(L, s, NULL);
+    *best_E = e;
+    *best_step = 0;
+    memcpy(best_s, s, (size_t)L);
+
+    int32_t t = 1;
+    for (; t <= steps; ++t) {
+        int64_t e_here = or_energy(L, s, NULL);
+        for (int32_t a = p + 1; a <= k + 1; ++a) {
+            or_flip_skew(L, s, a);
+            delta[a - p - 1] = or_energy(L, s, NULL) - e_here;
+            fresh[a - p - 1] = !or_bloom_member(bits, log2_bits, n_hash, or_seq_hash(L, s));
+            or_flip_skew(L, s, a);
+        }
+        int32_t best_a = -1;
+        for (int32_t a = p + 1; a <= k + 1; ++a) {
+            if (!fresh[a - p - 1]) continue;
+            if (best_a < 0 || delta[a - p - 1] < delta[best_a - p - 1]) best_a = a;
+        }
+        if (best_a < 0) break;
+        or_flip_skew(L, s, best_a);
+        or_bloom_insert(bits, log2_bits, n_hash, or_seq_hash(L, s));
+        e += delta[best_a - p - 1];
+        if (traj) traj[t - 1] = (int32_t)e;
+        if (moves) moves[t - 1] = best_a;
+        if (e < *best_E) {
+            *best_E = e;
+            *best_step = t;
+            memcpy(best_s, s, (size_t)L);
+        }
+        if (e_max >= 0 && e <= e_max) {
+            if (n_emit < emit_cap && emit_E) {
+                emit_E[n_emit] = e;
+                memcpy(emit_s + n_emit * L, s, (size_t)L);
+                emit_t[n_emit] = t;
+            }
+            ++n_emit;
+        }
+    }
+    for (; t <= steps; ++t) {
+        if (traj) traj[t - 1] = -1;
+        if (moves) moves[t - 1] = -1;
+    }
+    memcpy(final_s, s, (size_t)L);
+    *final_E = e;
+    free(s);
+    free(bits);
+    free(delta);
+    free(fresh);
+    return n_emit;
 }

@@ -4,37 +4,41 @@
 // few rounds.
 //
 // Data structures (all in the caller's workspace):
-//  * a hash set H keyed by the exact sequence (open addressing, linear probing).
-//    A slot holds a 64-bit Zobrist key (0 = empty), a state (OPEN, CLOSED,
-//    EVICTED), E and the packed sequence.  Zobrist keys make a neighbour's key one
-//    XOR away from its pivot's (Alg. 2's HASH_FLIP).  H holds Closed U Open U
-//    evicted sequences; an EVICTED slot counts as absent and is re-opened when its
-//    sequence is pushed again.  When half of H is claimed it is rebuilt without
-//    the evicted tombstones.
-//  * the Open list: (E, slot) pairs, unordered.  Pops mark entries dead; the
-//    capacity cut at the end of each round compacts the list into the other
-//    buffer, so every round starts from a dense list.
+//  * a hash set H keyed by the exact sequence (open addressing, linear probing,
+//    four slots per live entry).  A slot holds a 64-bit Zobrist key (0 = empty),
+//    a one-byte tag of the key that lets most probes stop without touching the
+//    key array, a state (OPEN, CLOSED, EVICTED), E and the packed sequence.
+//    Zobrist keys make a neighbour's key one XOR away from its pivot's (Alg. 2's
+//    HASH_FLIP).  H holds Closed U Open U evicted sequences; an EVICTED slot
+//    counts as absent and is re-opened when its sequence is pushed again.  When
+//    half of H is claimed it is rebuilt without the evicted tombstones.
+//  * the Open list: (E, slot, key) entries, unordered.  Pops mark entries dead;
+//    the capacity cut at the end of each round compacts the list into the other
+//    buffer, so every round starts from a dense list.  A round's neighbours sit
+//    at fixed positions (pivot b, flip i) after the surviving old entries.
 //  * an exact "T smallest" selection in the order (E, Zobrist key, sequence):
-//    radix select on E in 11-bit digits, then a byte-wise radix select on the
-//    Zobrist key and the sequence among the entries tied at the threshold energy,
-//    skipping digit positions on which they all agree.
+//    energies of one length are congruent mod 4, so (E - emin)/4 is selected in
+//    two 14-bit radix levels, then the entries tied at the threshold energy are
+//    split byte by byte on the Zobrist key (and, if keys collide, the sequence).
+//    The energy window of the last cut is carried to the next round as the
+//    starting bounds.
 //
 // A round's neighbours do not enter H when they are generated.  The expansion
 // only reads H (no writer runs beside it): a neighbour whose sequence H holds as
-// OPEN or CLOSED is a duplicate; any other neighbour is appended to the Open
-// list as a "new" entry (source pivot, flip position, and the slot of its
-// evicted tombstone if H has one) and entered into a per-round table R keyed by
-// the Zobrist key, which finds the neighbours produced twice in the round.  The
-// capacity cut then runs over old and new entries alike, and only the new
-// entries that survive it are written into H (the tombstone re-opened, or an
-// empty slot claimed by CAS).  Neighbours cut in their own round never touch H,
-// so H holds little more than Closed U Open and rarely needs a rebuild.
-// Insertions into R and the seeding insertions into H are exact and use no
-// fences: a candidate walks its probe sequence with 64-bit CAS on the key word;
-// an empty slot is claimed, a slot already holding its key makes the candidate
-// "pending".  After the kernel boundary the pending candidates are compared with
-// the slot's sequence; a mismatch is a true 64-bit key collision, finished one at
-// a time by a single thread.
+// OPEN or CLOSED is a duplicate.  Two pivots of one round produce a common
+// neighbour exactly when they differ in two positions (each flips the other's
+// position), so the in-round repeats are found by comparing the pivots pairwise
+// (k_repeats, 64 x 64 tiles in LDS) before the expansion, which then skips the
+// second copy.  The capacity cut runs over old and new entries alike, and only
+// the new entries that survive it are written into H (the tombstone re-opened,
+// or an empty slot claimed by CAS).  Neighbours cut in their own round never
+// touch H, so H holds little more than Closed U Open and rarely needs a rebuild.
+// The seeding insertions are exact and use no fences: a candidate walks its
+// probe sequence with 64-bit CAS on the key word; an empty slot is claimed, a
+// slot already holding its key makes the candidate "pending".  After the kernel
+// boundary the pending candidates are compared with the slot's sequence; a
+// mismatch is a true 64-bit key collision, finished one at a time by a single
+// thread.
 #include "labs_internal.h"
 
 #include <climits>
@@ -1169,9 +1173,9 @@ expand_kernel_t pick_expand(int L, unsigned* threads) {
 
 __device__ void best_scan(const Params& P, int initial);
 
-// After the expansion: the key collisions of R (one thread), the pushed count
-// and least energy over the pivots' blocks, the statistics, the capacity-cut
-// setup, and the new best when the round improved it.
+// After the expansion: the pushed count and least and greatest energy over the
+// pivots' blocks, the statistics, the capacity-cut setup, and the new best when
+// the round improved it.
 __global__ __launch_bounds__(1024) void k_round_mid(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
@@ -1664,9 +1668,9 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     labs_status s;
     unsigned eth = 64;
     const expand_kernel_t ek = pick_expand(cfg.L, &eth);
-    // A round: pop selection, pop (also clears R), expansion, R's pending
-    // entries, counts / statistics / best, cut selection, cut, then the end of
-    // the round together with the start of the next.
+    // A round: pop selection, pop (also clears the repeat map), in-round
+    // repeats, expansion, counts / statistics / best, cut selection, cut, then
+    // the end of the round together with the start of the next.
     hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, P);
     for (long long r = 0;; ++r) {
         select(false);
