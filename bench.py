@@ -32,6 +32,9 @@ W_OPS = 2 * (L - 1)
 W2_OPS = 4 * (L - 1)
 # gfx950 integer VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
+# Bloom filter of the first step's own walk: 2^15 bits and 8 probes per walker
+# (about 5e-4 false positives per test once T_i = 4(L+1) keys are in at L = 501).
+BLOOM = (15, 8)
 
 
 def log(msg: str) -> None:
@@ -55,6 +58,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the uneven-length batched launch measurement")
     ap.add_argument("--batched-steps", type=int, default=20000)
+    ap.add_argument("--no-bloom", action="store_true",
+                    help="skip the Bloom-filter walk measurement")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the first-step rates of the L=101 and L=451/475/527 configurations")
     ap.add_argument("--ab-seeds", type=int, default=1,
@@ -207,6 +212,36 @@ def batched_measure(a, labs, dev):
             "per_L_flip_evals_per_s": {str(k): round(v, -6) for k, v in per_L.items()}}
 
 
+def bloom_measure(a, labs, dev):
+    """The first step with the Bloom filter of Algorithm 1 at the bench's shape
+    (L = 501, p = 16, the bench's walker count, T_i = 4(L+1) steps, 2^15 bits and
+    8 probes per walker) beside the tabu walker for the same steps: kernel rate,
+    its ALU fraction on the nominal count, and the best F reached."""
+    import torch
+    T_i = 4 * (L + 1)
+    out = {"L": L, "p": P, "walkers": a.walkers, "steps": T_i,
+           "bloom": {"log2_bits": BLOOM[0], "n_hash": BLOOM[1]}}
+    for name, kw, kern in (("tabu", dict(tenure_lo=L // 10, tenure_hi=L // 5), "walk"),
+                           ("bloom", dict(tenure_lo=0, tenure_hi=0, bloom=BLOOM), "walk_bloom")):
+        for rep in range(2):
+            labs.timing_reset()
+            labs.timing_enable(True)
+            r = labs.walk_step1(L, P, T_i, kw["tenure_lo"], kw["tenure_hi"], 31 + rep, a.walkers,
+                                bloom=kw.get("bloom"), device=dev)
+            torch.cuda.synchronize()
+            labs.timing_enable(False)
+        ms, _ = labs.timing_read(kern)
+        fe = int(r.flip_evals.item())
+        ach = fe * W_OPS / (ms / 1e3) / 1e12
+        out[name] = {"kernel_ms": ms, "flip_evals": fe, "flip_evals_per_s": fe / (ms / 1e3),
+                     "alu_frac": ach / (PEAK_INT_OPS / 1e12),
+                     "best_F": L * L / (2.0 * int(r.best_E.min().item())),
+                     "mean_best_F": float((L * L / (2.0 * r.best_E.double())).mean().item())}
+    log("bloom walk: %.3e flip-evals/s, best F %.3f (tabu %.3f)"
+        % (out["bloom"]["flip_evals_per_s"], out["bloom"]["best_F"], out["tabu"]["best_F"]))
+    return out
+
+
 def learned_ab(a, labs, dev):
     """Learned proposal against the plain walker at equal wall budgets (L = 501,
     p = 16, the bench's walker count): log plain-walker pairs (seed 5), train the
@@ -215,7 +250,9 @@ def learned_ab(a, labs, dev):
     the budget from seed 1001: the plain walker, the trained network (top-8, a
     full scan every 64 steps), the untrained network and a random top-8.  The
     time to reach F >= tau* is the first hit step over all walkers times the arm's
-    measured time per step (walkers advance in lockstep)."""
+    measured time per step (walkers advance in lockstep).  A further arm runs the
+    paper's own first step, the Bloom-filter walk of T_i = 4(L+1) steps, in
+    batches of fresh walkers for the same budget."""
     import numpy as np
     import torch
     import labs_inputs as li
@@ -287,6 +324,48 @@ def learned_ab(a, labs, dev):
                 "hit_step": first(e_max) if e_max >= 0 else None, "ladder_hit_steps": hits,
                 "flip_evals": int(r.flip_evals.item()), "pool_dropped": int(pool.dropped.item())}
 
+    T_i = 4 * (L + 1)
+
+    def bloom_run(budget_s, seed, e_max):
+        # Algorithm 1 as the paper runs it: every walker stops after T_i = 4(L+1)
+        # steps, so fresh batches of walkers (new ids) are launched until the
+        # budget is spent; a level's hit time is the start of the batch that first
+        # reaches it plus the fraction of that batch up to its earliest hit step
+        e_pool = max(e_max, int(np.floor(L * L / (2.0 * ladder[0])))) if e_max >= 0 else -1
+        pool = labs.PoolBuffers.empty(L, 1 << 20, device=dev)
+        hits = {str(tl): None for tl in ladder}
+        hit = None
+        t_total, b, best, flips = 0.0, 0, None, 0
+        while t_total < budget_s:
+            pool.count.zero_()
+            pool.dropped.zero_()
+            sync()
+            t0 = time.perf_counter()
+            r = labs.walk_step1(L, P, T_i, 0, 0, seed, n, walker_begin=b * n, e_max=e_pool, pool=pool,
+                                bloom=BLOOM, device=dev)
+            sync()
+            dt = time.perf_counter() - t0
+            c = int(pool.count.item())
+            pE = pool.E[:c].cpu().numpy()
+            pS = pool.step[:c].cpu().numpy()
+
+            def at(em):
+                sel = pS[pE <= em]
+                return t_total + sel.min() / T_i * dt if sel.size else None
+            for tl in ladder:
+                if hits[str(tl)] is None:
+                    hits[str(tl)] = at(int(np.floor(L * L / (2.0 * tl))))
+            if hit is None and e_max >= 0:
+                hit = at(e_max)
+            e = int(r.best_E.min().item())
+            best = e if best is None or e < best else best
+            flips += int(r.flip_evals.item())
+            t_total += dt
+            b += 1
+        return {"seconds": t_total, "steps": b * T_i, "batches": b, "steps_per_walk": T_i,
+                "bloom": {"log2_bits": BLOOM[0], "n_hash": BLOOM[1]}, "best_E": best,
+                "time_to_tau_s": hit, "ladder_time_s": hits, "flip_evals": flips}
+
     def learned_run(steps, seed, e_max, kw):
         sync()
         t0 = time.perf_counter()
@@ -323,6 +402,8 @@ def learned_ab(a, labs, dev):
         steps = max(64, int(rate["plain"] * a.ab_budget))
         out["plain"] = plain_run(steps, seed, e_max)
         log("seed %d plain: best E %d" % (seed, out["plain"]["best_E"]))
+        out["bloom"] = bloom_run(a.ab_budget, seed, e_max)
+        log("seed %d bloom: best E %d" % (seed, out["bloom"]["best_E"]))
         for name, kw in arms.items():
             steps = max(64, int(rate[name] * a.ab_budget))
             steps -= steps % 64
@@ -330,8 +411,9 @@ def learned_ab(a, labs, dev):
             log("seed %d %s: best E %d" % (seed, name, out[name]["best_E"]))
         for name, o in out.items():
             o["best_F"] = L * L / (2.0 * o["best_E"])
-            o["time_to_tau_s"] = (o["hit_step"] / o["steps"] * o["seconds"]
-                                  if o["hit_step"] is not None else None)
+            if "time_to_tau_s" not in o:
+                o["time_to_tau_s"] = (o["hit_step"] / o["steps"] * o["seconds"]
+                                      if o["hit_step"] is not None else None)
             o["walker_steps_per_s"] = n * o["steps"] / o["seconds"]
             o["flip_evals_per_s"] = o["flip_evals"] / o["seconds"]
         o = out["plain"]
@@ -364,7 +446,7 @@ def main():
         return
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(walkers shard by id range; see DESIGN.md)", file=sys.stderr)
+              "(walkers shard across GPUs by walker-id range; only the one-GPU path is built)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2409_07222_amd import labs
@@ -461,6 +543,7 @@ def main():
     log("dual-step passes done: %.3e flip-evals/s" % (evals / dt))
     batched = None if a.no_batched else batched_measure(a, labs, dev)
     configs = None if a.no_configs else step1_configs(a, labs, dev)
+    bloom = None if a.no_bloom else bloom_measure(a, labs, dev)
     ab = None
     if not a.no_ab:
         s2_ws = None
@@ -491,6 +574,7 @@ def main():
         "learned_ab": ab,
         "batched_uneven_L": batched,
         "step1_configs": configs,
+        "bloom_walk": bloom,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

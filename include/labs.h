@@ -134,7 +134,11 @@ typedef struct {
  * distinct sequences in (its previous contents) U (this call's offers), sorted
  * ascending; `walker`/`step` of an entry are those of its earliest offer in
  * (walker, step) order.  Overflow is not an error: *dropped grows by the number
- * of distinct sequences cut by the capacity. */
+ * of distinct sequences that reached the pool and were cut by the capacity.
+ * Once the pool is full a walker no longer hands over a sequence whose energy
+ * is above the pool's largest (it could not enter), so such sequences are not
+ * counted: *dropped is a lower bound on the distinct offers the pool lacks, and
+ * exact while the pool is not full. */
 typedef struct {
     uint32_t* seqs;     /* [capacity*W] */
     int32_t* E;         /* [capacity] */
@@ -177,6 +181,38 @@ labs_status labs_walk_step1_workspace(const labs_step1_cfg* cfg, int32_t n_cfg,
 labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void* prop,
                             labs_pool* pools, labs_step1_out* outs, void* ws, size_t ws_bytes,
                             void* stream);
+
+/* ----------------------------------------------------------------------------
+ * First step with the Bloom filter of Alg. 1 (Sec. 3) in place of the tabu
+ * tenure.  The walker, its stream, its initial sequence and the sieve are those
+ * of labs_walk_step1; tenure_lo and tenure_hi must be 0.  Each walker owns a
+ * Bloom filter (Bloom 1970) of m = 2^log2_bits bits.  A sequence is keyed by
+ *   h(S) = XOR of Z_i over i = 1..k+1 with s_i = +1,
+ * Z_i being output i-1 of the SplitMix64 stream whose state starts at
+ * 0x6A09E667F3BCC909 (the table the second step keys sequences with), and a key
+ * sets / tests the n_hash bits (g1 + j g2) mod m, j = 0..n_hash-1, with g1 the
+ * low 32 bits of h, g2 its high 32 bits with the lowest bit set, arithmetic
+ * modulo 2^32 (double hashing, Kirsch and Mitzenmacher 2006).  The initial
+ * sequence is inserted; at step t every free position a = p+1..k+1 is evaluated,
+ * a neighbour is unexplored when its key is not in the filter, the walker takes
+ * the unexplored a with the lowest (dE_a, a), even uphill, inserts the new
+ * sequence and E += dE_a; with no unexplored neighbour the walk stops (its
+ * remaining trajectory is -1).  The filter sits in LDS for each launch segment
+ * and in the workspace (n_walkers * m / 8 bytes) between segments.
+ * steps = 0 is the paper's T_i = 4(L+1).  One configuration per call; pool and
+ * outputs as in labs_walk_step1 with n_cfg = 1, results again independent of
+ * how the walker range is split.
+ */
+typedef struct {
+    int32_t log2_bits;    /* filter bits per walker m = 2^log2_bits, 6..18 */
+    int32_t n_hash;       /* bits set and tested per key, 1..16 */
+    int32_t reserved[2];  /* must be 0 */
+} labs_bloom;
+
+labs_status labs_walk_step1_bloom_workspace(const labs_step1_cfg* cfg, const labs_bloom* bloom,
+                                            int64_t pool_capacity, size_t* bytes);
+labs_status labs_walk_step1_bloom(const labs_step1_cfg* cfg, const labs_bloom* bloom, labs_pool* pool,
+                                  labs_step1_out* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------
  * Autotuner of the walker's tiles.  A shape class is (NW, R): NW = ceil(k/32)

@@ -149,13 +149,15 @@ bool uses_pool(const labs_step1_cfg& c) {
 struct WalkLayout {
     size_t state_bytes = 0;   // one contiguous block, checkpointed as a unit
     size_t off_seq = 0, off_E = 0, off_ten = 0, off_halt = 0, off_tabu = 0, off_bE = 0, off_bT = 0,
-           off_bS = 0;
+           off_bS = 0, off_zh = 0, off_bloom = 0;
     int64_t S = 0, cap = 0;
     int32_t KW = 0;
     size_t total = 0;
 };
 
-WalkLayout walk_layout(const labs_step1_cfg& c, int64_t pool_cap, bool pool) {
+// bloom: the Bloom walk's filters and keys join the state block (no tabu table).
+WalkLayout walk_layout(const labs_step1_cfg& c, int64_t pool_cap, bool pool,
+                       const labs_bloom* bloom = nullptr) {
     WalkLayout lo;
     const int64_t n = c.n_walkers;
     const int W = words_of(c.L);
@@ -171,10 +173,14 @@ WalkLayout walk_layout(const labs_step1_cfg& c, int64_t pool_cap, bool pool) {
     lo.off_E = put(sizeof(int32_t) * n);
     lo.off_ten = put(sizeof(int32_t) * n);
     lo.off_halt = put(sizeof(int32_t) * n);
-    lo.off_tabu = put(sizeof(int32_t) * n * nf);
+    lo.off_tabu = put(bloom ? 0 : sizeof(int32_t) * n * nf);
     lo.off_bE = put(sizeof(int32_t) * n);
     lo.off_bT = put(sizeof(int32_t) * n);
     lo.off_bS = put(sizeof(uint32_t) * n * W);
+    if (bloom) {
+        lo.off_zh = put(sizeof(uint64_t) * n);
+        lo.off_bloom = put((size_t)n << (bloom->log2_bits - 3));
+    }
     lo.state_bytes = o;
     size_t total = o;
     if (pool) {
@@ -197,6 +203,18 @@ labs_status check_pool(const labs_pool* pl) {
         return invalid("pool capacity must be in [1, 2^31)");
     if (!pl->seqs || !pl->E || !pl->count || !pl->dropped)
         return invalid("pool seqs, E, count and dropped must not be NULL");
+    return LABS_OK;
+}
+
+labs_status check_bloom(const labs_step1_cfg& c, const labs_bloom* b) {
+    if (!b) return invalid("bloom must not be NULL");
+    if (b->log2_bits < 6 || b->log2_bits > 18)
+        return invalid("Bloom filter bits must be 2^6..2^18 per walker, got 2^%d", b->log2_bits);
+    if (b->n_hash < 1 || b->n_hash > 16) return invalid("n_hash must be in [1, 16], got %d", b->n_hash);
+    if (b->reserved[0] || b->reserved[1]) return invalid("bloom reserved fields must be 0");
+    if (c.tenure_lo != 0 || c.tenure_hi != 0) return invalid("a Bloom walk takes no tenure (lo = hi = 0)");
+    if ((uint64_t)c.n_walkers << (b->log2_bits - 3) > (1ull << 40))
+        return invalid("Bloom filters of %lld walkers exceed 1 TiB", (long long)c.n_walkers);
     return LABS_OK;
 }
 
@@ -285,30 +303,17 @@ labs_status labs_walk_step1_workspace(const labs_step1_cfg* cfg, int32_t n_cfg, 
     return LABS_OK;
 }
 
-labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void* prop,
-                            labs_pool* pools, labs_step1_out* outs, void* ws, size_t ws_bytes,
-                            void* stream) {
-    clear_error();
-    if (!cfg || !outs) return invalid("cfg and outs must not be NULL");
-    if (prop) return invalid("prop must be NULL for the plain walker");
-    if (n_cfg > 1) {
-        labs_status sb = check_batch(cfg, n_cfg);
-        if (sb != LABS_OK) return sb;
-        if (pools) return invalid("batched walks take no pool");
-        for (int i = 0; i < n_cfg; ++i)
-            if (!outs[i].final_seqs || !outs[i].final_E) return invalid("final_seqs and final_E must not be NULL");
-        if (!ws) return invalid("workspace must not be NULL");
-        LaunchTimer tb("walk_batched");
-        if ((sb = tb.begin(S(stream))) != LABS_OK) return sb;
-        if ((sb = batch_walk(cfg, n_cfg, outs, ws, ws_bytes, S(stream), nullptr, true)) != LABS_OK) return sb;
-        if ((sb = tb.end(S(stream))) != LABS_OK) return sb;
-        return tb.flush();
-    }
-    if (n_cfg != 1) return invalid("n_cfg must be >= 1");
-    const labs_step1_cfg c = cfg[0];
+}  // extern "C"
+
+namespace {
+
+// One configuration in segmented launches (tabu tenure, or the Bloom filter when
+// `bloom` is set).
+labs_status walk_single(const labs_step1_cfg& c, const labs_bloom* bloom, labs_pool* pools,
+                        const labs_step1_out& o, void* ws, size_t ws_bytes, hipStream_t st) {
     labs_status s = check_step1_cfg(c);
     if (s != LABS_OK) return s;
-    const labs_step1_out o = outs[0];
+    if (bloom && (s = check_bloom(c, bloom)) != LABS_OK) return s;
     if (!o.final_seqs || !o.final_E) return invalid("final_seqs and final_E must not be NULL");
     const bool pool = uses_pool(c);
     labs_pool pl{};
@@ -317,12 +322,11 @@ labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void
         pl = pools[0];
     }
     if (!ws) return invalid("workspace must not be NULL");
-    const WalkLayout lo = walk_layout(c, pool ? pl.capacity : 0, pool);
+    const WalkLayout lo = walk_layout(c, pool ? pl.capacity : 0, pool, bloom);
     if (ws_bytes < lo.total) {
         set_error("workspace needs %zu bytes, got %zu", lo.total, ws_bytes);
         return LABS_E_NOMEM;
     }
-    hipStream_t st = S(stream);
     const int L = c.L, k = (L - 1) / 2, W = words_of(L);
     const int steps = c.steps ? c.steps : 4 * (L + 1);
     char* base = (char*)ws;
@@ -349,9 +353,17 @@ labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void
     A.traj = o.traj_E;
     A.e_max = c.e_max;
     A.thr = nullptr;
+    if (bloom) {
+        A.tabu = nullptr;
+        A.zh = (uint64_t*)(base + lo.off_zh);
+        A.bloom = (uint32_t*)(base + lo.off_bloom);
+        A.bloom_log2 = bloom->log2_bits;
+        A.bloom_hashes = bloom->n_hash;
+    }
 
     if ((s = launch_walker_init(A, st)) != LABS_OK) return s;
-    LaunchTimer tw("walk");
+    if (bloom && (s = launch_bloom_init(A, st)) != LABS_OK) return s;
+    LaunchTimer tw(bloom ? "walk_bloom" : "walk");
     auto walk = [&]() -> labs_status {
         labs_status r;
         if ((r = tw.begin(st)) != LABS_OK) return r;
@@ -452,6 +464,55 @@ labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void
     A.t1 = steps;
     if ((s = launch_walk_outputs(A, o, st)) != LABS_OK) return s;
     return tw.flush();
+}
+
+}  // namespace
+
+extern "C" {
+
+labs_status labs_walk_step1(const labs_step1_cfg* cfg, int32_t n_cfg, const void* prop,
+                            labs_pool* pools, labs_step1_out* outs, void* ws, size_t ws_bytes,
+                            void* stream) {
+    clear_error();
+    if (!cfg || !outs) return invalid("cfg and outs must not be NULL");
+    if (prop) return invalid("prop must be NULL for the plain walker");
+    if (n_cfg > 1) {
+        labs_status sb = check_batch(cfg, n_cfg);
+        if (sb != LABS_OK) return sb;
+        if (pools) return invalid("batched walks take no pool");
+        for (int i = 0; i < n_cfg; ++i)
+            if (!outs[i].final_seqs || !outs[i].final_E) return invalid("final_seqs and final_E must not be NULL");
+        if (!ws) return invalid("workspace must not be NULL");
+        LaunchTimer tb("walk_batched");
+        if ((sb = tb.begin(S(stream))) != LABS_OK) return sb;
+        if ((sb = batch_walk(cfg, n_cfg, outs, ws, ws_bytes, S(stream), nullptr, true)) != LABS_OK) return sb;
+        if ((sb = tb.end(S(stream))) != LABS_OK) return sb;
+        return tb.flush();
+    }
+    if (n_cfg != 1) return invalid("n_cfg must be >= 1");
+    return walk_single(cfg[0], nullptr, pools, outs[0], ws, ws_bytes, S(stream));
+}
+
+labs_status labs_walk_step1_bloom_workspace(const labs_step1_cfg* cfg, const labs_bloom* bloom,
+                                            int64_t pool_capacity, size_t* bytes) {
+    clear_error();
+    if (!cfg || !bytes) return invalid("cfg and bytes must not be NULL");
+    labs_status s = check_step1_cfg(*cfg);
+    if (s != LABS_OK) return s;
+    if ((s = check_bloom(*cfg, bloom)) != LABS_OK) return s;
+    const bool pool = uses_pool(*cfg);
+    if (pool && (pool_capacity < 1 || pool_capacity > (int64_t)INT32_MAX))
+        return invalid("pool capacity must be in [1, 2^31)");
+    *bytes = walk_layout(*cfg, pool ? pool_capacity : 0, pool, bloom).total;
+    return LABS_OK;
+}
+
+labs_status labs_walk_step1_bloom(const labs_step1_cfg* cfg, const labs_bloom* bloom, labs_pool* pool,
+                                  labs_step1_out* out, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (!cfg || !out) return invalid("cfg and out must not be NULL");
+    if (!bloom) return invalid("bloom must not be NULL");
+    return walk_single(*cfg, bloom, pool, *out, ws, ws_bytes, S(stream));
 }
 
 static labs_status check_step2_cfg(const labs_step2_cfg& c, int64_t n_cand) {

@@ -60,6 +60,11 @@ __device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
 __device__ __forceinline__ uint64_t sm64_at(uint64_t key, uint64_t i) {
     return sm64_mix(key + (i + 1ull) * 0x9E3779B97F4A7C15ull);
 }
+// Zobrist table of sequence keys (Zobrist 1970): Z for position i+1 is output i
+// of the SplitMix64 stream started at kZobristState.  The second step keys whole
+// sequences with it, the first step's Bloom filter the first k+1 elements.
+constexpr uint64_t kZobristState = 0x6A09E667F3BCC909ull;
+__device__ __forceinline__ uint64_t zobrist_at(int i) { return sm64_at(kZobristState, (uint64_t)i); }
 __device__ __forceinline__ uint64_t walker_key(uint64_t seed, int32_t L, int64_t w) {
     uint64_t lw = ((uint64_t)(uint32_t)L << 32) ^ (uint64_t)(w + 1);
     return sm64_mix(seed ^ sm64_mix(lw));
@@ -123,6 +128,11 @@ struct WalkArgs {
     int64_t rec_stride;
     uint32_t* st_count;
     uint32_t st_cap;
+    // Bloom-filter self-avoidance (null bloom: the tabu tenure)
+    uint64_t* zh;          // [n] Zobrist key of the current sequence's first k+1 elements
+    uint32_t* bloom;       // [n << (bloom_log2 - 5)] filter words per walker
+    int32_t bloom_log2;    // filter bits per walker = 2^bloom_log2
+    int32_t bloom_hashes;  // bits set / tested per key
 };
 bool walk_shape_supported(int L, int p);
 size_t step2_workspace_bytes(const labs_step2_cfg& c, long long n_cand);
@@ -132,6 +142,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
                       labs_status (*tb)(void*, hipStream_t), labs_status (*te)(void*, hipStream_t),
                       void* tctx);
 labs_status launch_walker_init(const WalkArgs& A, hipStream_t st);
+labs_status launch_bloom_init(const WalkArgs& A, hipStream_t st);
 labs_status launch_walker_init_items(const WalkArgs* args, const int2* items, int n_items, hipStream_t st);
 // Autotuned register tile (slots per pass) for the walker of (L, p); R when untuned.
 int walk_tile_rb(int L, int p, int R);

@@ -49,7 +49,6 @@ namespace {
 
 constexpr int32_t DEAD = INT32_MAX;
 constexpr uint32_t ST_OPEN = 1, ST_CLOSED = 2, ST_EVICTED = 3;
-constexpr uint64_t ZKEY = 0x6A09E667F3BCC909ull;   // Zobrist stream key
 // Radix digit of the energy select.  All energies of one length L are congruent
 // mod 4 (C_k has the parity of L-k, so C_k^2 is 0 mod 4 or 1 mod 8), so the
 // select works on (E - emin)/4.  E <= sum_{j<L} j^2 = (L-1)L(2L-1)/6 < 2^29 for
@@ -139,7 +138,7 @@ struct Params {
     uint8_t* repeat;
 };
 
-__device__ __forceinline__ uint64_t zob(int i) { return sm64_at(ZKEY, (uint64_t)i); }
+__device__ __forceinline__ uint64_t zob(int i) { return zobrist_at(i); }
 
 // Block-aggregated append: every thread of the block must call it (uniformly).
 __device__ long long block_append(long long* counter, bool take) {

@@ -1,4 +1,5 @@
-// First step (Algorithm 1 with a tabu tenure): walker init and the walk.
+// First step (Algorithm 1, with a tabu tenure or with its Bloom filter): walker
+// init and the walk.
 //
 // One wavefront runs one walker.  Notation: L = 2k+1, even lags d = 2m,
 // m = 1..K with K = k (odd-lag C vanish for skew sequences, Sec. 1).  Free
@@ -95,7 +96,8 @@ __device__ void walker_init_body(const WalkArgs& A, int64_t j, Lds<10>& S) {
         A.seq[j * W + lane] = S.pk[lane];
         A.bestSeq[j * W + lane] = S.pk[lane];
     }
-    for (int i = lane; i < A.nf; i += 64) A.tabu[j * A.nf + i] = 0;
+    if (A.tabu)   // null for Bloom-filter walks
+        for (int i = lane; i < A.nf; i += 64) A.tabu[j * A.nf + i] = 0;
     if (lane == 0) {
         A.E[j] = e;
         A.tenure[j] = ten;
@@ -116,6 +118,37 @@ __global__ __launch_bounds__(64) void k_walker_init_items(const WalkArgs* args, 
     const int2 it = items[blockIdx.x];
     const WalkArgs A = args[it.x];
     walker_init_body(A, (int64_t)it.y, S);
+}
+
+// Bloom-filter walks: the key of each walker's initial sequence (Zobrist XOR over
+// the +1 elements among s_1..s_{k+1}), and its filter holding only that key.
+__global__ __launch_bounds__(64) void k_bloom_init(WalkArgs A) {
+    const int lane = threadIdx.x;
+    const int64_t j = blockIdx.x;
+    const uint32_t* s = A.seq + j * A.W;
+    uint64_t h = 0;
+    for (int i = 1 + lane; i <= A.k + 1; i += 64)
+        if (packed_bit(s, i)) h ^= zobrist_at(i - 1);
+    uint32_t lo = (uint32_t)h, hi = (uint32_t)(h >> 32);
+    for (int o = 32; o > 0; o >>= 1) {
+        lo ^= (uint32_t)__shfl_xor((int)lo, o, 64);
+        hi ^= (uint32_t)__shfl_xor((int)hi, o, 64);
+    }
+    h = ((uint64_t)hi << 32) | lo;
+    const int nbw = 1 << (A.bloom_log2 - 5);
+    const uint32_t mask = (1u << A.bloom_log2) - 1u;
+    const uint32_t g2 = hi | 1u;
+    uint32_t* f = A.bloom + j * (int64_t)nbw;
+    for (int w = lane; w < nbw; w += 64) {
+        uint32_t v = 0, x = lo;
+        for (int q = 0; q < A.bloom_hashes; ++q) {
+            const uint32_t b = x & mask;
+            if ((int)(b >> 5) == w) v |= 1u << (b & 31);
+            x += g2;
+        }
+        f[w] = v;
+    }
+    if (lane == 0) A.zh[j] = h;
 }
 
 // Offer every walker's best sequence to the staging buffer.
@@ -194,12 +227,24 @@ labs_status launch_walker_init(const WalkArgs& A, hipStream_t st) {
     return LABS_OK;
 }
 
+labs_status launch_bloom_init(const WalkArgs& A, hipStream_t st) {
+    hipLaunchKernelGGL(k_bloom_init, dim3((unsigned)A.n), dim3(64), 0, st, A);
+    LABS_LAUNCHED("k_bloom_init");
+    return LABS_OK;
+}
+
 labs_status launch_walk(const WalkArgs& A, hipStream_t st) {
     const int NW = (A.k + 31) / 32;
     const int R = (A.nf + 63) / 64;
     WalkKernels wk;
     if (!walk_kernels_lookup(NW, R, walk_tile_rb(A.L, A.p, R), &wk))
         return invalid("no walker kernel for L=%d p=%d", A.L, A.p);
+    if (A.bloom) {
+        const size_t lds = sizeof(uint32_t) << (A.bloom_log2 - 5);
+        hipLaunchKernelGGL(wk.bloom, dim3((unsigned)A.n), dim3(64), lds, st, A);
+        LABS_LAUNCHED("k_walk_bloom");
+        return LABS_OK;
+    }
     hipLaunchKernelGGL(wk.plain, dim3((unsigned)A.n), dim3(64), 0, st, A);
     LABS_LAUNCHED("k_walk");
     return LABS_OK;

@@ -135,8 +135,10 @@ __device__ __forceinline__ void build_windows(const Lds<NW>& S, int p, int k, in
 // One walker (walker index j of configuration A) for steps t0+1..t1.  Slots are
 // scanned in groups of RB (R = RB: one pass with every window resident; smaller
 // RB: fewer window registers, the bit planes re-ballotted once per group).
-template <int NW, int R, int RB>
-__device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>& S) {
+// BL: self-avoidance by the walker's Bloom filter (copied into `bl` in LDS for
+// the segment) instead of the tabu tenure.
+template <int NW, int R, int RB, bool BL>
+__device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>& S, uint32_t* bl) {
     constexpr int NQ = (NW + 1) / 2;
     constexpr int PADL = Lds<NW>::PADL;
     constexpr int NG = (R + RB - 1) / RB;
@@ -162,10 +164,28 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
     compute_cev<NW>(S, L, K, lane, C);
     store_tables<NW>(S, K, lane, C);
     int32_t tabu[R];
+    uint64_t zr[R];        // Bloom: Zobrist entry of each slot's position
+    uint64_t hk = 0;       // Bloom: key of the current sequence
+    int last_a = -1;       // Bloom: position flipped by the previous step of this segment
+    uint32_t* gbl = nullptr;
+    const int nbw = BL ? 1 << (A.bloom_log2 - 5) : 0;
+    const uint32_t bmask = BL ? (1u << A.bloom_log2) - 1u : 0u;
+    const int nh = BL ? A.bloom_hashes : 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         int i = lane + 64 * r;
-        tabu[r] = (i < nf) ? A.tabu[j * nf + i] : INT_MAX;
+        if constexpr (BL) {
+            tabu[r] = 0;
+            zr[r] = zobrist_at(p + (i < nf ? i : nf - 1));
+        } else {
+            tabu[r] = (i < nf) ? A.tabu[j * nf + i] : INT_MAX;
+            zr[r] = 0;
+        }
+    }
+    if constexpr (BL) {
+        gbl = A.bloom + j * (int64_t)nbw;
+        for (int i = lane; i < nbw; i += 64) bl[i] = gbl[i];
+        hk = A.zh[j];
     }
     int E = A.E[j];
     int bestE = A.bestE[j];
@@ -254,20 +274,64 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
                     d = -8 * sa * G + 16 * Q;
                 }
                 dlt[r] = d;
-                adm[r] = valid && tabu[r] < t;
+                // Bloom: undoing the last move returns to a sequence the filter holds
+                // (no false negatives), so that slot is out without a probe; the
+                // others are tested below, best candidate first
+                if constexpr (BL) adm[r] = valid && a0 != last_a;
+                else adm[r] = valid && tabu[r] < t;
                 if (adm[r]) dmin = min(dmin, d);
             }
         }
-        const int g = __ockl_wfred_min_i32(dmin);
+        int g = INT_MAX, astar = -1;
+        uint64_t hnext = 0;
+        for (;;) {
+            g = __ockl_wfred_min_i32(dmin);
+            if (g == INT_MAX) break;
+            astar = -1;
+            int owner = 0, rsel = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint64_t m = __ballot(adm[r] && dlt[r] == g);
+                if (astar < 0 && m) {
+                    owner = __ffsll((unsigned long long)m) - 1;
+                    rsel = r;
+                    astar = p + 1 + 64 * r + owner;
+                }
+            }
+            if constexpr (!BL) {
+                break;
+            } else {
+                // Bloom: the lowest (dE, a) not in the filter.  Test the current
+                // best candidate (probe q on lane q); a member is excluded and the
+                // next best taken, so each pass removes one slot and the loop ends.
+                uint64_t z = 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (r == rsel) z = zr[r];
+                const uint32_t zlo = __builtin_amdgcn_readlane((uint32_t)z, owner);
+                const uint32_t zhi = __builtin_amdgcn_readlane((uint32_t)(z >> 32), owner);
+                const uint64_t key = hk ^ (((uint64_t)zhi << 32) | zlo);
+                bool set = true;
+                if (lane < nh) {
+                    const uint32_t b =
+                        ((uint32_t)key + (uint32_t)lane * ((uint32_t)(key >> 32) | 1u)) & bmask;
+                    set = (bl[b >> 5] >> (b & 31)) & 1u;
+                }
+                if (__ballot(!set)) {
+                    hnext = key;
+                    break;
+                }
+                dmin = INT_MAX;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (p + 1 + lane + 64 * r == astar) adm[r] = false;
+                    if (adm[r]) dmin = min(dmin, dlt[r]);
+                }
+            }
+        }
         if (g == INT_MAX) {
             halted = t;
             break;
-        }
-        int astar = -1;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint64_t m = __ballot(adm[r] && dlt[r] == g);
-            if (astar < 0 && m) astar = p + 1 + 64 * r + (__ffsll((unsigned long long)m) - 1);
         }
         // ---- apply: C update from the old sequence
         const int as = astar, bs = L + 1 - astar;
@@ -286,10 +350,21 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
             }
         }
         E += g;
+        if constexpr (!BL) {
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (p + 1 + lane + 64 * r == as) tabu[r] = t + tenure;
+            for (int r = 0; r < R; ++r)
+                if (p + 1 + lane + 64 * r == as) tabu[r] = t + tenure;
+        }
         __syncthreads();
+        if constexpr (BL) {
+            // insert the new sequence's key; read by the next step after the barrier below
+            hk = hnext;
+            last_a = as;
+            if (lane < nh) {
+                const uint32_t b = ((uint32_t)hk + (uint32_t)lane * ((uint32_t)(hk >> 32) | 1u)) & bmask;
+                atomicOr(&bl[b >> 5], 1u << (b & 31));
+            }
+        }
         store_tables<NW>(S, K, lane, C);
         if (lane == 0 || (lane == 1 && !cen)) {
             const int x = lane == 0 ? as : bs;
@@ -329,10 +404,15 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
         A.seq[j * W + lane] = S.pk[lane];
         A.bestSeq[j * W + lane] = S.pkbest[lane];
     }
+    if constexpr (BL) {
+        for (int i = lane; i < nbw; i += 64) gbl[i] = bl[i];
+        if (lane == 0) A.zh[j] = hk;
+    } else {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        int i = lane + 64 * r;
-        if (i < nf) A.tabu[j * nf + i] = tabu[r];
+        for (int r = 0; r < R; ++r) {
+            int i = lane + 64 * r;
+            if (i < nf) A.tabu[j * nf + i] = tabu[r];
+        }
     }
     if (lane == 0) {
         A.E[j] = E;
@@ -346,7 +426,15 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
 template <int NW, int R, int RB>
 __global__ __launch_bounds__(64) void k_walk(WalkArgs A) {
     __shared__ Lds<NW> S;
-    walk_body<NW, R, RB>(A, blockIdx.x, S);
+    walk_body<NW, R, RB, false>(A, blockIdx.x, S, nullptr);
+}
+
+// Bloom-filter form: the walker's filter (2^bloom_log2 bits) in dynamic LDS.
+template <int NW, int R, int RB>
+__global__ __launch_bounds__(64) void k_walk_bloom(WalkArgs A) {
+    __shared__ Lds<NW> S;
+    extern __shared__ uint32_t bloom_words[];
+    walk_body<NW, R, RB, true>(A, blockIdx.x, S, bloom_words);
 }
 
 // Persistent form: each wavefront takes (configuration, walker) items from a
@@ -362,7 +450,7 @@ __global__ __launch_bounds__(64) void k_walk_persistent(const WalkArgs* args, co
         if (it >= (unsigned)n_items) break;
         const int2 w = items[it];
         const WalkArgs A = args[w.x];
-        walk_body<NW, R, RB>(A, (int64_t)w.y, S);
+        walk_body<NW, R, RB, false>(A, (int64_t)w.y, S, nullptr);
     }
 }
 
@@ -375,6 +463,7 @@ typedef void (*walk_persistent_t)(const WalkArgs*, const int2*, int, unsigned*);
 // (NW, R, RB); R is rounded up to an instantiated value, RB to R or ceil(R/2).
 struct WalkKernels {
     walkimpl::walk_kernel_t plain;
+    walkimpl::walk_kernel_t bloom;
     walkimpl::walk_persistent_t persistent;
     int R, RB;
 };

@@ -7,6 +7,7 @@ namespace {
 template <int NW, int R, int RB>
 void fill(WalkKernels* o) {
     o->plain = walkimpl::k_walk<NW, R, RB>;
+    o->bloom = walkimpl::k_walk_bloom<NW, R, RB>;
     o->persistent = walkimpl::k_walk_persistent<NW, R, RB>;
     o->R = R;
     o->RB = RB;

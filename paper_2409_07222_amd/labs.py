@@ -26,6 +26,11 @@ class LabsError(RuntimeError):
     pass
 
 
+class BloomCfg(ctypes.Structure):
+    _fields_ = [("log2_bits", ctypes.c_int32), ("n_hash", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
 class Step1Cfg(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("p", ctypes.c_int32), ("steps", ctypes.c_int32),
                 ("tenure_lo", ctypes.c_int32), ("tenure_hi", ctypes.c_int32),
@@ -118,6 +123,12 @@ def lib():
             L.labs_walk_step1.restype = i32
             L.labs_walk_step1.argtypes = [ctypes.POINTER(Step1Cfg), i32, vp, ctypes.POINTER(Pool),
                                           ctypes.POINTER(Step1Out), vp, sz, vp]
+            L.labs_walk_step1_bloom_workspace.restype = i32
+            L.labs_walk_step1_bloom_workspace.argtypes = [ctypes.POINTER(Step1Cfg), ctypes.POINTER(BloomCfg),
+                                                          i64, ctypes.POINTER(sz)]
+            L.labs_walk_step1_bloom.restype = i32
+            L.labs_walk_step1_bloom.argtypes = [ctypes.POINTER(Step1Cfg), ctypes.POINTER(BloomCfg),
+                                                ctypes.POINTER(Pool), ctypes.POINTER(Step1Out), vp, sz, vp]
             L.labs_pool_topk_workspace.restype = i32
             L.labs_pool_topk_workspace.argtypes = [i64, i32, ctypes.POINTER(sz)]
             L.labs_pool_topk.restype = i32
@@ -314,15 +325,23 @@ class Step1Result:
 def walk_step1(L: int, p: int, steps: int, tenure_lo: int, tenure_hi: int, seed: int,
                n_walkers: int, walker_begin: int = 0, e_max: int = -1,
                pool: PoolBuffers | None = None, want_traj: bool = False,
-               pool_walker_best: bool = False, device="cuda", workspace=None) -> Step1Result:
+               pool_walker_best: bool = False, device="cuda", workspace=None,
+               bloom: tuple | None = None) -> Step1Result:
+    """labs_walk_step1 for one configuration; with bloom = (log2_bits, n_hash),
+    labs_walk_step1_bloom (tenure_lo = tenure_hi = 0)."""
     torch = _torch()
     cfg = Step1Cfg(L, p, steps, tenure_lo, tenure_hi, e_max, walker_begin, n_walkers, seed,
                    LABS_POOL_WALKER_BEST if pool_walker_best else 0, 0)
+    bc = BloomCfg(bloom[0], bloom[1]) if bloom is not None else None
     W = words(L)
     steps_eff = steps if steps else 4 * (L + 1)
     cap = pool.capacity if pool is not None else 0
     sz = ctypes.c_size_t(0)
-    _check(lib().labs_walk_step1_workspace(ctypes.byref(cfg), 1, cap, ctypes.byref(sz)))
+    if bc is not None:
+        _check(lib().labs_walk_step1_bloom_workspace(ctypes.byref(cfg), ctypes.byref(bc), cap,
+                                                     ctypes.byref(sz)))
+    else:
+        _check(lib().labs_walk_step1_workspace(ctypes.byref(cfg), 1, cap, ctypes.byref(sz)))
     if workspace is None or workspace.numel() < sz.value:
         workspace = torch.empty(int(sz.value), dtype=torch.uint8, device=device)
     r = Step1Result(
@@ -338,10 +357,16 @@ def walk_step1(L: int, p: int, steps: int, tenure_lo: int, tenure_hi: int, seed:
                    r.best_E.data_ptr(), r.best_step.data_ptr(),
                    r.traj_E.data_ptr() if want_traj else None, r.flip_evals.data_ptr())
     ps = pool.struct() if pool is not None else None
-    _check(lib().labs_walk_step1(ctypes.byref(cfg), 1, None,
-                                 ctypes.byref(ps) if ps is not None else None,
-                                 ctypes.byref(out), _ptr(workspace), workspace.numel(),
-                                 _stream(torch.device(device))))
+    if bc is not None:
+        _check(lib().labs_walk_step1_bloom(ctypes.byref(cfg), ctypes.byref(bc),
+                                           ctypes.byref(ps) if ps is not None else None,
+                                           ctypes.byref(out), _ptr(workspace), workspace.numel(),
+                                           _stream(torch.device(device))))
+    else:
+        _check(lib().labs_walk_step1(ctypes.byref(cfg), 1, None,
+                                     ctypes.byref(ps) if ps is not None else None,
+                                     ctypes.byref(out), _ptr(workspace), workspace.numel(),
+                                     _stream(torch.device(device))))
     return r
 
 

@@ -130,3 +130,31 @@ def test_step2_validation_without_a_gpu():
     huge.max_expansions = 1 << 30              # the hash set would pass 2^31 slots
     assert L.labs_refine_step2_workspace(ctypes.byref(huge), 1024, ctypes.byref(sz)) == -1
     assert L.labs_refine_step2_workspace(ctypes.byref(ok), 0, ctypes.byref(sz)) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_bloom_walk_validation_without_a_gpu():
+    """labs_walk_step1_bloom_workspace is a host call: it sizes the per-walker
+    filters (n * 2^log2_bits / 8 bytes) and rejects out-of-range parameters."""
+    import ctypes as C
+    from paper_2409_07222_amd import labs
+    lib = labs.lib()
+
+    def ws(L=101, p=8, lo=0, hi=0, n=1000, log2=15, nh=8, res=(0, 0)):
+        cfg = labs.Step1Cfg(L, p, 0, lo, hi, -1, 0, n, 1, 0, 0)
+        b = labs.BloomCfg(log2, nh, (C.c_int32 * 2)(*res))
+        sz = C.c_size_t(0)
+        st = lib.labs_walk_step1_bloom_workspace(C.byref(cfg), C.byref(b), 0, C.byref(sz))
+        return st, sz.value
+
+    st, small = ws(log2=10)
+    assert st == 0
+    st, big = ws(log2=15)
+    assert st == 0 and big - small >= 1000 * ((1 << 15) - (1 << 10)) // 8
+    for bad in (dict(lo=1, hi=1), dict(log2=5), dict(log2=19), dict(nh=0), dict(nh=17),
+                dict(res=(1, 0)), dict(L=36)):
+        assert ws(**bad)[0] != 0, bad
+    cfg = labs.Step1Cfg(101, 8, 0, 0, 0, -1, 0, 10, 1, 0, 0)
+    sz = C.c_size_t(0)
+    assert lib.labs_walk_step1_bloom_workspace(C.byref(cfg), None, 0, C.byref(sz)) != 0
+    assert b"bloom" in lib.labs_last_error()
