@@ -380,6 +380,61 @@ def topk(entries, k: int):
     return pool(entries, k)[0]
 
 
+# ---------------------------------------------------------------- Legendre seeds
+def legendre_chi(n: int) -> np.ndarray:
+    """chi(a), a = 0..n-1, for an odd prime n by Euler's criterion: a^((n-1)/2) mod n
+    is 1 for quadratic residues; chi(0) = -1 (the construction's reading)."""
+    chi = np.array([1 if pow(a, (n - 1) // 2, n) == 1 else -1 for a in range(n)], dtype=np.int8)
+    chi[0] = -1
+    return chi
+
+
+def _is_prime(n: int) -> bool:
+    if n < 2:
+        return False
+    d = 2
+    while d * d <= n:
+        if n % d == 0:
+            return False
+        d += 1
+    return True
+
+
+def legendre_pairs(L: int, t_lo: int = 0, t_hi: int = 900, r_lo: int = 1800, r_hi: int = 2600):
+    """Sec. 4.1 sweep (a reading): every odd prime n <= L whose appended fraction
+    (L - n)/n lies in [t_lo, t_hi] / 10^4 and every rotation o with o/n in
+    [r_lo, r_hi] / 10^4, in (n, o) order.  The paper's narrower ranges
+    (0.055..0.063, 0.20..0.24) hold no prime at most lengths; this sweep's best
+    reproduces its construction column."""
+    out = []
+    for n in range(3, L + 1):
+        if not _is_prime(n):
+            continue
+        if not (t_lo * n <= (L - n) * 10000 <= t_hi * n):
+            continue
+        for o in range(n):
+            if r_lo * n <= o * 10000 <= r_hi * n:
+                out.append((n, o))
+    return out
+
+
+def legendre_sequence(n: int, o: int, L: int, chi=None) -> np.ndarray:
+    """The rotated Legendre sequence extended periodically: s_j = chi((j + o) mod n), j = 0..L-1."""
+    c = legendre_chi(n) if chi is None else chi
+    return c[(np.arange(L) + o) % n].astype(np.int8)
+
+
+def legendre_sweep(L: int, **kw):
+    """[(n, o, E)] over the sweep's pairs, each energy from the definition."""
+    out = []
+    chis = {}
+    for n, o in legendre_pairs(L, **kw):
+        if n not in chis:
+            chis[n] = legendre_chi(n)
+        out.append((n, o, energy(legendre_sequence(n, o, L, chis[n]))))
+    return out
+
+
 # ---------------------------------------------------------------- second step
 # Second-step tie order (a reading; the paper is silent on ties): (E, z, key)
 # where z is the sequence's Zobrist key -- the XOR, over the positions i with

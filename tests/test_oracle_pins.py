@@ -103,6 +103,26 @@ def test_legendre_construction_values(orc):
         assert "%.4f" % orc.merit_factor(L, E) == F
 
 
+def test_legendre_sweep_best_is_the_printed_construction(orc):
+    """Sec. 4.1 table: over the sweep (primes with appended fraction <= 0.09,
+    rotations 0.18..0.26 of n) the best construction's F is the printed one at all
+    four lengths, and it is the tabulated (n, o) pair; Euler's criterion agrees
+    with the squaring table of the input generator."""
+    for L, n, o, F in _rows("legendre_construct.txt"):
+        L, n, o = int(L), int(n), int(o)
+        sw = orc.legendre_sweep(L)
+        assert len(sw) > 40
+        bn, bo, bE = min(sw, key=lambda x: (x[2], x[0], x[1]))
+        assert "%.4f" % orc.merit_factor(L, bE) == F
+        assert (bn, bo) == (n, o)
+        assert np.array_equal(orc.legendre_chi(n), li.legendre_symbol_table(n))
+        assert np.array_equal(orc.legendre_sequence(n, o, L), li.legendre_rotated(n, o, L))
+    # the pair enumeration's boundaries are inclusive and exact
+    prs = orc.legendre_pairs(53, t_lo=0, t_hi=10000, r_lo=0, r_hi=10000)
+    assert (53, 0) in prs and (53, 52) in prs and (29, 28) in prs and (23, 0) not in prs
+    assert all(orc._is_prime(n) for n, _ in prs)
+
+
 def test_merit_factor_printed_values(orc):
     """Eq. (1) with the F values printed in Sec. 4: exactly one integer energy
     rounds to each printed F."""
