@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the uneven-length batched launch measurement")
     ap.add_argument("--batched-steps", type=int, default=20000)
+    ap.add_argument("--no-legendre", action="store_true",
+                    help="skip the Legendre-seeded second step at L = 450, 471, 491, 526")
+    ap.add_argument("--legendre-expansions", type=int, default=10_000_000)
     ap.add_argument("--no-bloom", action="store_true",
                     help="skip the Bloom-filter walk measurement")
     ap.add_argument("--no-configs", action="store_true",
@@ -239,6 +242,42 @@ def bloom_measure(a, labs, dev):
                      "mean_best_F": float((L * L / (2.0 * r.best_E.double())).mean().item())}
     log("bloom walk: %.3e flip-evals/s, best F %.3f (tabu %.3f)"
         % (out["bloom"]["flip_evals_per_s"], out["bloom"]["best_F"], out["tabu"]["best_F"]))
+    return out
+
+
+# Sec. 4.1 table: merit factor of the best construction and after the second step
+# ("DFS") seeded with the constructions, at four lengths (the paper's numbers).
+LEGENDRE_TABLE = {450: (6.1976, 6.3088), 471: (6.2332, 6.2998), 491: (6.4292, 6.4292),
+                  526: (6.3240, 6.3240)}
+
+
+def legendre_step2(a, labs, dev):
+    """The second step seeded with the Legendre-construction sweep (Sec. 4.1) at the
+    four tabulated lengths: the sweep's sequences and energies are built on the
+    device, then the second step runs from all of them (batch 1024, queue 2^20,
+    --legendre-expansions pops)."""
+    import torch
+    out = {"expansions": a.legendre_expansions, "batch": 1024, "queue": 1 << 20, "lengths": {}}
+    for Lq, (f_con, f_dfs) in LEGENDRE_TABLE.items():
+        n, o = labs.legendre_pairs(Lq)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        seqs, E = labs.legendre_build(Lq, n, o, device=dev)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        e0 = int(E.min().item())
+        t0 = time.perf_counter()
+        r = labs.refine_step2(Lq, seqs, 1024, 1 << 20, a.legendre_expansions, 1 << 62)
+        torch.cuda.synchronize()
+        t_s2 = time.perf_counter() - t0
+        out["lengths"][str(Lq)] = {
+            "pairs": int(len(n)), "build_s": t_build, "construction_F": Lq * Lq / (2.0 * e0),
+            "second_step_F": Lq * Lq / (2.0 * r["best_E"]), "second_step_s": t_s2,
+            "paper_construction_F": f_con, "paper_dfs_F": f_dfs,
+            "neighbour_evals_per_s": r["expansions"] * Lq / t_s2,
+            "rounds_to_best": r["best_round"] + 1}
+        log("legendre L=%d: construction F %.4f -> second step F %.4f (paper %.4f -> %.4f)"
+            % (Lq, Lq * Lq / (2.0 * e0), Lq * Lq / (2.0 * r["best_E"]), f_con, f_dfs))
     return out
 
 
@@ -544,6 +583,7 @@ def main():
     batched = None if a.no_batched else batched_measure(a, labs, dev)
     configs = None if a.no_configs else step1_configs(a, labs, dev)
     bloom = None if a.no_bloom else bloom_measure(a, labs, dev)
+    legendre = None if a.no_legendre else legendre_step2(a, labs, dev)
     ab = None
     if not a.no_ab:
         s2_ws = None
@@ -575,6 +615,7 @@ def main():
         "batched_uneven_L": batched,
         "step1_configs": configs,
         "bloom_walk": bloom,
+        "legendre_seeded_step2": legendre,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

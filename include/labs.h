@@ -311,6 +311,37 @@ labs_status labs_refine_step2(const labs_step2_cfg* cfg, int64_t n_cand, const u
                               const labs_step2_out* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------
+ * Legendre-construction seeds of the second step (Sec. 4.1).  A pair (n, o) of
+ * an odd prime n and a rotation 0 <= o < n gives the length-L sequence
+ *   s_j = chi((j + o) mod n),  j = 0..L-1,
+ * chi(a) = +1 for the non-zero quadratic residues mod n and -1 otherwise,
+ * chi(0) = -1: a Legendre sequence rotated by o with its first L - n elements
+ * appended (periodic extension).  The sweep (a reading of the section's ranges,
+ * which hold no prime at most lengths) takes every odd prime n <= L with
+ * t_lo <= 10^4 (L - n)/n <= t_hi and every o with r_lo <= 10^4 o/n <= r_hi, in
+ * (n, o) order; sweep = NULL means {0, 900, 1800, 2600}, whose best pair gives
+ * the construction column of the section's table at L = 450, 471, 491, 526.
+ *
+ * labs_legendre_pairs (host only): writes up to `capacity` pairs to the HOST
+ * arrays n_out / o_out and sets *count to the number of pairs in the sweep.
+ * labs_legendre_build: for the n_pairs HOST pairs (validated: n an odd prime <=
+ * 1023, 0 <= o < n), writes the packed sequences [n_pairs*W] and their energies
+ * [n_pairs] to DEVICE arrays; the workspace (labs_legendre_build_workspace
+ * bytes, device) holds the pairs on the device.  2 <= L <= 1023.  The call
+ * synchronises `stream`.  The sequences feed labs_refine_step2 as candidates.
+ */
+typedef struct {
+    int32_t t_lo, t_hi;   /* appended fraction (L - n)/n, in 1/10^4 */
+    int32_t r_lo, r_hi;   /* rotation o/n, in 1/10^4, <= 10^4 */
+} labs_legendre_sweep;
+
+labs_status labs_legendre_pairs(int32_t L, const labs_legendre_sweep* sweep, int32_t* n_out,
+                                int32_t* o_out, int64_t capacity, int64_t* count);
+labs_status labs_legendre_build_workspace(int64_t n_pairs, size_t* bytes);
+labs_status labs_legendre_build(int32_t L, int64_t n_pairs, const int32_t* n, const int32_t* o,
+                                uint32_t* seqs, int32_t* E, void* ws, size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------------------------
  * Launch timing (diagnostics).  While enabled, every launch of a timed kernel
  * is bracketed by HIP events on the stream it runs on, and the entry point
  * that launched it synchronises that stream before returning and adds the

@@ -627,6 +627,27 @@ labs_status labs_timing_read(const char* kernel, double* total_ms, int64_t* laun
     return LABS_OK;
 }
 
+labs_status labs_legendre_pairs(int32_t L, const labs_legendre_sweep* sweep, int32_t* n_out, int32_t* o_out,
+                                int64_t capacity, int64_t* count) {
+    clear_error();
+    const labs_legendre_sweep def{0, 900, 1800, 2600};
+    return legendre_pairs(L, sweep ? *sweep : def, n_out, o_out, capacity, count);
+}
+
+labs_status labs_legendre_build_workspace(int64_t n_pairs, size_t* bytes) {
+    clear_error();
+    if (!bytes) return invalid("bytes must not be NULL");
+    if (n_pairs < 0) return invalid("n_pairs must be >= 0");
+    *bytes = legendre_workspace_bytes(n_pairs);
+    return LABS_OK;
+}
+
+labs_status labs_legendre_build(int32_t L, int64_t n_pairs, const int32_t* n, const int32_t* o,
+                                uint32_t* seqs, int32_t* E, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    return legendre_build(L, n_pairs, n, o, seqs, E, ws, ws_bytes, S(stream));
+}
+
 labs_status labs_pool_topk_workspace(int64_t capacity, int32_t L, size_t* bytes) {
     clear_error();
     if (!bytes) return invalid("bytes must not be NULL");

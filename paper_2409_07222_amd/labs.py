@@ -31,6 +31,11 @@ class BloomCfg(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 2)]
 
 
+class LegendreSweep(ctypes.Structure):
+    _fields_ = [("t_lo", ctypes.c_int32), ("t_hi", ctypes.c_int32),
+                ("r_lo", ctypes.c_int32), ("r_hi", ctypes.c_int32)]
+
+
 class Step1Cfg(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("p", ctypes.c_int32), ("steps", ctypes.c_int32),
                 ("tenure_lo", ctypes.c_int32), ("tenure_hi", ctypes.c_int32),
@@ -129,6 +134,14 @@ def lib():
             L.labs_walk_step1_bloom.restype = i32
             L.labs_walk_step1_bloom.argtypes = [ctypes.POINTER(Step1Cfg), ctypes.POINTER(BloomCfg),
                                                 ctypes.POINTER(Pool), ctypes.POINTER(Step1Out), vp, sz, vp]
+            L.labs_legendre_pairs.restype = i32
+            L.labs_legendre_pairs.argtypes = [i32, ctypes.POINTER(LegendreSweep), ctypes.POINTER(i32),
+                                              ctypes.POINTER(i32), i64, ctypes.POINTER(i64)]
+            L.labs_legendre_build_workspace.restype = i32
+            L.labs_legendre_build_workspace.argtypes = [i64, ctypes.POINTER(sz)]
+            L.labs_legendre_build.restype = i32
+            L.labs_legendre_build.argtypes = [i32, i64, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp,
+                                              vp, sz, vp]
             L.labs_pool_topk_workspace.restype = i32
             L.labs_pool_topk_workspace.argtypes = [i64, i32, ctypes.POINTER(sz)]
             L.labs_pool_topk.restype = i32
@@ -368,6 +381,39 @@ def walk_step1(L: int, p: int, steps: int, tenure_lo: int, tenure_hi: int, seed:
                                      ctypes.byref(out), _ptr(workspace), workspace.numel(),
                                      _stream(torch.device(device))))
     return r
+
+
+# ---------------------------------------------------------------- Legendre seeds
+def legendre_pairs(L: int, t_lo: int = 0, t_hi: int = 900, r_lo: int = 1800, r_hi: int = 2600):
+    """labs_legendre_pairs: the sweep's (n, o) pairs as two int32 numpy arrays."""
+    import numpy as np
+    sw = LegendreSweep(t_lo, t_hi, r_lo, r_hi)
+    cnt = ctypes.c_int64(0)
+    _check(lib().labs_legendre_pairs(L, ctypes.byref(sw), None, None, 0, ctypes.byref(cnt)))
+    n = np.zeros(max(cnt.value, 1), dtype=np.int32)
+    o = np.zeros(max(cnt.value, 1), dtype=np.int32)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    _check(lib().labs_legendre_pairs(L, ctypes.byref(sw), n.ctypes.data_as(i32p), o.ctypes.data_as(i32p),
+                                     cnt.value, ctypes.byref(cnt)))
+    return n[:cnt.value], o[:cnt.value]
+
+
+def legendre_build(L: int, n, o, device="cuda"):
+    """labs_legendre_build: packed sequences (int32 [m, W]) and energies of the pairs."""
+    import numpy as np
+    torch = _torch()
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    o = np.ascontiguousarray(o, dtype=np.int32)
+    m = len(n)
+    sz = ctypes.c_size_t(0)
+    _check(lib().labs_legendre_build_workspace(m, ctypes.byref(sz)))
+    ws = torch.empty(max(int(sz.value), 1), dtype=torch.uint8, device=device)
+    seqs = torch.empty((m, words(L)), dtype=torch.int32, device=device)
+    E = torch.empty(m, dtype=torch.int32, device=device)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    _check(lib().labs_legendre_build(L, m, n.ctypes.data_as(i32p), o.ctypes.data_as(i32p), _ptr(seqs),
+                                     _ptr(E), _ptr(ws), ws.numel(), _stream(torch.device(device))))
+    return seqs, E
 
 
 # ---------------------------------------------------------------- second step

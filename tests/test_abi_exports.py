@@ -158,3 +158,19 @@ def test_bloom_walk_validation_without_a_gpu():
     sz = C.c_size_t(0)
     assert lib.labs_walk_step1_bloom_workspace(C.byref(cfg), None, 0, C.byref(sz)) != 0
     assert b"bloom" in lib.labs_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_legendre_pairs_host_call():
+    """labs_legendre_pairs is host-only and enumerates the oracle's sweep."""
+    import oracle
+    from paper_2409_07222_amd import labs
+    for L, kw in ((450, {}), (526, {}), (53, dict(t_lo=0, t_hi=10000, r_lo=0, r_hi=10000)),
+                  (5, dict(t_lo=0, t_hi=10000, r_lo=0, r_hi=10000)), (2, {})):
+        n, o = labs.legendre_pairs(L, **kw)
+        assert list(zip(n.tolist(), o.tolist())) == oracle.legendre_pairs(L, **kw)
+    for bad in (dict(t_lo=5, t_hi=4), dict(r_hi=10001), dict(r_lo=-1)):
+        with pytest.raises(labs.LabsError):
+            labs.legendre_pairs(101, **bad)
+    with pytest.raises(labs.LabsError):
+        labs.legendre_pairs(1024)
