@@ -435,6 +435,22 @@ def legendre_sweep(L: int, **kw):
     return out
 
 
+# ---------------------------------------------------------------- length operators
+def length_operators(s):
+    """Sec. 3 (the sequence operators that extend the search to even lengths):
+    from a sequence of length L, the two sequences of length L-1 that remove its
+    first or its last element, and the four of length L+1 that put +1 or -1
+    before its first or after its last element.  Returns (minus, plus) as int8
+    arrays [2, L-1] (remove first, remove last) and [4, L+1] (+1 first, -1 first,
+    +1 last, -1 last)."""
+    a = _seq(s)
+    minus = np.stack([a[1:], a[:-1]])
+    one = np.ones(1, np.int8)
+    plus = np.stack([np.concatenate([one, a]), np.concatenate([-one, a]),
+                     np.concatenate([a, one]), np.concatenate([a, -one])])
+    return minus, plus
+
+
 # ---------------------------------------------------------------- second step
 # Second-step tie order (a reading; the paper is silent on ties): (E, z, key)
 # where z is the sequence's Zobrist key -- the XOR, over the positions i with

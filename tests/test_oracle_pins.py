@@ -123,6 +123,27 @@ def test_legendre_sweep_best_is_the_printed_construction(orc):
     assert all(orc._is_prime(n) for n, _ in prs)
 
 
+def test_length_operators(orc):
+    """The end operators: removing after appending gives the sequence back; the
+    first-element operators are the last-element ones under reversal (which keeps
+    E); a removal changes C_k by exactly the dropped products (numpy correlate)."""
+    for L in (2, 3, 8, 37, 500, 501):
+        for s in li.random_pm1(40 + L, 3, L):
+            minus, plus = orc.length_operators(s)
+            assert minus.shape == (2, L - 1) and plus.shape == (4, L + 1)
+            for q in range(4):
+                m2, _ = orc.length_operators(plus[q])
+                assert np.array_equal(m2[0 if q < 2 else 1], s)
+                assert plus[q][0 if q < 2 else L] == (1 if q % 2 == 0 else -1)
+            rm, rp = orc.length_operators(s[::-1])
+            assert np.array_equal(minus[0], rm[1][::-1]) and np.array_equal(plus[0], rp[2][::-1])
+            assert orc.energy(minus[0]) == orc.energy(rm[1])
+            c_full = np_autocorr(s)
+            c_last = np_autocorr(minus[1])
+            for k in range(1, L - 1):
+                assert c_last[k - 1] == c_full[k - 1] - int(s[L - 1 - k]) * int(s[L - 1])
+
+
 def test_merit_factor_printed_values(orc):
     """Eq. (1) with the F values printed in Sec. 4: exactly one integer energy
     rounds to each printed F."""
