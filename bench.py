@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the uneven-length batched launch measurement")
     ap.add_argument("--batched-steps", type=int, default=20000)
+    ap.add_argument("--no-even", action="store_true",
+                    help="skip carrying the result to L - 1 and L + 1 with the end operators")
+    ap.add_argument("--even-expansions", type=int, default=2_000_000)
     ap.add_argument("--no-legendre", action="store_true",
                     help="skip the Legendre-seeded second step at L = 450, 471, 491, 526")
     ap.add_argument("--legendre-expansions", type=int, default=10_000_000)
@@ -278,6 +281,30 @@ def legendre_step2(a, labs, dev):
             "rounds_to_best": r["best_round"] + 1}
         log("legendre L=%d: construction F %.4f -> second step F %.4f (paper %.4f -> %.4f)"
             % (Lq, Lq * Lq / (2.0 * e0), Lq * Lq / (2.0 * r["best_E"]), f_con, f_dfs))
+    return out
+
+
+def even_lengths(a, labs, dev, top_seqs, best_seq):
+    """The end operators carry the dual-step result to the even lengths L - 1 and
+    L + 1 (Sec. 3): the second step's best and the first step's top-k, each with
+    its first or last element removed (L - 1) or with +1 / -1 put at either end
+    (L + 1), seed the second step at that length (batch 1024, queue 2^20,
+    --even-expansions pops)."""
+    import torch
+    seqs = torch.cat([best_seq.view(1, -1), top_seqs]).contiguous()
+    minus, Em, plus, Ep = labs.length_operators(L, seqs)
+    out = {"inputs": int(seqs.shape[0]), "expansions": a.even_expansions}
+    for Lq, cand, Ec in ((L - 1, minus, Em), (L + 1, plus, Ep)):
+        e0 = int(Ec.min().item())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = labs.refine_step2(Lq, cand.contiguous(), 1024, 1 << 20, a.even_expansions, 1 << 62)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[str(Lq)] = {"candidates": int(cand.shape[0]), "candidate_F": Lq * Lq / (2.0 * e0),
+                        "second_step_F": Lq * Lq / (2.0 * r["best_E"]), "second_step_s": dt}
+        log("even lengths: L=%d candidates F %.4f -> second step F %.4f"
+            % (Lq, Lq * Lq / (2.0 * e0), Lq * Lq / (2.0 * r["best_E"])))
     return out
 
 
@@ -503,6 +530,8 @@ def main():
 
     s2_ws = None
 
+    top = {}
+
     def one(seed):
         nonlocal cfg_ws, s2_ws
         pool.count.zero_()
@@ -510,6 +539,7 @@ def main():
         r = labs.walk_step1(L, P, a.walk_steps, lo, hi, seed, a.walkers, e_max=e_max, pool=pool,
                             pool_walker_best=True, device=dev, workspace=cfg_ws)
         s, E = labs.pool_topk(pool, topk)
+        top["seqs"] = s
         if a.s2_expansions > 0:
             if s2_ws is None:
                 cfg2 = labs.Step2Cfg(L, a.s2_batch, 0, 0, a.s2_capacity, a.s2_expansions, 1 << 62)
@@ -521,6 +551,7 @@ def main():
                                    1 << 62, workspace=s2_ws)
         else:
             r2 = {"expansions": 0, "best_E": int(E[0].item())}
+        top["best"] = r2.get("best_seq")
         return r, E, r2
 
     # workspace reuse across steps
@@ -584,6 +615,9 @@ def main():
     configs = None if a.no_configs else step1_configs(a, labs, dev)
     bloom = None if a.no_bloom else bloom_measure(a, labs, dev)
     legendre = None if a.no_legendre else legendre_step2(a, labs, dev)
+    even = None
+    if not a.no_even and top.get("best") is not None:
+        even = even_lengths(a, labs, dev, top["seqs"], top["best"])
     ab = None
     if not a.no_ab:
         s2_ws = None
@@ -616,6 +650,7 @@ def main():
         "step1_configs": configs,
         "bloom_walk": bloom,
         "legendre_seeded_step2": legendre,
+        "even_lengths": even,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -342,6 +342,20 @@ labs_status labs_legendre_build(int32_t L, int64_t n_pairs, const int32_t* n, co
                                 uint32_t* seqs, int32_t* E, void* ws, size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------
+ * End operators (Sec. 3: the operators that extend the search to even lengths
+ * by removing or appending elements at either end of a sequence).  For each of
+ * the n packed sequences of length L (device), writes
+ *   minus[(2j + q)*W(L-1)]: q = 0 without its first element, q = 1 without its last;
+ *   plus [(4j + q)*W(L+1)]: q = 0 +1 before the first element, q = 1 -1 before it,
+ *                           q = 2 +1 after the last element,   q = 3 -1 after it;
+ * and their energies E_minus[2n], E_plus[4n] (all device).  1 <= L <= 1022; for
+ * L = 1 minus and E_minus are not written (may be NULL).  Asynchronous on `stream`.
+ * The results feed labs_refine_step2 at L - 1 and L + 1.
+ */
+labs_status labs_length_operators(int32_t L, int64_t n, const uint32_t* seqs, uint32_t* minus,
+                                  int32_t* E_minus, uint32_t* plus, int32_t* E_plus, void* stream);
+
+/* ----------------------------------------------------------------------------
  * Launch timing (diagnostics).  While enabled, every launch of a timed kernel
  * is bracketed by HIP events on the stream it runs on, and the entry point
  * that launched it synchronises that stream before returning and adds the

@@ -648,6 +648,12 @@ labs_status labs_legendre_build(int32_t L, int64_t n_pairs, const int32_t* n, co
     return legendre_build(L, n_pairs, n, o, seqs, E, ws, ws_bytes, S(stream));
 }
 
+labs_status labs_length_operators(int32_t L, int64_t n, const uint32_t* seqs, uint32_t* minus, int32_t* E_minus,
+                                  uint32_t* plus, int32_t* E_plus, void* stream) {
+    clear_error();
+    return length_operators(L, n, seqs, minus, E_minus, plus, E_plus, S(stream));
+}
+
 labs_status labs_pool_topk_workspace(int64_t capacity, int32_t L, size_t* bytes) {
     clear_error();
     if (!bytes) return invalid("bytes must not be NULL");

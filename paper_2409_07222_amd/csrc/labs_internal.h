@@ -146,6 +146,8 @@ labs_status launch_bloom_init(const WalkArgs& A, hipStream_t st);
 labs_status legendre_pairs(int32_t L, const labs_legendre_sweep& sw, int32_t* n_out, int32_t* o_out,
                            int64_t capacity, int64_t* count);
 size_t legendre_workspace_bytes(int64_t n_pairs);
+labs_status length_operators(int32_t L, int64_t n, const uint32_t* seqs, uint32_t* minus, int32_t* E_minus,
+                             uint32_t* plus, int32_t* E_plus, hipStream_t st);
 labs_status legendre_build(int32_t L, int64_t n_pairs, const int32_t* n_host, const int32_t* o_host,
                            uint32_t* seqs, int32_t* E, void* ws, size_t ws_bytes, hipStream_t st);
 labs_status launch_walker_init_items(const WalkArgs* args, const int2* items, int n_items, hipStream_t st);

@@ -142,6 +142,8 @@ def lib():
             L.labs_legendre_build.restype = i32
             L.labs_legendre_build.argtypes = [i32, i64, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp,
                                               vp, sz, vp]
+            L.labs_length_operators.restype = i32
+            L.labs_length_operators.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp]
             L.labs_pool_topk_workspace.restype = i32
             L.labs_pool_topk_workspace.argtypes = [i64, i32, ctypes.POINTER(sz)]
             L.labs_pool_topk.restype = i32
@@ -414,6 +416,23 @@ def legendre_build(L: int, n, o, device="cuda"):
     _check(lib().labs_legendre_build(L, m, n.ctypes.data_as(i32p), o.ctypes.data_as(i32p), _ptr(seqs),
                                      _ptr(E), _ptr(ws), ws.numel(), _stream(torch.device(device))))
     return seqs, E
+
+
+# ---------------------------------------------------------------- end operators
+def length_operators(L: int, seqs):
+    """labs_length_operators: (minus [2n, W(L-1)], E_minus [2n], plus [4n, W(L+1)],
+    E_plus [4n]) for packed sequences of length L (int32 [n, W] device tensor)."""
+    torch = _torch()
+    s = _dev(seqs, torch.int32, "seqs")
+    n = s.shape[0]
+    dev = s.device
+    minus = torch.empty((2 * n, words(max(L - 1, 1))), dtype=torch.int32, device=dev)
+    Em = torch.empty(2 * n, dtype=torch.int32, device=dev)
+    plus = torch.empty((4 * n, words(L + 1)), dtype=torch.int32, device=dev)
+    Ep = torch.empty(4 * n, dtype=torch.int32, device=dev)
+    _check(lib().labs_length_operators(L, n, _ptr(s), _ptr(minus) if L >= 2 else None,
+                                       _ptr(Em) if L >= 2 else None, _ptr(plus), _ptr(Ep), _stream(dev)))
+    return minus, Em, plus, Ep
 
 
 # ---------------------------------------------------------------- second step
