@@ -484,11 +484,15 @@ def step2(L: int, candidates, batch: int, pq_capacity: int, max_expansions: int,
     best sequence improves only on a strictly lower energy; u counts pops since
     the last improvement (reset to 0 by an improving round, else += pops), which
     for batch = 1 is exactly the dynamic-depth counter of Algorithm 2.  Open is
-    then cut to the pq_capacity smallest.  Rotations (T_r > 0) are not part of
-    this reading.
+    then cut to the pq_capacity smallest.
+
+    MAKE_ROTATIONS (T_r > 0; Sec. 3, rotations of the pivot): after the single
+    flips of every pivot of the round, each pivot in pop order also produces its
+    cyclic rotations left by 1..T_r (the first element moved to the end, repeatedly)
+    and then right by 1..T_r, each skipped or pushed like a neighbour.
     """
-    if T_r != 0:
-        raise NotImplementedError("rotations are not part of the second-step reading")
+    if T_r < 0 or (T_r and 2 * T_r >= L):
+        raise ValueError("T_r must satisfy 0 <= 2 T_r < L")
     lb = lib()
     zt = zobrist_table(L)
 
@@ -531,6 +535,15 @@ def step2(L: int, candidates, batch: int, pq_capacity: int, max_expansions: int,
                     continue
                 t = s.copy()
                 t[i] = -t[i]
+                new[nk] = int(lb.or_energy(L, _p(t, _i8p), None))
+        for E, _, k in P if T_r else ():
+            s = key_seq(k, L)
+            for shift in list(range(1, T_r + 1)) + [-r for r in range(1, T_r + 1)]:
+                t = np.ascontiguousarray(np.roll(s, -shift))   # left by shift (right if negative)
+                nk = seq_key(t)
+                if nk in closed or nk in open_ or nk in new:
+                    dups += 1
+                    continue
                 new[nk] = int(lb.or_energy(L, _p(t, _i8p), None))
         pushes += len(new)
         if new:

@@ -413,6 +413,52 @@ def test_step2_pop_order_single(orc):
     assert r1["pushes"] == L
 
 
+def _moved(s, r):
+    """The text's rotation: r times, move the first element to the end (r > 0),
+    or the last element to the start (r < 0)."""
+    t = list(s)
+    for _ in range(abs(r)):
+        t = t[1:] + t[:1] if r > 0 else t[-1:] + t[:-1]
+    return np.array(t, dtype=np.int8)
+
+
+def test_step2_rotations_first_round(orc):
+    """B = 1, one pop: Open is the pivot's single flips and its rotations left and
+    right by 1..T_r, each once, with energies from numpy; a pivot of period 3
+    meets itself at shift 3, which is skipped."""
+    for L, T_r, c in ((11, 2, li.random_pm1(4, 1, 11)[0]),
+                      (9, 4, np.array([1, 1, -1] * 3, np.int8))):
+        r = orc.step2(L, [c], 1, 1 << 20, 1, 1 << 40, T_r=T_r)
+        want = {}
+        for i in range(L):
+            t = c.copy()
+            t[i] *= -1
+            want[orc.seq_key(t)] = np_energy(t)
+        for q in list(range(1, T_r + 1)) + [-q for q in range(1, T_r + 1)]:
+            t = _moved(c, q)
+            if orc.seq_key(t) != orc.seq_key(c):
+                want.setdefault(orc.seq_key(t), np_energy(t))
+        assert r["open_keys"] == sorted((E, k) for k, E in want.items())
+        assert r["pushes"] == len(want)
+        assert r["pushes"] + r["dup_skips"] == L + 2 * T_r
+
+
+def test_step2_rotations_full_space(orc):
+    """With rotations the search still visits every sequence once and ends at the
+    exhaustive optimum; the accounting counts L + 2 T_r products per pop."""
+    table = {int(a): int(b) for a, b in _rows("labs_optimal_energies.txt")}
+    for L, T_r in ((7, 1), (9, 3), (10, 2)):
+        c = li.random_pm1(L + 50, 2, L)
+        for B in (1, 4):
+            r = orc.step2(L, list(c), B, 1 << 20, 1 << 20, 1 << 40, T_r=T_r)
+            assert r["best_E"] == table[L]
+            assert r["expansions"] == 2 ** L
+            assert r["pushes"] == 2 ** L - len({tuple(x) for x in c})
+            assert r["pushes"] + r["dup_skips"] == r["expansions"] * (L + 2 * T_r)
+    with pytest.raises(ValueError):
+        orc.step2(9, list(li.random_pm1(1, 1, 9)), 1, 10, 10, 10, T_r=5)
+
+
 def test_step2_dynamic_depth(orc):
     """T_u bounds the pops since the last strict improvement."""
     L = 13
