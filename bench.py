@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the uneven-length batched launch measurement")
     ap.add_argument("--batched-steps", type=int, default=20000)
+    ap.add_argument("--no-rotations", action="store_true",
+                    help="skip the second step with rotations (T_r = 1, 4, 16)")
+    ap.add_argument("--rot-expansions", type=int, default=2_000_000)
     ap.add_argument("--no-even", action="store_true",
                     help="skip carrying the result to L - 1 and L + 1 with the end operators")
     ap.add_argument("--even-expansions", type=int, default=2_000_000)
@@ -305,6 +308,25 @@ def even_lengths(a, labs, dev, top_seqs, best_seq):
                         "second_step_F": Lq * Lq / (2.0 * r["best_E"]), "second_step_s": dt}
         log("even lengths: L=%d candidates F %.4f -> second step F %.4f"
             % (Lq, Lq * Lq / (2.0 * e0), Lq * Lq / (2.0 * r["best_E"])))
+    return out
+
+
+def rotations_measure(a, labs, dev, top_seqs):
+    """MAKE_ROTATIONS in the second step at L = 501: from the first step's top-k,
+    the second step without rotations and with T_r = 1, 4, 16 (batch 1024, queue
+    2^20, --rot-expansions pops): time per round and best F."""
+    import torch
+    out = {"expansions": a.rot_expansions, "runs": {}}
+    for T_r in (0, 1, 4, 16):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = labs.refine_step2(L, top_seqs.contiguous(), 1024, 1 << 20, a.rot_expansions, 1 << 62, T_r=T_r)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["runs"][str(T_r)] = {"seconds": dt, "rounds": r["rounds"], "us_per_round": dt / max(1, r["rounds"]) * 1e6,
+                                 "pushes": r["pushes"], "best_F": L * L / (2.0 * r["best_E"])}
+        log("rotations T_r=%d: %.1f us per round, best F %.4f" % (T_r, dt / max(1, r["rounds"]) * 1e6,
+                                                                 L * L / (2.0 * r["best_E"])))
     return out
 
 
@@ -618,6 +640,7 @@ def main():
     even = None
     if not a.no_even and top.get("best") is not None:
         even = even_lengths(a, labs, dev, top["seqs"], top["best"])
+    rot = None if a.no_rotations else rotations_measure(a, labs, dev, top["seqs"])
     ab = None
     if not a.no_ab:
         s2_ws = None
@@ -651,6 +674,7 @@ def main():
         "bloom_walk": bloom,
         "legendre_seeded_step2": legendre,
         "even_lengths": even,
+        "step2_rotations": rot,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -263,6 +263,10 @@ labs_status labs_pool_topk(const labs_pool* pool, int32_t L, int32_t k, uint32_t
  *     neighbour already in Closed, in Open or produced earlier in this round is
  *     skipped (Alg. 2's PQ.contains test, by exact sequence); the others are
  *     pushed with their exact energy;
+ *   - with T_r > 0 (MAKE_ROTATIONS, rotations of the pivot), after every single
+ *     flip of the round each pivot also produces its cyclic rotations left by
+ *     1..T_r (the first element moved to the end, repeatedly), then right by
+ *     1..T_r, skipped or pushed by the same rule;
  *   - if the round's smallest pushed energy is below best's, best becomes the
  *     smallest pushed entry and u = 0; otherwise u grows by the
  *     number of pivots (u counts pops since the last strict improvement; with
@@ -271,14 +275,14 @@ labs_status labs_pool_topk(const labs_pool* pool, int32_t L, int32_t k, uint32_t
  *     and may be pushed again later).
  * Results do not depend on scheduling.  The call synchronises `stream`.
  * Memory: the workspace holds two hash tables of next_pow2(4 x (n_cand +
- * max_expansions + pq_capacity + 9 batch L)) slots of 16 + 4W bytes (10.7 GB at
- * 10^7 expansions of L = 501); configurations whose table would pass 2^31 slots
- * are rejected (LABS_E_INVALID).
+ * max_expansions + pq_capacity + 9 batch (L + 2 T_r))) slots of 16 + 4W bytes
+ * (10.7 GB at 10^7 expansions of L = 501); configurations whose table would pass
+ * 2^31 slots are rejected (LABS_E_INVALID).
  */
 typedef struct {
     int32_t L;               /* 2..1023 */
     int32_t batch;           /* pivots per round, >= 1 */
-    int32_t T_r;             /* rotations; must be 0 in this build */
+    int32_t T_r;             /* rotations per side, 0..32 with 2 T_r < L (0: none) */
     int32_t reserved;        /* must be 0 */
     int64_t pq_capacity;     /* Q >= 1 */
     int64_t max_expansions;  /* >= 0 */

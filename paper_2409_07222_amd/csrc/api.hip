@@ -518,7 +518,8 @@ labs_status labs_walk_step1_bloom(const labs_step1_cfg* cfg, const labs_bloom* b
 static labs_status check_step2_cfg(const labs_step2_cfg& c, int64_t n_cand) {
     if (c.L < 2 || c.L > 1023) return invalid("second-step L must be in [2, 1023], got %d", c.L);
     if (c.batch < 1 || c.batch > (1 << 20)) return invalid("batch must be in [1, 2^20]");
-    if (c.T_r != 0) return invalid("rotations (T_r > 0) are not part of this build");
+    if (c.T_r < 0 || c.T_r > 32 || (c.T_r > 0 && 2 * c.T_r >= c.L))
+        return invalid("T_r must be in [0, 32] with 2 T_r < L, got %d", c.T_r);
     if (c.reserved != 0) return invalid("reserved must be 0");
     if (c.pq_capacity < 1 || c.pq_capacity > (int64_t)1 << 28) return invalid("pq_capacity must be in [1, 2^28]");
     if (c.max_expansions < 0 || c.max_expansions > (int64_t)1 << 30)

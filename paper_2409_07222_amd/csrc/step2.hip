@@ -136,6 +136,12 @@ struct Params {
     int32_t* bmax;         // [B] their greatest energy
     // [B*L] 1 when neighbour (b, i) repeats a neighbour of a lower-numbered pivot
     uint8_t* repeat;
+    // MAKE_ROTATIONS: rotation q of pivot b sits at Open position batch_begin +
+    // n_piv*L + b*R2 + q (after every single flip of the round); q < Tr rotates
+    // left by q+1, else right by q-Tr+1.
+    int32_t Tr, R2;
+    unsigned long long* rkey;   // [B*R2] their Zobrist keys
+    int32_t* rE;                // [B*R2] their energies
 };
 
 __device__ __forceinline__ uint64_t zob(int i) { return zobrist_at(i); }
@@ -217,12 +223,44 @@ __device__ __forceinline__ uint32_t src_word(const Params& P, int src, int flip,
     return x;
 }
 
+// 32 elements of a packed sequence from element a (0-based) on, first element in
+// the top bit (elements past the last word read as 0).
+__device__ __forceinline__ uint32_t read32(const uint32_t* p, int W, int a) {
+    const int q = a >> 5, h = a & 31;
+    const uint32_t hi = p[q];
+    if (!h) return hi;
+    const uint32_t lo = q + 1 < W ? p[q + 1] : 0u;
+    return (hi << h) | (lo >> (32 - h));
+}
+
+// Word w of the left rotation by r (0 < r < L) of a packed sequence: element i
+// is element (i + r) mod L of the original; bits past element L-1 are 0.
+__device__ __forceinline__ uint32_t rot_word(const uint32_t* p, int L, int W, int r, int w) {
+    const int a = (32 * w + r) % L;
+    const int n1 = L - a;   // elements before the wrap
+    uint32_t x = read32(p, W, a);
+    if (n1 < 32) x = (x & (~0u << (32 - n1))) | (read32(p, W, 0) >> n1);
+    if (w == W - 1 && (L & 31)) x &= ~0u << (32 - (L & 31));
+    return x;
+}
+
+// Left shift of rotation q of a pivot.
+__device__ __forceinline__ int rot_shift(const Params& P, int q) { return q < P.Tr ? q + 1 : P.L - (q - P.Tr + 1); }
+
+// Word w of this round's new entry at offset j from batch_begin: a single flip
+// of a pivot, or (past every flip) a rotation of one.
+__device__ __forceinline__ uint32_t new_word(const Params& P, long long j, int w) {
+    const long long nf = P.ctl->n_piv * P.L;
+    if (j < nf) return src_word(P, P.piv[j / P.L], (int)(j % P.L) + 1, w);
+    const long long jr = j - nf;
+    return rot_word(P.H.seq + (size_t)P.piv[jr / P.R2] * P.W, P.L, P.W, rot_shift(P, (int)(jr % P.R2)), w);
+}
+
 // Word w of the sequence of Open entry o (table slot `slot`, or a new entry of
 // this round when slot < 0).
 __device__ __forceinline__ uint32_t entry_word(const Params& P, int slot, long long o, int w) {
     if (slot >= 0) return P.H.seq[(size_t)slot * P.W + w];
-    const long long j = o - P.ctl->batch_begin;
-    return src_word(P, P.piv[j / P.L], (int)(j % P.L) + 1, w);
+    return new_word(P, o - P.ctl->batch_begin, w);
 }
 
 __device__ __forceinline__ bool entries_equal(const Params& P, int sa, long long a, int sb, long long b) {
@@ -1170,6 +1208,184 @@ expand_kernel_t pick_expand(int L, unsigned* threads) {
     return k_expand_direct;
 }
 
+// ---------------------------------------------------------------- rotations
+constexpr int kRotThreads = 256;
+constexpr int kMaxTr = 32;
+
+// Energies and keys of the rotations of each pivot (MAKE_ROTATIONS).  C_k of the
+// pivot is computed once; moving the first element x_1 of a sequence to its end
+// changes C_k by x_1 (x_{L+1-k} - x_{1+k}), moving the last element x_L to its
+// front by x_L (x_k - x_{L-k}), so each rotation costs O(L) after the previous
+// one.  Keys are the Zobrist XOR of the rotated sequence.
+__global__ __launch_bounds__(kRotThreads) void k_rot_build(Params P) {
+    Ctl* c = P.ctl;
+    if (c->stop) return;
+    const long long b = blockIdx.x;
+    if (b >= c->n_piv) return;
+    __shared__ int8_t s[kMaxL];
+    __shared__ int32_t C0[kMaxL], C[kMaxL];
+    __shared__ int32_t red_e[kRotThreads / 64];
+    __shared__ uint32_t red_lo[kRotThreads / 64], red_hi[kRotThreads / 64];
+    const int L = P.L, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint32_t* ps = P.H.seq + (size_t)P.piv[b] * P.W;
+    for (int x = t; x < L; x += kRotThreads) s[x] = ((ps[x >> 5] >> (31 - (x & 31))) & 1u) ? 1 : -1;
+    __syncthreads();
+    for (int k = 1 + t; k < L; k += kRotThreads) {
+        int acc = 0;
+        for (int i = 0; i + k < L; ++i) acc += s[i] * s[i + k];
+        C0[k] = acc;
+    }
+    __syncthreads();
+    for (int dir = 0; dir < 2; ++dir) {
+        for (int k = 1 + t; k < L; k += kRotThreads) C[k] = C0[k];
+        __syncthreads();
+        for (int r = 1; r <= P.Tr; ++r) {
+            // x_i (1-based) of the pivot rotated by r-1 in this direction is
+            // s[(i - 1 + off) mod L]
+            const int off = dir == 0 ? r - 1 : L - (r - 1);
+            for (int k = 1 + t; k < L; k += kRotThreads) {
+                if (dir == 0)
+                    C[k] += s[off % L] * (s[(L + off - k) % L] - s[(k + off) % L]);
+                else
+                    C[k] += s[(L - 1 + off) % L] * (s[(k - 1 + off) % L] - s[(L - k - 1 + off) % L]);
+            }
+            __syncthreads();
+            const int off2 = dir == 0 ? r : L - r;   // the rotation by r
+            int e = 0;
+            for (int k = 1 + t; k < L; k += kRotThreads) e += C[k] * C[k];
+            unsigned long long h = 0;
+            for (int i = t; i < L; i += kRotThreads)
+                if (s[(i + off2) % L] > 0) h ^= zob(i);
+            e = __ockl_wfred_add_i32(e);
+            uint32_t lo = (uint32_t)h, hi = (uint32_t)(h >> 32);
+            for (int o = 32; o > 0; o >>= 1) {
+                lo ^= (uint32_t)__shfl_xor((int)lo, o, 64);
+                hi ^= (uint32_t)__shfl_xor((int)hi, o, 64);
+            }
+            if (lane == 0) {
+                red_e[wv] = e;
+                red_lo[wv] = lo;
+                red_hi[wv] = hi;
+            }
+            __syncthreads();
+            if (t == 0) {
+                int E = 0;
+                uint32_t l2 = 0, h2 = 0;
+                for (int q = 0; q < kRotThreads / 64; ++q) {
+                    E += red_e[q];
+                    l2 ^= red_lo[q];
+                    h2 ^= red_hi[q];
+                }
+                const long long idx = b * P.R2 + dir * P.Tr + (r - 1);
+                P.rkey[idx] = (((unsigned long long)h2 << 32) | l2) | 1ull;
+                P.rE[idx] = E;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// The rotations of pivot b take their fixed Open positions.  One is DEAD when it
+// equals an earlier rotation of the round (in (pivot, q) order), when it lies
+// within one flip of a pivot of the round (it is then that pivot, CLOSED, or one
+// of the round's single-flip neighbours, which come first), or when H holds it
+// as OPEN or CLOSED; otherwise it is a new entry.  H is only read.
+__global__ __launch_bounds__(kRotThreads) void k_rot_stage(Params P) {
+    Ctl* c = P.ctl;
+    if (c->stop) return;
+    const long long b = blockIdx.x;
+    const long long np = c->n_piv;
+    if (b >= np) return;
+    __shared__ uint32_t rw[2 * kMaxTr][32];
+    __shared__ unsigned long long rk[2 * kMaxTr];
+    __shared__ int dupq[2 * kMaxTr];
+    __shared__ int s_cnt, s_min, s_max;
+    const int t = threadIdx.x, L = P.L, W = P.W, R2 = P.R2;
+    const uint32_t last_mask = (L & 31) ? ~0u << (32 - (L & 31)) : ~0u;
+    const uint32_t* ps = P.H.seq + (size_t)P.piv[b] * W;
+    for (int x = t; x < R2 * W; x += kRotThreads) rw[x / W][x % W] = rot_word(ps, L, W, rot_shift(P, x / W), x % W);
+    if (t < R2) {
+        rk[t] = P.rkey[b * R2 + t];
+        dupq[t] = 0;
+    }
+    if (t == 0) {
+        s_cnt = 0;
+        s_min = INT32_MAX;
+        s_max = 0;
+    }
+    __syncthreads();
+    // earlier rotations with an equal key: compare the sequences
+    for (long long u = t; u < (b + 1) * R2; u += kRotThreads) {
+        const unsigned long long ku = P.rkey[u];
+        for (int q = 0; q < R2; ++q) {
+            if (u >= b * R2 + q || ku != rk[q]) continue;
+            const uint32_t* pu = P.H.seq + (size_t)P.piv[u / R2] * W;
+            const int su = rot_shift(P, (int)(u % R2));
+            bool eq = true;
+            for (int w = 0; w < W && eq; ++w) eq = rot_word(pu, L, W, su, w) == rw[q][w];
+            if (eq) dupq[q] = 1;
+        }
+    }
+    // within one flip of a pivot of the round
+    for (long long v = t; v < np; v += kRotThreads) {
+        const uint32_t* pv = P.H.seq + (size_t)P.piv[v] * W;
+        for (int q = 0; q < R2; ++q) {
+            int d = 0;
+            for (int w = 0; w < W && d <= 1; ++w) {
+                uint32_t x = rw[q][w] ^ pv[w];
+                if (w == W - 1) x &= last_mask;
+                d += __popc(x);
+            }
+            if (d <= 1) dupq[q] = 1;
+        }
+    }
+    __syncthreads();
+    if (t < R2) {
+        const int q = t;
+        const long long idx = b * R2 + q;
+        const unsigned long long key = rk[q];
+        bool take = !dupq[q];
+        int tomb = -1;
+        if (take) {
+            const Table& H = P.H;
+            const uint8_t tg = tag_of(key);
+            uint64_t sl = key & H.mask;
+            for (uint64_t probe = 0; probe <= H.mask; ++probe, sl = (sl + 1) & H.mask) {
+                const uint8_t ts = H.tag[sl];
+                if (ts == 0) break;
+                if (ts != tg || H.hkey[sl] != key) continue;
+                bool eq = true;
+                for (int w = 0; w < W && eq; ++w) eq = H.seq[sl * W + w] == rw[q][w];
+                if (!eq) continue;
+                if (H.state[sl] == ST_EVICTED) tomb = (int)sl;
+                else take = false;
+                break;
+            }
+        }
+        const int cur = c->which;
+        const long long j = np * L + idx;
+        const long long o = c->batch_begin + j;
+        if (!take) {
+            P.oE[cur][o] = DEAD;
+        } else {
+            const int32_t En = P.rE[idx];
+            P.oE[cur][o] = En;
+            P.oS[cur][o] = -1;
+            P.oZ[cur][o] = key;
+            P.ntomb[j] = tomb;
+            atomicAdd(&s_cnt, 1);
+            atomicMin(&s_min, En);
+            atomicMax(&s_max, En);
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        P.bcnt[b] += s_cnt;
+        if (s_min < P.bmin[b]) P.bmin[b] = s_min;
+        if (s_max > P.bmax[b]) P.bmax[b] = s_max;
+    }
+}
+
 __device__ void best_scan(const Params& P, int initial);
 
 // After the expansion: the pushed count and least and greatest energy over the
@@ -1207,13 +1423,13 @@ __global__ __launch_bounds__(1024) void k_round_mid(Params P) {
             mn = s_min[k] < mn ? s_min[k] : mn;
             mx = s_max[k] > mx ? s_max[k] : mx;
         }
-        c->n_tot = c->batch_begin + c->n_piv * P.L;
+        c->n_tot = c->batch_begin + c->n_piv * (P.L + P.R2);
         c->batch_minE = mn;
         c->expansions += c->n_piv;
         c->n_live -= c->n_piv;
         const long long n_new = cnt;
         c->pushes += n_new;
-        c->dups += c->n_piv * P.L - n_new;
+        c->dups += c->n_piv * (P.L + P.R2) - n_new;
         c->n_live += n_new;
         if (c->batch_minE < c->best_E) c->improved = 1;
         else c->u += c->n_piv;
@@ -1334,9 +1550,8 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
                             atomicExch(&c->error, 2);
                             keep[k] = false;
                         } else {
-                            const int ps = P.piv[j / P.L], fl = (int)(j % P.L) + 1;
                             for (int w = 0; w < H.W; ++w)
-                                H.seq[(size_t)slot[k] * H.W + w] = src_word(P, ps, fl, w);
+                                H.seq[(size_t)slot[k] * H.W + w] = new_word(P, j, w);
                             H.E[slot[k]] = P.oE[cur][i];
                             H.state[slot[k]] = ST_OPEN;
                             ++claims;
@@ -1532,7 +1747,7 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     S2Layout lo;
     const int W = words_of(c.L);
     const long long base = (n_cand > c.pq_capacity ? n_cand : c.pq_capacity);
-    const long long BL = (long long)c.batch * c.L;
+    const long long BL = (long long)c.batch * (c.L + 2 * c.T_r);   // products of one round
     lo.cap_o = base + BL + 1024;
     lo.cap_pend = (BL > n_cand ? BL : n_cand) + 1024;
     // live slots never exceed n_cand + X + Q + BL; the table is rebuilt when half
@@ -1553,6 +1768,8 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     t += align_up(sizeof(int32_t) * lo.cap_new, 256);                  // ntomb
     t += 3 * align_up(sizeof(int32_t) * c.batch, 256);                 // bcnt, bmin, bmax
     t += align_up(lo.cap_new + 4, 256);                                // repeat
+    t += align_up(sizeof(unsigned long long) * (2 * c.T_r * c.batch + 1), 256);   // rotation keys
+    t += align_up(sizeof(int32_t) * (2 * c.T_r * c.batch + 1), 256);              // rotation energies
     t += align_up(sizeof(Ctl), 256);
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // oE
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // oS
@@ -1614,6 +1831,10 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.bmin = cv.take<int32_t>(cfg.batch);
     P.bmax = cv.take<int32_t>(cfg.batch);
     P.repeat = cv.take<uint8_t>(lo.cap_new + 4);
+    P.Tr = cfg.T_r;
+    P.R2 = 2 * cfg.T_r;
+    P.rkey = cv.take<unsigned long long>((size_t)P.R2 * cfg.batch + 1);
+    P.rE = cv.take<int32_t>((size_t)P.R2 * cfg.batch + 1);
     int tcur = 0;
     P.H = tabs[0];
     P.ctl = cv.take<Ctl>(1);
@@ -1681,6 +1902,10 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
         if (tb && (s = tb(tctx, st)) != LABS_OK) return s;
         hipLaunchKernelGGL(ek, dim3((unsigned)cfg.batch), dim3(eth), 0, st, P);
         if (te && (s = te(tctx, st)) != LABS_OK) return s;
+        if (P.Tr) {
+            hipLaunchKernelGGL(k_rot_build, dim3((unsigned)cfg.batch), dim3(kRotThreads), 0, st, P);
+            hipLaunchKernelGGL(k_rot_stage, dim3((unsigned)cfg.batch), dim3(kRotThreads), 0, st, P);
+        }
         hipLaunchKernelGGL(k_round_mid, dim3(1), dim3(1024), 0, st, P);
         select(false);
         hipLaunchKernelGGL(k_keep, gS, tS, 0, st, P);

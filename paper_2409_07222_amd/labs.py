@@ -437,14 +437,14 @@ def length_operators(L: int, seqs):
 
 # ---------------------------------------------------------------- second step
 def refine_step2(L: int, cands, batch: int, pq_capacity: int, max_expansions: int, T_u: int,
-                 open_capacity: int = 0, workspace=None):
+                 open_capacity: int = 0, workspace=None, T_r: int = 0):
     """labs_refine_step2 over packed candidates (int32 [n, W] device tensor).
     Returns a dict with best_seq, best_E, the stats and (optionally) Open."""
     torch = _torch()
     c = _dev(cands, torch.int32, "cands")
     n = c.shape[0]
     dev = c.device
-    cfg = Step2Cfg(L, batch, 0, 0, pq_capacity, max_expansions, T_u)
+    cfg = Step2Cfg(L, batch, T_r, 0, pq_capacity, max_expansions, T_u)
     sz = ctypes.c_size_t(0)
     _check(lib().labs_refine_step2_workspace(ctypes.byref(cfg), n, ctypes.byref(sz)))
     if workspace is None or workspace.numel() < sz.value:

@@ -121,8 +121,8 @@ def test_step2_validation_without_a_gpu():
     ok = labs.Step2Cfg(501, 1024, 0, 0, 1 << 20, 10_000_000, 1 << 62)
     assert L.labs_refine_step2_workspace(ctypes.byref(ok), 1024, ctypes.byref(sz)) == 0
     assert sz.value > 10 ** 9                  # the hash set is sized for 10^7 expansions
-    for field, value in (("L", 1), ("L", 1024), ("batch", 0), ("T_r", 1), ("pq_capacity", 0),
-                         ("max_expansions", -1), ("T_u", 0)):
+    for field, value in (("L", 1), ("L", 1024), ("batch", 0), ("T_r", -1), ("T_r", 33),
+                         ("pq_capacity", 0), ("max_expansions", -1), ("T_u", 0)):
         c = labs.Step2Cfg.from_buffer_copy(ok)
         setattr(c, field, value)
         assert L.labs_refine_step2_workspace(ctypes.byref(c), 1024, ctypes.byref(sz)) == -1, field
@@ -130,6 +130,16 @@ def test_step2_validation_without_a_gpu():
     huge.max_expansions = 1 << 30              # the hash set would pass 2^31 slots
     assert L.labs_refine_step2_workspace(ctypes.byref(huge), 1024, ctypes.byref(sz)) == -1
     assert L.labs_refine_step2_workspace(ctypes.byref(ok), 0, ctypes.byref(sz)) == -1
+    # rotations: accepted while 2 T_r < L, and they widen each round's products
+    base = sz.value if L.labs_refine_step2_workspace(ctypes.byref(ok), 1024, ctypes.byref(sz)) == 0 else 0
+    rot = labs.Step2Cfg.from_buffer_copy(ok)
+    rot.T_r = 8
+    assert L.labs_refine_step2_workspace(ctypes.byref(rot), 1024, ctypes.byref(sz)) == 0
+    assert sz.value > base
+    small = labs.Step2Cfg(9, 4, 4, 0, 100, 100, 100)
+    assert L.labs_refine_step2_workspace(ctypes.byref(small), 1, ctypes.byref(sz)) == 0
+    small.T_r = 5                              # 2 T_r >= L
+    assert L.labs_refine_step2_workspace(ctypes.byref(small), 1, ctypes.byref(sz)) == -1
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")

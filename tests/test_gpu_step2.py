@@ -23,9 +23,9 @@ def _dev(packed):
     return torch.from_numpy(np.ascontiguousarray(packed).view(np.int32)).cuda()
 
 
-def _run_both(lb, orc, L, cands, B, Q, X, T_u):
-    g = lb.refine_step2(L, _dev(li.pack(cands)), B, Q, X, T_u, open_capacity=Q)
-    o = orc.step2(L, list(cands), B, Q, X, T_u)
+def _run_both(lb, orc, L, cands, B, Q, X, T_u, T_r=0):
+    g = lb.refine_step2(L, _dev(li.pack(cands)), B, Q, X, T_u, open_capacity=Q, T_r=T_r)
+    o = orc.step2(L, list(cands), B, Q, X, T_u, T_r=T_r)
     for f in ("expansions", "pushes", "dup_skips", "evictions", "rounds", "best_round"):
         assert g[f] == o[f], (f, g[f], o[f])
     assert g["best_E"] == o["best_E"]
@@ -80,3 +80,43 @@ def test_step2_zero_budget(lb, orc):
     cands = li.random_pm1(2, 3, L)
     g, o = _run_both(lb, orc, L, cands, 4, 100, 0, 1 << 40)
     assert g["expansions"] == 0 and g["rounds"] == 0
+
+
+# ------------------------------------------------------------------ rotations
+@pytest.mark.parametrize("L,n,B,Q,X,T_u,T_r", [
+    (11, 3, 1, 1 << 20, 60, 1 << 40, 2),       # Algorithm 2 with rotations, batch 1
+    (13, 4, 4, 30, 200, 1 << 40, 3),           # capacity cut and re-pushes
+    (16, 2, 7, 1 << 20, 300, 1 << 40, 7),      # even length, 2 T_r = L - 2
+    (33, 5, 3, 64, 150, 12, 1),                # dynamic depth stop
+    (101, 6, 64, 3000, 1500, 300, 8),
+    (200, 2, 32, 500, 400, 1 << 40, 32),       # the largest T_r
+    (701, 2, 4, 200, 16, 1 << 40, 4),          # direct expansion
+    (1023, 2, 2, 100, 8, 1 << 40, 32),
+])
+def test_step2_rotations_parity(lb, orc, L, n, B, Q, X, T_u, T_r):
+    cands = li.random_pm1(L * 11 + n, n, L)
+    g, o = _run_both(lb, orc, L, cands, B, Q, X, T_u, T_r)
+    assert g["pushes"] + g["dup_skips"] == g["expansions"] * (L + 2 * T_r)
+
+
+def test_step2_rotations_periodic_pivot(lb, orc):
+    """A pivot of period 3 meets itself at shift 3 and repeats its own rotations."""
+    L = 9
+    c = np.array([[1, 1, -1] * 3], np.int8)
+    _run_both(lb, orc, L, c, 1, 1 << 20, 1, 1 << 40, 4)
+    _run_both(lb, orc, L, c, 2, 1 << 20, 40, 1 << 40, 4)
+
+
+def test_step2_rotations_full_space(lb, orc):
+    """Room for all 2^10 sequences: with rotations the search still ends at the
+    published optimum after popping every sequence once."""
+    L = 10
+    cands = li.random_pm1(4, 2, L)
+    g, o = _run_both(lb, orc, L, cands, 5, 1 << 20, 1 << 20, 1 << 40, 2)
+    assert g["best_E"] == 13 and g["expansions"] == 1 << L
+
+
+def test_step2_rotations_L501(lb, orc):
+    L = 501
+    cands = li.random_skew(6, 3, L, 16)
+    _run_both(lb, orc, L, cands, 16, 1000, 48, 1 << 40, 4)
