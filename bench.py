@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--no-rotations", action="store_true",
                     help="skip the second step with rotations (T_r = 1, 4, 16)")
     ap.add_argument("--rot-expansions", type=int, default=2_000_000)
+    ap.add_argument("--rot-values", default="0,1,4,16", help="comma-separated T_r values")
     ap.add_argument("--no-even", action="store_true",
                     help="skip carrying the result to L - 1 and L + 1 with the end operators")
     ap.add_argument("--even-expansions", type=int, default=2_000_000)
@@ -313,11 +314,11 @@ def even_lengths(a, labs, dev, top_seqs, best_seq):
 
 def rotations_measure(a, labs, dev, top_seqs):
     """MAKE_ROTATIONS in the second step at L = 501: from the first step's top-k,
-    the second step without rotations and with T_r = 1, 4, 16 (batch 1024, queue
-    2^20, --rot-expansions pops): time per round and best F."""
+    the second step at each T_r of --rot-values (default 0, 1, 4, 16; batch 1024,
+    queue 2^20, --rot-expansions pops): time per round and best F."""
     import torch
     out = {"expansions": a.rot_expansions, "runs": {}}
-    for T_r in (0, 1, 4, 16):
+    for T_r in [int(x) for x in a.rot_values.split(",")]:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = labs.refine_step2(L, top_seqs.contiguous(), 1024, 1 << 20, a.rot_expansions, 1 << 62, T_r=T_r)

@@ -142,6 +142,7 @@ struct Params {
     int32_t Tr, R2;
     unsigned long long* rkey;   // [B*R2] their Zobrist keys
     int32_t* rE;                // [B*R2] their energies
+    uint32_t* pw0;              // [B] first packed word of each pivot of the round
 };
 
 __device__ __forceinline__ uint64_t zob(int i) { return zobrist_at(i); }
@@ -1224,16 +1225,27 @@ __global__ __launch_bounds__(kRotThreads) void k_rot_build(Params P) {
     if (b >= c->n_piv) return;
     __shared__ int8_t s[kMaxL];
     __shared__ int32_t C0[kMaxL], C[kMaxL];
+    __shared__ uint32_t V[40];
     __shared__ int32_t red_e[kRotThreads / 64];
     __shared__ uint32_t red_lo[kRotThreads / 64], red_hi[kRotThreads / 64];
-    const int L = P.L, t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const uint32_t* ps = P.H.seq + (size_t)P.piv[b] * P.W;
+    const int L = P.L, W = P.W, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint32_t* ps = P.H.seq + (size_t)P.piv[b] * W;
     for (int x = t; x < L; x += kRotThreads) s[x] = ((ps[x >> 5] >> (31 - (x & 31))) & 1u) ? 1 : -1;
+    // V bit j = digit of element j (LSB first), zero past the sequence
+    for (int w = t; w < 40; w += kRotThreads) V[w] = w < W ? __builtin_bitreverse32(ps[w]) : 0u;
+    if (t == 0) P.pw0[b] = ps[0];
     __syncthreads();
+    // C_k = (L - k) - 2 (number of positions where s_i != s_{i+k}), by popcounts
     for (int k = 1 + t; k < L; k += kRotThreads) {
-        int acc = 0;
-        for (int i = 0; i + k < L; ++i) acc += s[i] * s[i + k];
-        C0[k] = acc;
+        const int q = k >> 5, r = k & 31, n = L - k;
+        int dis = 0;
+        for (int w = 0; w * 32 < n; ++w) {
+            const uint32_t sh = __builtin_amdgcn_alignbit(V[w + q + 1], V[w + q], r);
+            const int left = n - 32 * w;
+            const uint32_t m = left >= 32 ? 0xffffffffu : ((1u << left) - 1u);
+            dis += __popc((V[w] ^ sh) & m);
+        }
+        C0[k] = n - 2 * dis;
     }
     __syncthreads();
     for (int dir = 0; dir < 2; ++dir) {
@@ -1326,12 +1338,16 @@ __global__ __launch_bounds__(kRotThreads) void k_rot_stage(Params P) {
             if (eq) dupq[q] = 1;
         }
     }
-    // within one flip of a pivot of the round
+    // within one flip of a pivot of the round (first words compared first)
     for (long long v = t; v < np; v += kRotThreads) {
-        const uint32_t* pv = P.H.seq + (size_t)P.piv[v] * W;
+        const uint32_t w0 = P.pw0[v];
         for (int q = 0; q < R2; ++q) {
-            int d = 0;
-            for (int w = 0; w < W && d <= 1; ++w) {
+            uint32_t x0 = rw[q][0] ^ w0;
+            if (W == 1) x0 &= last_mask;
+            if (__popc(x0) > 1) continue;
+            const uint32_t* pv = P.H.seq + (size_t)P.piv[v] * W;
+            int d = __popc(x0);
+            for (int w = 1; w < W && d <= 1; ++w) {
                 uint32_t x = rw[q][w] ^ pv[w];
                 if (w == W - 1) x &= last_mask;
                 d += __popc(x);
@@ -1770,6 +1786,7 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     t += align_up(lo.cap_new + 4, 256);                                // repeat
     t += align_up(sizeof(unsigned long long) * (2 * c.T_r * c.batch + 1), 256);   // rotation keys
     t += align_up(sizeof(int32_t) * (2 * c.T_r * c.batch + 1), 256);              // rotation energies
+    t += align_up(sizeof(uint32_t) * c.batch, 256);                                // pivots' first words
     t += align_up(sizeof(Ctl), 256);
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // oE
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // oS
@@ -1835,6 +1852,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.R2 = 2 * cfg.T_r;
     P.rkey = cv.take<unsigned long long>((size_t)P.R2 * cfg.batch + 1);
     P.rE = cv.take<int32_t>((size_t)P.R2 * cfg.batch + 1);
+    P.pw0 = cv.take<uint32_t>((size_t)cfg.batch);
     int tcur = 0;
     P.H = tabs[0];
     P.ctl = cv.take<Ctl>(1);
