@@ -54,8 +54,12 @@ constexpr uint32_t ST_OPEN = 1, ST_CLOSED = 2, ST_EVICTED = 3;
 // select works on (E - emin)/4.  E <= sum_{j<L} j^2 = (L-1)L(2L-1)/6 < 2^29 for
 // L <= 1023, so (E - emin)/4 < 2^27 and two 14-bit levels always suffice.
 constexpr int kSelBits = 14;
-constexpr int kSelLevels = 2;
-static_assert(2 * kSelBits >= 27, "two select levels must cover (E - emin)/4 for L <= 1023");
+// One radix level of kSelBits over D = (E - emin)/4 (< 2^27 for L <= 1023); when it
+// leaves a bin of 2^ls values (ls = bit length of the range - kSelBits), the cut
+// takes everything below the bin and the tie select resolves the bin's values
+// (at most 2^kSubBits of them) before the key bytes.
+constexpr int kSubBits = 13;
+static_assert(kSelBits + kSubBits >= 27, "the sub-bins must cover (E - emin)/4 for L <= 1023");
 constexpr int kSelBins = 1 << kSelBits;
 constexpr int kSelBlocks = 128;
 constexpr int kSelThreads = 512;
@@ -711,7 +715,12 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
     if (c->stop || !c->sel_enabled) return;
     const int cur = c->which;
     const bool all = c->sel_all;
+    // resolved: the threshold energy Et; otherwise the threshold bin [Dlo, Dhi) of D
+    const bool res = c->resolved;
     const uint32_t Et = c->emin + (c->Dt << 2);
+    const uint32_t emin = c->emin;
+    const uint32_t Dlo = res ? 0u : c->prefix << c->hi_shift;
+    const uint32_t Dhi = res ? 0u : (c->prefix + 1u) << c->hi_shift;
     const long long n_tot = c->n_tot;
     const long long stride = (long long)gridDim.x * blockDim.x * kItems;
     for (long long base = (long long)blockIdx.x * blockDim.x * kItems; base < n_tot; base += stride) {
@@ -725,8 +734,16 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
                 const int32_t e = P.oE[cur][i];
                 uint32_t f = 0;
                 if (e != DEAD) {
-                    if (all || (uint32_t)e < Et) f = 1;
-                    else if ((uint32_t)e == Et) tie[k] = true;
+                    if (all) {
+                        f = 1;
+                    } else if (res) {
+                        if ((uint32_t)e < Et) f = 1;
+                        else if ((uint32_t)e == Et) tie[k] = true;
+                    } else {
+                        const uint32_t D = ((uint32_t)e - emin) >> 2;
+                        if (D < Dlo) f = 1;
+                        else if (D < Dhi) tie[k] = true;
+                    }
                 }
                 P.flag[i] = f;
             }
@@ -791,6 +808,62 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
     long long r = c->T - c->c_lt;
     int src = 0;
     int pos = 0;
+    // every thread reads the control block before thread 0 updates it below
+    const bool unres = !c->resolved;
+    const int ls = c->hi_shift;
+    __syncthreads();
+    if (unres && (ls > kSubBits || r >= m)) {
+        // the whole bin is taken (or its width is out of range: an error the host sees)
+        if (t == 0) {
+            if (ls > kSubBits) atomicExch(&c->error, 6);
+            c->Dt = ((c->prefix + 1u) << ls) - 1u;
+            c->resolved = 1;
+        }
+        if (ls > kSubBits) return;
+    } else if (unres && r > 0) {
+        // The one radix level left a bin of 2^ls values of D: select its r smallest
+        // values exactly (a histogram of D - Dlo in LDS, over the zs storage), keep
+        // the entries below the threshold value, and go on with the tied ones.
+        const uint32_t Dlo = c->prefix << ls;
+        const uint32_t emin = c->emin;
+        const int nsub = 1 << ls;
+        uint32_t* hs = (uint32_t*)&zs[0][0];   // 2 * kTieLds * 8 bytes = 2^kSubBits counts
+        for (int k = t; k < nsub; k += blockDim.x) hs[k] = 0;
+        if (t == 0) s_m2 = 0;
+        __syncthreads();
+        for (int q = t; q < m; q += blockDim.x)
+            atomicAdd(&hs[((uint32_t)P.oE[cur][P.cand[src][q]] - emin) / 4u - Dlo], 1u);
+        __syncthreads();
+        if (t == 0) {
+            long long cum = 0;
+            int v = 0;
+            for (; v < nsub; ++v) {
+                if (cum + hs[v] >= r) break;
+                cum += hs[v];
+            }
+            s_v = v;
+            s_r = r - cum;
+            c->Dt = Dlo + (uint32_t)v;   // the cut's energy, for the next round's bounds
+            c->resolved = 1;
+        }
+        __syncthreads();
+        const uint32_t Dv = Dlo + (uint32_t)s_v;
+        for (int q = t; q < m; q += blockDim.x) {
+            const int idx = P.cand[src][q];
+            const uint32_t D = ((uint32_t)P.oE[cur][idx] - emin) / 4u;
+            if (D < Dv) P.flag[idx] = 1;
+            else if (D == Dv) {
+                const int o2 = atomicAdd(&s_m2, 1);
+                P.cand[1 - src][o2] = idx;
+                P.candz[1 - src][o2] = P.candz[src][q];
+            }
+        }
+        __syncthreads();
+        m = s_m2;
+        r = s_r;
+        src = 1 - src;
+        __syncthreads();
+    }
     // Large tie sets: partition on key bytes read from the Open list until the
     // remaining set fits in LDS (keys are pseudo-random, so one byte divides
     // the set by about 256).
@@ -1880,10 +1953,8 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     // of a min/max pass.
     auto select = [&](bool minmax) {
         if (minmax) hipLaunchKernelGGL(k_sel_minmax, dim3(kSelBlocks), tS, 0, st, P);
-        for (int lv = 0; lv < kSelLevels; ++lv) {
-            hipLaunchKernelGGL(k_sel_hist, dim3(kSelBlocks), tS, 0, st, P, lv);
-            hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(1024), 0, st, P, lv);
-        }
+        hipLaunchKernelGGL(k_sel_hist, dim3(kSelBlocks), tS, 0, st, P, 0);
+        hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(1024), 0, st, P, 0);
         hipLaunchKernelGGL(k_sel_classify, gS, tS, 0, st, P);
         hipLaunchKernelGGL(k_sel_keys, dim3(1), dim3(1024), 0, st, P);
     };

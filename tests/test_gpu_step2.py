@@ -120,3 +120,19 @@ def test_step2_rotations_L501(lb, orc):
     L = 501
     cands = li.random_skew(6, 3, L, 16)
     _run_both(lb, orc, L, cands, 16, 1000, 48, 1 << 40, 4)
+
+
+@pytest.mark.parametrize("L,B,Q,X", [(301, 4, 50, 40), (501, 3, 20, 12), (64, 2, 30, 30)])
+def test_step2_wide_energy_range(lb, orc, L, B, Q, X):
+    """Candidates whose energies span millions (the all +1 and alternating
+    sequences beside random ones): one 14-bit radix level cannot resolve the
+    selection, so the tie select resolves the threshold bin's energies first."""
+    allp = np.ones(L, np.int8)
+    alt = np.array([1 if i % 2 == 0 else -1 for i in range(L)], np.int8)
+    rnd = li.random_pm1(L + 3, 5, L)
+    cands = np.concatenate([allp[None], alt[None], rnd])
+    E = [orc.energy(x) for x in cands]
+    if L > 100:
+        assert (max(E) - min(E)) // 4 >= 1 << 14
+    _run_both(lb, orc, L, cands, B, Q, X, 1 << 40)
+    _run_both(lb, orc, L, cands, B, Q, X, 1 << 40, T_r=2)
