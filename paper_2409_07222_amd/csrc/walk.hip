@@ -15,16 +15,18 @@
 // The centre a = k+1 flips alone: dC_{2m} = -4 s_a s_{a-2m}.
 //
 // G_a is evaluated bit-sliced.  Forward/backward windows F_a, B_a hold, at bit
-// m-1, the 0/1 digit of s_{a+2m} / s_{a-2m} (0 outside 1..L).  With the
-// two's-complement bit planes P_j of the vector (C_{2m})_m,
-//   sum_m C_{2m} F_a(m) = sum_j w_j popcount(P_j & F_a),  w_j = 2^j (sign plane -2^j),
+// m-1, the 0/1 digit of s_{a+2m} / s_{a-2m} (0 outside 1..L).  Every C_{2m} is
+// odd (L - 2m terms of +-1), so with C'_m = (C_{2m} - 1)/2 and the two's-complement
+// bit planes P_j of (C'_m)_m,
+//   sum_m C_{2m} F_a(m) = 2 sum_j w_j popcount(P_j & F_a) + popcount(F_a),
+//   w_j = 2^j (sign plane -2^j),
 // and since s = 2*digit - 1 on valid lags,
 //   G_a = 2 (H_f + H_b) - PC[Mf] - PC[Mb] - C_{2mp} s_b,   PC = prefix sums of C_{2m},
 //   Q_a = Mf - 1 + 3 Mb - 4 popcount((F ^ B) & [m <= Mb]) - 2 [mp <= Mb] s_b s_{a-2mp},
 // with Mf = (L-a)/2 and Mb = (a-1)/2 the valid forward/backward lag counts.
 // The planes are built per step with one ballot per (plane, 64 lags); the
-// number of planes is the bit length of max |C_{2m}| plus the sign, read off
-// the current table each step, so the scan is exact for every state.
+// number of planes is the bit length of max |C'_m| plus the sign, read off the
+// current table each step, so the scan is exact for every state.
 //
 // Windows come from per-parity bit vectors of the sequence: V_pi bit j is the
 // digit of position 2j+2-pi (pi = x & 1, j = (x-1)>>1), VR_pi its reversal over

@@ -212,10 +212,16 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
     }
 
     for (int t = t0 + 1; t <= t1; ++t) {
-        // ---- number of bit planes for the current C table
+        // ---- bit planes of C' = (C - 1)/2: for odd L every even-lag C_{2m} is odd
+        // (a sum of L - 2m terms of +-1), so sum_m C F = 2 sum_m C' F + popcount(F)
+        // with one plane fewer
         uint32_t orv = 0;
+        int32_t Ch[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) orv |= (uint32_t)(C[q] ^ (C[q] >> 31));
+        for (int q = 0; q < NQ; ++q) {
+            Ch[q] = (64 * q + lane + 1 <= K) ? (C[q] - 1) >> 1 : 0;
+            orv |= (uint32_t)(Ch[q] ^ (Ch[q] >> 31));
+        }
         orv = __ockl_wfred_or_u32(orv);
         const int nb = (32 - __clz((int)orv)) + 1;
 
@@ -236,7 +242,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
                 for (int r = 0; r < RB; ++r) acc[r] = 0;
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
-                    const uint64_t bal = __ballot((C[q] >> jp) & 1);
+                    const uint64_t bal = __ballot((Ch[q] >> jp) & 1);
                     const uint32_t lo = (uint32_t)bal, hi = (uint32_t)(bal >> 32);
 #pragma unroll
                     for (int r = 0; r < RB; ++r) {
@@ -249,6 +255,15 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
                 const int wgt = (jp == nb - 1) ? -(1 << jp) : (1 << jp);
 #pragma unroll
                 for (int r = 0; r < RB; ++r) H[r] += wgt * (int)acc[r];
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                int pf = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) pf += __popc(F[r][w]);
+#pragma unroll
+                for (int w = 0; w < NQ; ++w) pf += __popc(B[r][w]);
+                H[r] = 2 * H[r] + pf;
             }
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr) {
