@@ -163,6 +163,9 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
     int32_t C[NQ];
     compute_cev<NW>(S, L, K, lane, C);
     store_tables<NW>(S, K, lane, C);
+    int32_t Ch[NQ];   // (C_{2m} - 1)/2 on valid lags, 0 beyond; kept beside C
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) Ch[q] = (64 * q + lane + 1 <= K) ? (C[q] - 1) >> 1 : 0;
     int32_t tabu[R];
     uint64_t zr[R];        // Bloom: Zobrist entry of each slot's position
     uint64_t hk = 0;       // Bloom: key of the current sequence
@@ -216,12 +219,8 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
         // (a sum of L - 2m terms of +-1), so sum_m C F = 2 sum_m C' F + popcount(F)
         // with one plane fewer
         uint32_t orv = 0;
-        int32_t Ch[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            Ch[q] = (64 * q + lane + 1 <= K) ? (C[q] - 1) >> 1 : 0;
-            orv |= (uint32_t)(Ch[q] ^ (Ch[q] >> 31));
-        }
+        for (int q = 0; q < NQ; ++q) orv |= (uint32_t)(Ch[q] ^ (Ch[q] >> 31));
         orv = __ockl_wfred_or_u32(orv);
         const int nb = (32 - __clz((int)orv)) + 1;
 
@@ -362,6 +361,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
                 if (cen) u = S.sv[PADL + as - 2 * m];
                 else u = S.sv[PADL + as + 2 * m] + S.sv[PADL + as - 2 * m] - (m == mps ? s_bs : 0);
                 C[q] += -4 * s_as * u;
+                Ch[q] += -2 * s_as * u;
             }
         }
         E += g;
