@@ -17,9 +17,10 @@
 //    buffer, so every round starts from a dense list.  A round's neighbours sit
 //    at fixed positions (pivot b, flip i) after the surviving old entries.
 //  * an exact "T smallest" selection in the order (E, Zobrist key, sequence):
-//    energies of one length are congruent mod 4, so (E - emin)/4 is selected in
-//    two 14-bit radix levels, then the entries tied at the threshold energy are
-//    split byte by byte on the Zobrist key (and, if keys collide, the sequence).
+//    energies of one length are congruent mod 4, so (E - emin)/4 is selected by
+//    one 14-bit radix level (a bin it leaves unresolved is finished by the tie
+//    select), then the entries tied at the threshold energy are split byte by
+//    byte on the Zobrist key (and, if keys collide, the sequence).
 //    The energy window of the last cut is carried to the next round as the
 //    starting bounds.
 //
@@ -52,7 +53,7 @@ constexpr uint32_t ST_OPEN = 1, ST_CLOSED = 2, ST_EVICTED = 3;
 // Radix digit of the energy select.  All energies of one length L are congruent
 // mod 4 (C_k has the parity of L-k, so C_k^2 is 0 mod 4 or 1 mod 8), so the
 // select works on (E - emin)/4.  E <= sum_{j<L} j^2 = (L-1)L(2L-1)/6 < 2^29 for
-// L <= 1023, so (E - emin)/4 < 2^27 and two 14-bit levels always suffice.
+// L <= 1023, so (E - emin)/4 < 2^27.
 constexpr int kSelBits = 14;
 // One radix level of kSelBits over D = (E - emin)/4 (< 2^27 for L <= 1023); when it
 // leaves a bin of 2^ls values (ls = bit length of the range - kSelBits), the cut
@@ -99,7 +100,7 @@ struct Ctl {
     long long T, c_lt, need;
     uint32_t emin, emax;
     int32_t sel_enabled, sel_all;
-    int32_t hi_shift, lo_shift;
+    int32_t hi_shift, pad4;   // hi_shift: bin width (bits of D) of an unresolved select
     uint32_t prefix, Dt;
     int32_t resolved, n_cand;
     // table occupancy (claimed slots, tombstones included) and rebuild scratch
@@ -127,7 +128,7 @@ struct Params {
     int32_t* cand[2];      // [cap_o] each: Open positions of tied entries
     unsigned long long* candz[2];   // [cap_o] each: their Zobrist keys
     int32_t* piv;          // [B]
-    uint32_t* ghist;       // [kSelBins], zero between selection levels
+    uint32_t* ghist;       // [kSelBins], zero between selections
     uint32_t* best_seq;    // [W] copy of the best sequence
     Pend* pend;            // [cap_pend]
     Pend* slow;            // [cap_pend]
@@ -609,32 +610,24 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_minmax(Params P) {
     }
 }
 
-// Level 0 derives the digit layout from [emin, emax]; later levels read it back.
-__device__ __forceinline__ void level_shifts(const Ctl* c, int level, int* hs, int* ls, uint32_t* prefix) {
-    if (level == 0) {
-        const uint32_t R = (c->emax - c->emin) >> 2;
-        const int nbits = R ? 32 - __clz((int)R) : 0;
-        *hs = nbits;
-        *ls = nbits > kSelBits ? nbits - kSelBits : 0;
-        *prefix = 0;
-    } else {
-        *hs = c->hi_shift;
-        *ls = c->lo_shift;
-        *prefix = c->prefix;
-    }
+// The digit layout from [emin, emax]: D has hs bits; the histogram bins D >> ls.
+__device__ __forceinline__ void digit_shifts(const Ctl* c, int* hs, int* ls) {
+    const uint32_t R = (c->emax - c->emin) >> 2;
+    const int nbits = R ? 32 - __clz((int)R) : 0;
+    *hs = nbits;
+    *ls = nbits > kSelBits ? nbits - kSelBits : 0;
 }
 
-__global__ __launch_bounds__(kSelThreads) void k_sel_hist(Params P, int level) {
+// Block histograms of D >> ls over the live Open entries, merged into one.
+__global__ __launch_bounds__(kSelThreads) void k_sel_hist(Params P) {
     Ctl* c = P.ctl;
     if (c->stop || !c->sel_enabled || c->sel_all) return;
-    if (level > 0 && c->resolved) return;
-    if (level == 0 && c->emax == c->emin) return;
+    if (c->emax == c->emin) return;
     __shared__ uint32_t h[kSelBins];
     for (int b = threadIdx.x; b < kSelBins; b += blockDim.x) h[b] = 0;
     __syncthreads();
     int hs, ls;
-    uint32_t prefix;
-    level_shifts(c, level, &hs, &ls, &prefix);
+    digit_shifts(c, &hs, &ls);
     const int cur = c->which;
     const uint32_t emin = c->emin;
     const uint32_t dmask = (1u << (hs - ls)) - 1u;
@@ -643,7 +636,7 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_hist(Params P, int level) {
         const int32_t e = P.oE[cur][i];
         if (e == DEAD) continue;
         const uint32_t D = ((uint32_t)e - emin) >> 2;
-        if (hs < 32 && (D >> hs) != prefix) continue;
+        if (hs < 32 && (D >> hs) != 0u) continue;
         atomicAdd(&h[(D >> ls) & dmask], 1u);
     }
     __syncthreads();
@@ -651,12 +644,14 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_hist(Params P, int level) {
         if (h[b]) atomicAdd(&P.ghist[b], h[b]);
 }
 
-__global__ __launch_bounds__(1024) void k_sel_find(Params P, int level) {
+// The bin holding the T-th smallest entry: resolved when bins are single values
+// of D (ls = 0), else the bin [prefix << ls, (prefix + 1) << ls) is left to the
+// tie select.
+__global__ __launch_bounds__(1024) void k_sel_find(Params P) {
     Ctl* c = P.ctl;
     if (c->stop || !c->sel_enabled || c->sel_all) return;
-    if (level > 0 && c->resolved) return;
     const int t = threadIdx.x;
-    if (level == 0 && c->emax == c->emin) {   // every live entry has one energy
+    if (c->emax == c->emin) {   // every live entry has one energy
         if (t == 0) {
             c->c_lt = 0;
             c->resolved = 1;
@@ -667,14 +662,12 @@ __global__ __launch_bounds__(1024) void k_sel_find(Params P, int level) {
     constexpr int PER = kSelBins / 1024;
     __shared__ uint32_t part[1024];
     int hs, ls;
-    uint32_t prefix;
-    level_shifts(c, level, &hs, &ls, &prefix);
-    const long long c_lt = level == 0 ? 0 : c->c_lt;
+    digit_shifts(c, &hs, &ls);
     uint32_t cnt[PER];
     uint32_t a = 0;
     for (int k = 0; k < PER; ++k) {
         cnt[k] = P.ghist[PER * t + k];
-        P.ghist[PER * t + k] = 0;   // the histogram is empty for the next level
+        P.ghist[PER * t + k] = 0;   // the histogram is empty for the next selection
         a += cnt[k];
     }
     part[t] = a;
@@ -685,7 +678,7 @@ __global__ __launch_bounds__(1024) void k_sel_find(Params P, int level) {
         part[t] += x;
         __syncthreads();
     }
-    const long long need = c->T - c_lt;
+    const long long need = c->T;
     long long before = (long long)part[t] - a;
     if (before < need && need <= before + a) {
         int v = PER * t;
@@ -696,16 +689,14 @@ __global__ __launch_bounds__(1024) void k_sel_find(Params P, int level) {
             }
             before += cnt[k];
         }
-        c->c_lt = c_lt + before;
-        const uint32_t np = (prefix << (hs - ls)) | (uint32_t)v;
-        c->prefix = np;
+        c->c_lt = before;
+        c->prefix = (uint32_t)v;
         if (ls == 0) {
             c->resolved = 1;
-            c->Dt = np;
+            c->Dt = (uint32_t)v;
         } else {
             c->resolved = 0;
             c->hi_shift = ls;
-            c->lo_shift = ls > kSelBits ? ls - kSelBits : 0;
         }
     }
 }
@@ -1953,8 +1944,8 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     // of a min/max pass.
     auto select = [&](bool minmax) {
         if (minmax) hipLaunchKernelGGL(k_sel_minmax, dim3(kSelBlocks), tS, 0, st, P);
-        hipLaunchKernelGGL(k_sel_hist, dim3(kSelBlocks), tS, 0, st, P, 0);
-        hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(1024), 0, st, P, 0);
+        hipLaunchKernelGGL(k_sel_hist, dim3(kSelBlocks), tS, 0, st, P);
+        hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(1024), 0, st, P);
         hipLaunchKernelGGL(k_sel_classify, gS, tS, 0, st, P);
         hipLaunchKernelGGL(k_sel_keys, dim3(1), dim3(1024), 0, st, P);
     };
