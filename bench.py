@@ -182,26 +182,33 @@ def step1_configs(a, labs, dev):
     return out
 
 
-def batched_measure(a, labs, dev):
-    """Uneven lengths in one launch: every odd L in [301, 449] (75 lengths), 4096
+def batched_measure(a, labs, dev, walkers=4096, steps=None, tune=True):
+    """Uneven lengths in one launch: every odd L in [301, 449] (75 lengths), `walkers`
     walkers each, p = 12, tenure [L/10, L/5], seed 3.  Tiles come from the
     autotuner (short trials first); the batched call (hipGraph capture included)
-    is timed against one walk_step1 launch per length."""
+    and its replay are timed against one walk_step1 launch per length."""
     import torch
     sync = torch.cuda.synchronize
+    steps = steps or a.batched_steps
     Ls = list(range(301, 450, 2))
-    cfgs = [dict(L=x, p=12, steps=a.batched_steps, tenure_lo=x // 10, tenure_hi=x // 5, seed=3,
-                 n_walkers=4096) for x in Ls]
-    sync()
-    t0 = time.perf_counter()
-    labs.autotune_step1(Ls, 12, 4096, 1000, device=dev)
-    sync()
-    t_tune = time.perf_counter() - t0
+    cfgs = [dict(L=x, p=12, steps=steps, tenure_lo=x // 10, tenure_hi=x // 5, seed=3,
+                 n_walkers=walkers) for x in Ls]
+    t_tune = 0.0
+    if tune:
+        sync()
+        t0 = time.perf_counter()
+        labs.autotune_step1(Ls, 12, 4096, 1000, device=dev)
+        sync()
+        t_tune = time.perf_counter() - t0
     t0 = time.perf_counter()
     res, ws = labs.walk_step1_batch(cfgs, device=dev)
     sync()
     t_b = time.perf_counter() - t0
     evals = sum(int(r.flip_evals.item()) for r in res)
+    t0 = time.perf_counter()
+    labs.walk_step1_batch(cfgs, device=dev, workspace=ws, results=res)
+    sync()
+    t_replay = time.perf_counter() - t0
     del res, ws
     per_L = {}
     t_s = 0.0
@@ -214,11 +221,12 @@ def batched_measure(a, labs, dev):
         dt = time.perf_counter() - t0
         t_s += dt
         per_L[c["L"]] = int(r.flip_evals.item()) / dt
-    return {"lengths": len(Ls), "L_range": [Ls[0], Ls[-1]], "walkers_per_L": 4096, "p": 12,
-            "steps": a.batched_steps, "flip_evals": evals, "autotune_s": t_tune,
+    return {"lengths": len(Ls), "L_range": [Ls[0], Ls[-1]], "walkers_per_L": walkers, "p": 12,
+            "steps": steps, "flip_evals": evals, "autotune_s": t_tune,
             "batched_s": t_b, "batched_flip_evals_per_s": evals / t_b,
+            "replay_s": t_replay, "replay_flip_evals_per_s": evals / t_replay,
             "per_length_launches_s": t_s, "per_length_flip_evals_per_s": evals / t_s,
-            "speedup": t_s / t_b,
+            "speedup": t_s / t_b, "speedup_replay": t_s / t_replay,
             "per_L_flip_evals_per_s": {str(k): round(v, -6) for k, v in per_L.items()}}
 
 
@@ -645,7 +653,14 @@ def main():
                                     "kernel_share_of_pass": ms2 / 1e3 / t_pass}
 
     log("dual-step passes done: %.3e flip-evals/s" % (evals / dt))
-    batched = None if a.no_batched else batched_measure(a, labs, dev)
+    batched = batched_small = None
+    if not a.no_batched:
+        batched = batched_measure(a, labs, dev)
+        # small work per length: 256 walkers x 4000 steps, where one launch per length
+        # leaves most of the GPU idle
+        batched_small = batched_measure(a, labs, dev, walkers=256, steps=4000, tune=False)
+        log("batched: %.2fx at 4096 walkers per length, %.2fx at 256 (replay %.2fx)"
+            % (batched["speedup"], batched_small["speedup"], batched_small["speedup_replay"]))
     configs = None if a.no_configs else step1_configs(a, labs, dev)
     bloom = None if a.no_bloom else bloom_measure(a, labs, dev)
     legendre = None if a.no_legendre else legendre_step2(a, labs, dev)
@@ -682,6 +697,7 @@ def main():
         "tau_star": ab["tau_star"] if ab else None,
         "learned_ab": ab,
         "batched_uneven_L": batched,
+        "batched_uneven_L_small": batched_small,
         "step1_configs": configs,
         "bloom_walk": bloom,
         "legendre_seeded_step2": legendre,
