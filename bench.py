@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--s2-batch", type=int, default=1024)
     ap.add_argument("--s2-capacity", type=int, default=1 << 20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
+                    help="host threads of the CPU baseline (the box's CPU share for one GPU is 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline-pass", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
@@ -134,9 +136,12 @@ def walk_valu_utilisation():
     return float(v) if v is not None else None
 
 
-def cpu_baseline(budget_s: float):
-    """The oracle's first-step walker (definitional energies), single thread,
-    on a bounded sample of the same walk: one walker at L = 501, p = 16."""
+def cpu_baseline(budget_s: float, threads: int):
+    """The oracle's first-step walker (definitional energies) on a bounded sample of
+    the same walk: `threads` independent walkers at L = 501, p = 16 (walker ids
+    0..threads-1), one per host thread; the oracle's C walker runs outside the
+    interpreter lock, so the threads run in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
     oracle.lib()
     k = (L - 1) // 2
@@ -147,11 +152,14 @@ def cpu_baseline(budget_s: float):
     per_step = (time.perf_counter() - t0) / 4
     steps = max(4, int(budget_s / max(per_step, 1e-6)))
     t0 = time.perf_counter()
-    oracle.walk(L, P, steps, lo, hi, 4, [0], want_traj=False)
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda w: oracle.walk(L, P, steps, lo, hi, 4, [w], want_traj=False), range(threads)))
     dt = time.perf_counter() - t0
-    return {"value": steps * nf / dt, "unit": "flip-evals/s", "cores": 1, "kind": "oracle",
-            "sample": "1 walker x %d steps of the L=501 p=16 first-step walk (%d flip-evals, "
-                      "%.1f s), definitional energy per neighbour" % (steps, steps * nf, dt)}
+    n = threads * steps * nf
+    return {"value": n / dt, "unit": "flip-evals/s", "cores": threads, "kind": "oracle",
+            "sample": "%d walkers (one per thread) x %d steps of the L=501 p=16 first-step walk "
+                      "(%d flip-evals, %.1f s), definitional energy per neighbour"
+                      % (threads, steps, n, dt)}
 
 
 def step1_configs(a, labs, dev):
@@ -673,7 +681,7 @@ def main():
         s2_ws = None
         torch.cuda.empty_cache()
         ab = learned_ab(a, labs, dev)
-    cpu = None if a.no_cpu_baseline else cpu_baseline(a.cpu_seconds)
+    cpu = None if a.no_cpu_baseline else cpu_baseline(a.cpu_seconds, a.cpu_threads)
     value = evals / dt
     line = {
         "metric": METRIC, "value": value, "unit": "flip-evals/s", "n_gpus": 1,
