@@ -107,6 +107,13 @@ struct Ctl {
     long long claimed, claimed_new;
     long long out_count;
     uint32_t blo, bhi;     // bounds of the live Open energies (blo is one of them)
+    // A cut that also selects the next round's T2 pivots (the T2 smallest of the
+    // survivors are the T2 smallest before the cut): their own threshold, carried
+    // to the survivors' new positions by the cut (flagN); presel: this round's
+    // pivots were selected so.
+    long long T2, c_lt2, out_count2;
+    uint32_t Dt2, prefix2;
+    int32_t resolved2, dual, presel, dual_all;   // dual_all: T2 takes every survivor
 };
 
 // A pending insertion: the slot whose key matched, the source of the sequence
@@ -127,6 +134,9 @@ struct Params {
     uint32_t* flag;        // [cap_o]
     int32_t* cand[2];      // [cap_o] each: Open positions of tied entries
     unsigned long long* candz[2];   // [cap_o] each: their Zobrist keys
+    int32_t* cand2[2];     // the same for the next round's pivots (dual cut)
+    unsigned long long* candz2[2];
+    uint32_t* flagN;       // [cap_o] next round's pivots at the survivors' positions
     int32_t* piv;          // [B]
     uint32_t* ghist;       // [kSelBins], zero between selections
     uint32_t* best_seq;    // [W] copy of the best sequence
@@ -551,6 +561,30 @@ __global__ __launch_bounds__(256) void k_repeats(Params P) {
 }
 
 // ---------------------------------------------------------------- round control
+// The capacity cut (T = Q smallest survive; sel_all: nothing is evicted) together
+// with the next round's pivots (T2 = min(B, X - expansions) smallest of the
+// survivors, which are the T2 smallest overall).  sel_enabled: some threshold
+// needs the histogram.
+__device__ void cut_setup(const Params& P) {
+    Ctl* c = P.ctl;
+    c->T = P.Q;
+    c->sel_all = c->n_live > P.Q ? 0 : 1;
+    long long T2 = P.X - c->expansions;
+    if (T2 > P.B) T2 = P.B;
+    const long long surv = c->sel_all ? c->n_live : P.Q;
+    c->T2 = T2;
+    c->dual = T2 > 0 ? 1 : 0;
+    c->dual_all = T2 >= surv ? 1 : 0;
+    c->sel_enabled = (!c->sel_all || (c->dual && !c->dual_all)) ? 1 : 0;
+    c->c_lt2 = 0;
+    c->out_count2 = 0;
+    c->resolved2 = 1;
+    c->Dt2 = 0;
+    c->prefix2 = 0;
+    c->survivors = 0;
+    c->out_count = 0;
+}
+
 __device__ void round_begin(const Params& P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
@@ -561,8 +595,16 @@ __device__ void round_begin(const Params& P) {
     long long T = P.X - c->expansions;
     if (T > P.B) T = P.B;
     c->T = T;
-    c->sel_enabled = 1;
-    c->sel_all = T >= c->n_live ? 1 : 0;
+    // the last cut selected this round's T pivots (flagN at the survivors' positions)
+    c->presel = c->dual && c->T2 == T ? 1 : 0;
+    c->dual = 0;
+    c->sel_enabled = 0;
+    c->sel_all = 0;
+    if (!c->presel) {   // cannot happen while the search goes on
+        atomicExch(&c->error, 7);
+        c->stop = 1;
+        return;
+    }
     c->n_piv = 0;
     c->n_pend = 0;
     c->n_slow = 0;
@@ -580,7 +622,7 @@ __global__ void k_round_begin(Params P) { round_begin(P); }
 // Selects the T smallest live Open entries in key order into flag[].
 __global__ __launch_bounds__(kSelThreads) void k_sel_minmax(Params P) {
     Ctl* c = P.ctl;
-    if (c->stop || !c->sel_enabled || c->sel_all) return;
+    if (c->stop || !c->sel_enabled) return;
     __shared__ uint32_t smn, smx;
     if (threadIdx.x == 0) {
         smn = UINT32_MAX;
@@ -621,7 +663,7 @@ __device__ __forceinline__ void digit_shifts(const Ctl* c, int* hs, int* ls) {
 // Block histograms of D >> ls over the live Open entries, merged into one.
 __global__ __launch_bounds__(kSelThreads) void k_sel_hist(Params P) {
     Ctl* c = P.ctl;
-    if (c->stop || !c->sel_enabled || c->sel_all) return;
+    if (c->stop || !c->sel_enabled) return;
     if (c->emax == c->emin) return;
     __shared__ uint32_t h[kSelBins];
     for (int b = threadIdx.x; b < kSelBins; b += blockDim.x) h[b] = 0;
@@ -649,13 +691,16 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_hist(Params P) {
 // tie select.
 __global__ __launch_bounds__(1024) void k_sel_find(Params P) {
     Ctl* c = P.ctl;
-    if (c->stop || !c->sel_enabled || c->sel_all) return;
+    if (c->stop || !c->sel_enabled) return;
     const int t = threadIdx.x;
     if (c->emax == c->emin) {   // every live entry has one energy
         if (t == 0) {
             c->c_lt = 0;
             c->resolved = 1;
             c->Dt = 0;
+            c->c_lt2 = 0;
+            c->resolved2 = 1;
+            c->Dt2 = 0;
         }
         return;
     }
@@ -680,7 +725,7 @@ __global__ __launch_bounds__(1024) void k_sel_find(Params P) {
     }
     const long long need = c->T;
     long long before = (long long)part[t] - a;
-    if (before < need && need <= before + a) {
+    if (!c->sel_all && before < need && need <= before + a) {
         int v = PER * t;
         for (int k = 0; k < PER; ++k) {
             if (before + cnt[k] >= need) {
@@ -696,7 +741,26 @@ __global__ __launch_bounds__(1024) void k_sel_find(Params P) {
             c->Dt = (uint32_t)v;
         } else {
             c->resolved = 0;
-            c->hi_shift = ls;
+        }
+        c->hi_shift = ls;
+    }
+    if (t == 0) c->hi_shift = ls;
+    if (c->dual && !c->dual_all) {   // the next round's pivots from the same histogram
+        const long long need2 = c->T2;
+        long long before2 = (long long)part[t] - a;
+        if (before2 < need2 && need2 <= before2 + a) {
+            int v = PER * t;
+            for (int k = 0; k < PER; ++k) {
+                if (before2 + cnt[k] >= need2) {
+                    v = PER * t + k;
+                    break;
+                }
+                before2 += cnt[k];
+            }
+            c->c_lt2 = before2;
+            c->prefix2 = (uint32_t)v;
+            c->resolved2 = ls == 0;
+            c->Dt2 = (uint32_t)v;
         }
     }
 }
@@ -712,33 +776,53 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
     const uint32_t emin = c->emin;
     const uint32_t Dlo = res ? 0u : c->prefix << c->hi_shift;
     const uint32_t Dhi = res ? 0u : (c->prefix + 1u) << c->hi_shift;
+    // the dual cut's second threshold (bit 1 of flag: the next round's pivots)
+    const bool dual = c->dual;
+    const bool dual_all = c->dual_all;
+    const bool res2 = c->resolved2;
+    const uint32_t Et2 = c->emin + (c->Dt2 << 2);
+    const uint32_t D2lo = c->prefix2 << c->hi_shift;
+    const uint32_t D2hi = (c->prefix2 + 1u) << c->hi_shift;
     const long long n_tot = c->n_tot;
     const long long stride = (long long)gridDim.x * blockDim.x * kItems;
     for (long long base = (long long)blockIdx.x * blockDim.x * kItems; base < n_tot; base += stride) {
-        bool tie[kItems];
-        int cnt = 0;
+        bool tie[kItems], tie2[kItems];
+        int cnt = 0, cnt2 = 0;
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const long long i = base + threadIdx.x + (long long)k * blockDim.x;
             tie[k] = false;
+            tie2[k] = false;
             if (i < n_tot) {
                 const int32_t e = P.oE[cur][i];
                 uint32_t f = 0;
                 if (e != DEAD) {
+                    const uint32_t D = ((uint32_t)e - emin) >> 2;
                     if (all) {
                         f = 1;
                     } else if (res) {
                         if ((uint32_t)e < Et) f = 1;
                         else if ((uint32_t)e == Et) tie[k] = true;
                     } else {
-                        const uint32_t D = ((uint32_t)e - emin) >> 2;
                         if (D < Dlo) f = 1;
                         else if (D < Dhi) tie[k] = true;
+                    }
+                    if (dual && dual_all) {
+                        f |= 2u;
+                    } else if (dual) {
+                        if (res2) {
+                            if ((uint32_t)e < Et2) f |= 2u;
+                            else if ((uint32_t)e == Et2) tie2[k] = true;
+                        } else {
+                            if (D < D2lo) f |= 2u;
+                            else if (D < D2hi) tie2[k] = true;
+                        }
                     }
                 }
                 P.flag[i] = f;
             }
             cnt += tie[k] ? 1 : 0;
+            cnt2 += tie2[k] ? 1 : 0;
         }
         long long o = block_append_n(&c->out_count, cnt);
 #pragma unroll
@@ -749,6 +833,17 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
                 P.candz[0][o] = P.oZ[cur][i];
                 ++o;
             }
+        if (dual && !dual_all) {   // uniform
+            long long o2 = block_append_n(&c->out_count2, cnt2);
+#pragma unroll
+            for (int k = 0; k < kItems; ++k)
+                if (tie2[k]) {
+                    const long long i = base + threadIdx.x + (long long)k * blockDim.x;
+                    P.cand2[0][o2] = (int32_t)i;
+                    P.candz2[0][o2] = P.oZ[cur][i];
+                    ++o2;
+                }
+        }
     }
 }
 
@@ -784,9 +879,16 @@ __device__ __forceinline__ int first_diff(const Params& P, int cur, long long a,
 // from the first one, then partitions the candidates on that digit.
 constexpr int kTieLds = 2048;   // ties resolved on Zobrist bytes in LDS up to this count
 
-__global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
+// which = 0: the selection's own threshold (flag bit 0); which = 1: the dual cut's
+// second threshold, the next round's pivots (flag bit 1).
+__global__ __launch_bounds__(1024) void k_sel_keys(Params P, int which) {
     Ctl* c = P.ctl;
-    if (c->stop || !c->sel_enabled || c->sel_all) return;
+    if (c->stop || !c->sel_enabled) return;
+    if (which ? (!c->dual || c->dual_all) : c->sel_all) return;
+    int32_t* const* CA = which ? P.cand2 : P.cand;
+    unsigned long long* const* CZ = which ? P.candz2 : P.candz;
+    const uint32_t bit = which ? 2u : 1u;
+    const uint32_t prefix = which ? c->prefix2 : c->prefix;
     __shared__ uint32_t h[256];
     __shared__ int s_pos, s_v, s_m2;
     __shared__ long long s_r;
@@ -795,27 +897,29 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
     const int cur = c->which;
     const int t = threadIdx.x;
     const int npos = 8 + 4 * P.W;
-    int m = (int)c->out_count;
-    long long r = c->T - c->c_lt;
+    int m = (int)(which ? c->out_count2 : c->out_count);
+    long long r = which ? c->T2 - c->c_lt2 : c->T - c->c_lt;
     int src = 0;
     int pos = 0;
     // every thread reads the control block before thread 0 updates it below
-    const bool unres = !c->resolved;
+    const bool unres = which ? !c->resolved2 : !c->resolved;
     const int ls = c->hi_shift;
     __syncthreads();
     if (unres && (ls > kSubBits || r >= m)) {
         // the whole bin is taken (or its width is out of range: an error the host sees)
         if (t == 0) {
             if (ls > kSubBits) atomicExch(&c->error, 6);
-            c->Dt = ((c->prefix + 1u) << ls) - 1u;
-            c->resolved = 1;
+            if (!which) {
+                c->Dt = ((prefix + 1u) << ls) - 1u;
+                c->resolved = 1;
+            }
         }
         if (ls > kSubBits) return;
     } else if (unres && r > 0) {
         // The one radix level left a bin of 2^ls values of D: select its r smallest
         // values exactly (a histogram of D - Dlo in LDS, over the zs storage), keep
         // the entries below the threshold value, and go on with the tied ones.
-        const uint32_t Dlo = c->prefix << ls;
+        const uint32_t Dlo = prefix << ls;
         const uint32_t emin = c->emin;
         const int nsub = 1 << ls;
         uint32_t* hs = (uint32_t*)&zs[0][0];   // 2 * kTieLds * 8 bytes = 2^kSubBits counts
@@ -823,7 +927,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         if (t == 0) s_m2 = 0;
         __syncthreads();
         for (int q = t; q < m; q += blockDim.x)
-            atomicAdd(&hs[((uint32_t)P.oE[cur][P.cand[src][q]] - emin) / 4u - Dlo], 1u);
+            atomicAdd(&hs[((uint32_t)P.oE[cur][CA[src][q]] - emin) / 4u - Dlo], 1u);
         __syncthreads();
         if (t == 0) {
             long long cum = 0;
@@ -834,19 +938,21 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
             }
             s_v = v;
             s_r = r - cum;
-            c->Dt = Dlo + (uint32_t)v;   // the cut's energy, for the next round's bounds
-            c->resolved = 1;
+            if (!which) {
+                c->Dt = Dlo + (uint32_t)v;   // the cut's energy, for the next round's bounds
+                c->resolved = 1;
+            }
         }
         __syncthreads();
         const uint32_t Dv = Dlo + (uint32_t)s_v;
         for (int q = t; q < m; q += blockDim.x) {
-            const int idx = P.cand[src][q];
+            const int idx = CA[src][q];
             const uint32_t D = ((uint32_t)P.oE[cur][idx] - emin) / 4u;
-            if (D < Dv) P.flag[idx] = 1;
+            if (D < Dv) P.flag[idx] |= bit;
             else if (D == Dv) {
                 const int o2 = atomicAdd(&s_m2, 1);
-                P.cand[1 - src][o2] = idx;
-                P.candz[1 - src][o2] = P.candz[src][q];
+                CA[1 - src][o2] = idx;
+                CZ[1 - src][o2] = CZ[src][q];
             }
         }
         __syncthreads();
@@ -864,7 +970,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         if (t == 0) s_m2 = 0;
         __syncthreads();
         for (int q = t; q < m; q += blockDim.x)
-            atomicAdd(&h[(P.candz[src][q] >> sh) & 255ull], 1u);
+            atomicAdd(&h[(CZ[src][q] >> sh) & 255ull], 1u);
         __syncthreads();
         if (t < 64) {
             const uint32_t c0 = h[4 * t], c1 = h[4 * t + 1], c2 = h[4 * t + 2], c3 = h[4 * t + 3];
@@ -886,15 +992,15 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         __syncthreads();
         const int v = s_v;
         for (int q = t; q < m; q += blockDim.x) {
-            const int idx = P.cand[src][q];
-            const unsigned long long z = P.candz[src][q];
+            const int idx = CA[src][q];
+            const unsigned long long z = CZ[src][q];
             const int dgt = (int)((z >> sh) & 255ull);
             if (dgt < v) {
-                P.flag[idx] = 1;
+                P.flag[idx] |= bit;
             } else if (dgt == v) {
                 const int o2 = atomicAdd(&s_m2, 1);
-                P.cand[1 - src][o2] = idx;
-                P.candz[1 - src][o2] = z;
+                CA[1 - src][o2] = idx;
+                CZ[1 - src][o2] = z;
             }
         }
         __syncthreads();
@@ -908,8 +1014,8 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         // Fast path: the tied entries' keys in LDS, one byte of the key per pass.
         int b = 0;
         for (int q = t; q < m; q += blockDim.x) {
-            is[0][q] = P.cand[src][q];
-            zs[0][q] = P.candz[src][q];
+            is[0][q] = CA[src][q];
+            zs[0][q] = CZ[src][q];
         }
         __syncthreads();
         while (pos < 8 && r > 0 && r < m) {
@@ -953,7 +1059,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
             const int v = s_v;
             for (int q = t; q < m; q += blockDim.x) {
                 const int dgt = (int)((zs[b][q] >> sh) & 255ull);
-                if (dgt < v) P.flag[is[b][q]] = 1;
+                if (dgt < v) P.flag[is[b][q]] |= bit;
                 else if (dgt == v) {
                     const int o2 = atomicAdd(&s_m2, 1);
                     zs[1 - b][o2] = zs[b][q];
@@ -969,12 +1075,12 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         }
         if (pos < 8 || r <= 0 || r >= m) {
             if (r > 0)
-                for (int q = t; q < m; q += blockDim.x) P.flag[is[b][q]] = 1;
+                for (int q = t; q < m; q += blockDim.x) P.flag[is[b][q]] |= bit;
             return;
         }
         // the remaining m entries share their whole key: continue on the sequences
         __syncthreads();
-        for (int q = t; q < m; q += blockDim.x) P.cand[1 - src][q] = is[b][q];
+        for (int q = t; q < m; q += blockDim.x) CA[1 - src][q] = is[b][q];
         __syncthreads();
         src = 1 - src;
         pos = 8;
@@ -982,10 +1088,10 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
     while (pos < npos && r > 0 && r < m) {
         if (t == 0) s_pos = npos;
         __syncthreads();
-        const int ref_i = P.cand[src][0];
+        const int ref_i = CA[src][0];
         int first = npos;
         for (int q = t; q < m; q += blockDim.x) {
-            const int d = first_diff(P, cur, P.cand[src][q], ref_i, pos, npos);
+            const int d = first_diff(P, cur, CA[src][q], ref_i, pos, npos);
             first = d < first ? d : first;
         }
         first = __ockl_wfred_min_i32(first);
@@ -997,7 +1103,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         if (t == 0) s_m2 = 0;
         __syncthreads();
         for (int q = t; q < m; q += blockDim.x)
-            atomicAdd(&h[tie_digit(P, cur, P.cand[src][q], pos)], 1u);
+            atomicAdd(&h[tie_digit(P, cur, CA[src][q], pos)], 1u);
         __syncthreads();
         if (t == 0) {
             long long cum = 0;
@@ -1012,10 +1118,10 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         __syncthreads();
         const int v = s_v;
         for (int q = t; q < m; q += blockDim.x) {
-            const int idx = P.cand[src][q];
+            const int idx = CA[src][q];
             const int dgt = tie_digit(P, cur, idx, pos);
-            if (dgt < v) P.flag[idx] = 1;
-            else if (dgt == v) P.cand[1 - src][atomicAdd(&s_m2, 1)] = idx;
+            if (dgt < v) P.flag[idx] |= bit;
+            else if (dgt == v) CA[1 - src][atomicAdd(&s_m2, 1)] = idx;
         }
         __syncthreads();
         m = s_m2;
@@ -1025,7 +1131,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         __syncthreads();
     }
     if (r > 0)
-        for (int q = t; q < m; q += blockDim.x) P.flag[P.cand[src][q]] = 1;
+        for (int q = t; q < m; q += blockDim.x) P.flag[CA[src][q]] |= bit;
 }
 
 // ---------------------------------------------------------------- pop / expand
@@ -1042,6 +1148,8 @@ __global__ __launch_bounds__(kSelThreads) void k_pop(Params P) {
     }
     const int cur = c->which;
     const long long n_tot = c->n_tot;
+    // pivots preselected by the last cut sit at the survivors' positions in flagN
+    const uint32_t* fl = c->presel ? P.flagN : P.flag;
     const long long stride = (long long)gridDim.x * blockDim.x * kItems;
     for (long long base = (long long)blockIdx.x * blockDim.x * kItems; base < n_tot; base += stride) {
         bool take[kItems];
@@ -1049,7 +1157,7 @@ __global__ __launch_bounds__(kSelThreads) void k_pop(Params P) {
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const long long i = base + threadIdx.x + (long long)k * blockDim.x;
-            take[k] = i < n_tot && P.flag[i] && P.oE[cur][i] != DEAD;
+            take[k] = i < n_tot && (fl[i] & 1u) && P.oE[cur][i] != DEAD;
             cnt += take[k] ? 1 : 0;
         }
         long long o = block_append_n(&c->n_piv, cnt);
@@ -1515,13 +1623,9 @@ __global__ __launch_bounds__(1024) void k_round_mid(Params P) {
         else c->u += c->n_piv;
         // capacity cut setup; energy bounds: the live entries before the round
         // and this round's pushes
-        c->T = P.Q;
-        c->sel_enabled = c->n_live > P.Q ? 1 : 0;
-        c->sel_all = 0;
+        cut_setup(P);
         c->emin = (uint32_t)mn < c->blo ? (uint32_t)mn : c->blo;
         c->emax = (uint32_t)mx > c->bhi ? (uint32_t)mx : c->bhi;
-        c->survivors = 0;
-        c->out_count = 0;
         s_improved = c->improved;
     }
     __syncthreads();
@@ -1589,7 +1693,9 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
     const int cur = c->which;
-    const bool cut = c->sel_enabled;
+    const bool cut = !c->sel_all;           // entries are evicted
+    const bool dual = c->dual;
+    const bool dual_all = c->dual_all;
     const Table& H = P.H;
     const long long n_tot = c->n_tot, bb = c->batch_begin;
     long long claims = 0;
@@ -1604,7 +1710,7 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
             keep[k] = false;
             slot[k] = -1;
             if (i < n_tot && P.oE[cur][i] != DEAD) {
-                keep[k] = !cut || P.flag[i];
+                keep[k] = !cut || (P.flag[i] & 1u);
                 slot[k] = P.oS[cur][i];
                 if (slot[k] >= 0) {
                     if (!keep[k]) H.state[slot[k]] = ST_EVICTED;
@@ -1649,6 +1755,7 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
             P.oE[1 - cur][o] = P.oE[cur][i];
             P.oS[1 - cur][o] = slot[k];
             P.oZ[1 - cur][o] = P.oZ[cur][i];
+            if (dual) P.flagN[o] = dual_all ? 1u : (P.flag[i] >> 1) & 1u;
             ++o;
         }
     }
@@ -1658,7 +1765,7 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
 __device__ void round_end(const Params& P, int count_round) {
     Ctl* c = P.ctl;
     if (c->stop) return;
-    if (c->sel_enabled) {
+    if (!c->sel_all) {   // the cut evicted entries
         c->evictions += c->n_live - c->survivors;
         c->blo = c->emin;
         c->bhi = c->emin + (c->Dt << 2);   // survivors lie at or below the cut's energy
@@ -1760,13 +1867,9 @@ __global__ void k_seed_fin(Params P) {
     Ctl* c = P.ctl;
     c->n_live = c->n_tot;
     c->claimed = c->n_tot;
-    c->T = P.Q;
-    c->sel_enabled = c->n_live > P.Q ? 1 : 0;
-    c->sel_all = 0;
+    cut_setup(P);
     c->emin = UINT32_MAX;
     c->emax = 0;
-    c->survivors = 0;
-    c->out_count = 0;
 }
 
 // Before the initial best: the whole (cut) Open list is the "batch".
@@ -1858,6 +1961,9 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     t += align_up(sizeof(uint32_t) * lo.cap_o, 256);                   // flag
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // cand
     t += 2 * align_up(sizeof(unsigned long long) * lo.cap_o, 256);     // candz
+    t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // cand2
+    t += 2 * align_up(sizeof(unsigned long long) * lo.cap_o, 256);     // candz2
+    t += align_up(sizeof(uint32_t) * lo.cap_o, 256);                   // flagN
     t += align_up(sizeof(int32_t) * c.batch, 256);                     // piv
     t += align_up(sizeof(uint32_t) * kSelBins, 256);                   // select histogram
     t += align_up(sizeof(uint32_t) * 32, 256);                         // best sequence
@@ -1926,6 +2032,9 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.flag = cv.take<uint32_t>(lo.cap_o);
     for (int b = 0; b < 2; ++b) P.cand[b] = cv.take<int32_t>(lo.cap_o);
     for (int b = 0; b < 2; ++b) P.candz[b] = cv.take<unsigned long long>(lo.cap_o);
+    for (int b = 0; b < 2; ++b) P.cand2[b] = cv.take<int32_t>(lo.cap_o);
+    for (int b = 0; b < 2; ++b) P.candz2[b] = cv.take<unsigned long long>(lo.cap_o);
+    P.flagN = cv.take<uint32_t>(lo.cap_o);
     P.piv = cv.take<int32_t>(cfg.batch);
     P.ghist = cv.take<uint32_t>((size_t)kSelBins);
     P.best_seq = cv.take<uint32_t>(32);
@@ -1942,12 +2051,14 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     const dim3 gS(kGridBlocks), tS(kSelThreads);
     // Selection; rounds take their energy bounds from the control block instead
     // of a min/max pass.
-    auto select = [&](bool minmax) {
+    // dual: the round's cut, which may also select the next round's pivots
+    auto select = [&](bool minmax, bool dual) {
         if (minmax) hipLaunchKernelGGL(k_sel_minmax, dim3(kSelBlocks), tS, 0, st, P);
         hipLaunchKernelGGL(k_sel_hist, dim3(kSelBlocks), tS, 0, st, P);
         hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(1024), 0, st, P);
         hipLaunchKernelGGL(k_sel_classify, gS, tS, 0, st, P);
-        hipLaunchKernelGGL(k_sel_keys, dim3(1), dim3(1024), 0, st, P);
+        hipLaunchKernelGGL(k_sel_keys, dim3(1), dim3(1024), 0, st, P, 0);
+        if (dual) hipLaunchKernelGGL(k_sel_keys, dim3(1), dim3(1024), 0, st, P, 1);
     };
 
     // seeding: insert the candidates (exact dedupe), cut to Q, best = minimum
@@ -1956,7 +2067,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     hipLaunchKernelGGL(k_resolve, gS, tS, 0, st, P);
     hipLaunchKernelGGL(k_slow, dim3(1), dim3(1), 0, st, P);
     hipLaunchKernelGGL(k_seed_fin, dim3(1), dim3(1), 0, st, P);
-    select(true);
+    select(true, true);
     hipLaunchKernelGGL(k_keep, gS, tS, 0, st, P);
     hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, P, 0);
     hipLaunchKernelGGL(k_seed_best_setup, dim3(1), dim3(1), 0, st, P.ctl);
@@ -1973,7 +2084,6 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     // the end of the round together with the start of the next.
     hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, P);
     for (long long r = 0;; ++r) {
-        select(false);
         hipLaunchKernelGGL(k_pop, gS, tS, 0, st, P);
         {
             const unsigned nt = (unsigned)((cfg.batch + kRepTile - 1) / kRepTile);
@@ -1987,7 +2097,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
             hipLaunchKernelGGL(k_rot_stage, dim3((unsigned)cfg.batch), dim3(kRotThreads), 0, st, P);
         }
         hipLaunchKernelGGL(k_round_mid, dim3(1), dim3(1024), 0, st, P);
-        select(false);
+        select(false, true);
         hipLaunchKernelGGL(k_keep, gS, tS, 0, st, P);
         hipLaunchKernelGGL(k_round_next, dim3(1), dim3(1), 0, st, P);
         LABS_LAUNCHED("step2 round");
