@@ -878,6 +878,7 @@ __device__ __forceinline__ int first_diff(const Params& P, int cur, long long a,
 // pass, the first digit position (from `pos` on) at which any candidate differs
 // from the first one, then partitions the candidates on that digit.
 constexpr int kTieLds = 2048;   // ties resolved on Zobrist bytes in LDS up to this count
+constexpr int kTieU = 8;        // candidates loaded ahead per thread in the global passes
 
 // which = 0: the selection's own threshold (flag bit 0); which = 1: the dual cut's
 // second threshold, the next round's pivots (flag bit 1).
@@ -926,8 +927,17 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P, int which) {
         for (int k = t; k < nsub; k += blockDim.x) hs[k] = 0;
         if (t == 0) s_m2 = 0;
         __syncthreads();
-        for (int q = t; q < m; q += blockDim.x)
-            atomicAdd(&hs[((uint32_t)P.oE[cur][CA[src][q]] - emin) / 4u - Dlo], 1u);
+        for (int q0 = t; q0 < m; q0 += kTieU * blockDim.x) {
+            uint32_t e[kTieU];
+#pragma unroll
+            for (int u = 0; u < kTieU; ++u) {
+                const int q = q0 + u * blockDim.x;
+                e[u] = q < m ? (uint32_t)P.oE[cur][CA[src][q]] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kTieU; ++u)
+                if (q0 + u * blockDim.x < m) atomicAdd(&hs[(e[u] - emin) / 4u - Dlo], 1u);
+        }
         __syncthreads();
         if (t == 0) {
             long long cum = 0;
@@ -945,14 +955,26 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P, int which) {
         }
         __syncthreads();
         const uint32_t Dv = Dlo + (uint32_t)s_v;
-        for (int q = t; q < m; q += blockDim.x) {
-            const int idx = CA[src][q];
-            const uint32_t D = ((uint32_t)P.oE[cur][idx] - emin) / 4u;
-            if (D < Dv) P.flag[idx] |= bit;
-            else if (D == Dv) {
-                const int o2 = atomicAdd(&s_m2, 1);
-                CA[1 - src][o2] = idx;
-                CZ[1 - src][o2] = CZ[src][q];
+        for (int q0 = t; q0 < m; q0 += kTieU * blockDim.x) {
+            int idx[kTieU];
+            uint32_t e[kTieU];
+#pragma unroll
+            for (int u = 0; u < kTieU; ++u) {
+                const int q = q0 + u * blockDim.x;
+                idx[u] = q < m ? CA[src][q] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kTieU; ++u) e[u] = idx[u] >= 0 ? (uint32_t)P.oE[cur][idx[u]] : 0u;
+#pragma unroll
+            for (int u = 0; u < kTieU; ++u) {
+                if (idx[u] < 0) continue;
+                const uint32_t D = (e[u] - emin) / 4u;
+                if (D < Dv) atomicOr(&P.flag[idx[u]], bit);
+                else if (D == Dv) {
+                    const int o2 = atomicAdd(&s_m2, 1);
+                    CA[1 - src][o2] = idx[u];
+                    CZ[1 - src][o2] = CZ[src][q0 + u * blockDim.x];
+                }
             }
         }
         __syncthreads();
@@ -969,8 +991,17 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P, int which) {
         if (t < 256) h[t] = 0;
         if (t == 0) s_m2 = 0;
         __syncthreads();
-        for (int q = t; q < m; q += blockDim.x)
-            atomicAdd(&h[(CZ[src][q] >> sh) & 255ull], 1u);
+        for (int q0 = t; q0 < m; q0 += kTieU * blockDim.x) {
+            unsigned long long z[kTieU];
+#pragma unroll
+            for (int u = 0; u < kTieU; ++u) {
+                const int q = q0 + u * blockDim.x;
+                z[u] = q < m ? CZ[src][q] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < kTieU; ++u)
+                if (q0 + u * blockDim.x < m) atomicAdd(&h[(z[u] >> sh) & 255ull], 1u);
+        }
         __syncthreads();
         if (t < 64) {
             const uint32_t c0 = h[4 * t], c1 = h[4 * t + 1], c2 = h[4 * t + 2], c3 = h[4 * t + 3];
@@ -991,16 +1022,26 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P, int which) {
         }
         __syncthreads();
         const int v = s_v;
-        for (int q = t; q < m; q += blockDim.x) {
-            const int idx = CA[src][q];
-            const unsigned long long z = CZ[src][q];
-            const int dgt = (int)((z >> sh) & 255ull);
-            if (dgt < v) {
-                P.flag[idx] |= bit;
-            } else if (dgt == v) {
-                const int o2 = atomicAdd(&s_m2, 1);
-                CA[1 - src][o2] = idx;
-                CZ[1 - src][o2] = z;
+        for (int q0 = t; q0 < m; q0 += kTieU * blockDim.x) {
+            int idx[kTieU];
+            unsigned long long z[kTieU];
+#pragma unroll
+            for (int u = 0; u < kTieU; ++u) {
+                const int q = q0 + u * blockDim.x;
+                idx[u] = q < m ? CA[src][q] : -1;
+                z[u] = q < m ? CZ[src][q] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < kTieU; ++u) {
+                if (idx[u] < 0) continue;
+                const int dgt = (int)((z[u] >> sh) & 255ull);
+                if (dgt < v) {
+                    atomicOr(&P.flag[idx[u]], bit);
+                } else if (dgt == v) {
+                    const int o2 = atomicAdd(&s_m2, 1);
+                    CA[1 - src][o2] = idx[u];
+                    CZ[1 - src][o2] = z[u];
+                }
             }
         }
         __syncthreads();
@@ -1059,7 +1100,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P, int which) {
             const int v = s_v;
             for (int q = t; q < m; q += blockDim.x) {
                 const int dgt = (int)((zs[b][q] >> sh) & 255ull);
-                if (dgt < v) P.flag[is[b][q]] |= bit;
+                if (dgt < v) atomicOr(&P.flag[is[b][q]], bit);
                 else if (dgt == v) {
                     const int o2 = atomicAdd(&s_m2, 1);
                     zs[1 - b][o2] = zs[b][q];
@@ -1075,7 +1116,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P, int which) {
         }
         if (pos < 8 || r <= 0 || r >= m) {
             if (r > 0)
-                for (int q = t; q < m; q += blockDim.x) P.flag[is[b][q]] |= bit;
+                for (int q = t; q < m; q += blockDim.x) atomicOr(&P.flag[is[b][q]], bit);
             return;
         }
         // the remaining m entries share their whole key: continue on the sequences
@@ -1120,7 +1161,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P, int which) {
         for (int q = t; q < m; q += blockDim.x) {
             const int idx = CA[src][q];
             const int dgt = tie_digit(P, cur, idx, pos);
-            if (dgt < v) P.flag[idx] |= bit;
+            if (dgt < v) atomicOr(&P.flag[idx], bit);
             else if (dgt == v) CA[1 - src][atomicAdd(&s_m2, 1)] = idx;
         }
         __syncthreads();
@@ -1131,7 +1172,7 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P, int which) {
         __syncthreads();
     }
     if (r > 0)
-        for (int q = t; q < m; q += blockDim.x) P.flag[CA[src][q]] |= bit;
+        for (int q = t; q < m; q += blockDim.x) atomicOr(&P.flag[CA[src][q]], bit);
 }
 
 // ---------------------------------------------------------------- pop / expand
