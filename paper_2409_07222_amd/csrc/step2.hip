@@ -62,9 +62,9 @@ constexpr int kSelBits = 14;
 constexpr int kSubBits = 13;
 static_assert(kSelBits + kSubBits >= 27, "the sub-bins must cover (E - emin)/4 for L <= 1023");
 constexpr int kSelBins = 1 << kSelBits;
-constexpr int kSelBlocks = 128;
+constexpr int kSelBlocks = 256;
 constexpr int kSelThreads = 512;
-constexpr int kGridBlocks = 512;                     // grid-stride kernels over the Open list
+constexpr int kGridBlocks = 1024;                    // grid-stride kernels over the Open list
 constexpr int kMaxL = 1023;
 constexpr int kPad = 1024;
 constexpr int kSv = kMaxL + 2 * kPad + 2;
@@ -108,10 +108,10 @@ struct Ctl {
     long long out_count;
     uint32_t blo, bhi;     // bounds of the live Open energies (blo is one of them)
     // A cut that also selects the next round's T2 pivots (the T2 smallest of the
-    // survivors are the T2 smallest before the cut): their own threshold, carried
-    // to the survivors' new positions by the cut (flagN); presel: this round's
-    // pivots were selected so.
-    long long T2, c_lt2, out_count2;
+    // survivors are the T2 smallest before the cut): their own threshold; the cut
+    // lists their new positions (pivpos, n_pivpos); presel: this round's pivots
+    // were selected so.
+    long long T2, c_lt2, out_count2, n_pivpos;
     uint32_t Dt2, prefix2;
     int32_t resolved2, dual, presel, dual_all;   // dual_all: T2 takes every survivor
 };
@@ -136,7 +136,7 @@ struct Params {
     unsigned long long* candz[2];   // [cap_o] each: their Zobrist keys
     int32_t* cand2[2];     // the same for the next round's pivots (dual cut)
     unsigned long long* candz2[2];
-    uint32_t* flagN;       // [cap_o] next round's pivots at the survivors' positions
+    int32_t* pivpos;       // [B] Open positions of the next round's pivots (the cut)
     int32_t* piv;          // [B]
     uint32_t* ghist;       // [kSelBins], zero between selections
     uint32_t* best_seq;    // [W] copy of the best sequence
@@ -582,6 +582,7 @@ __device__ void cut_setup(const Params& P) {
     c->Dt2 = 0;
     c->prefix2 = 0;
     c->survivors = 0;
+    c->n_pivpos = 0;
     c->out_count = 0;
 }
 
@@ -595,7 +596,7 @@ __device__ void round_begin(const Params& P) {
     long long T = P.X - c->expansions;
     if (T > P.B) T = P.B;
     c->T = T;
-    // the last cut selected this round's T pivots (flagN at the survivors' positions)
+    // the last cut selected this round's T pivots and listed their positions
     c->presel = c->dual && c->T2 == T ? 1 : 0;
     c->dual = 0;
     c->sel_enabled = 0;
@@ -1187,35 +1188,21 @@ __global__ __launch_bounds__(kSelThreads) void k_pop(Params P) {
              i += (long long)gridDim.x * blockDim.x)
             rw[i] = 0u;
     }
+    // the last cut listed this round's pivots (round_begin stops the search when
+    // it did not)
     const int cur = c->which;
-    const long long n_tot = c->n_tot;
-    // pivots preselected by the last cut sit at the survivors' positions in flagN
-    const uint32_t* fl = c->presel ? P.flagN : P.flag;
-    const long long stride = (long long)gridDim.x * blockDim.x * kItems;
-    for (long long base = (long long)blockIdx.x * blockDim.x * kItems; base < n_tot; base += stride) {
-        bool take[kItems];
-        int cnt = 0;
-#pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            const long long i = base + threadIdx.x + (long long)k * blockDim.x;
-            take[k] = i < n_tot && (fl[i] & 1u) && P.oE[cur][i] != DEAD;
-            cnt += take[k] ? 1 : 0;
-        }
-        long long o = block_append_n(&c->n_piv, cnt);
-#pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            if (!take[k]) continue;
-            const long long i = base + threadIdx.x + (long long)k * blockDim.x;
-            if (o >= P.B) {
-                atomicExch(&c->error, 3);
-            } else {
-                const int slot = P.oS[cur][i];
-                P.piv[o] = slot;
-                P.oE[cur][i] = DEAD;
-                P.H.state[slot] = ST_CLOSED;
-            }
-            ++o;
-        }
+    const long long n = c->n_pivpos;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (n > P.B) atomicExch(&c->error, 3);
+        c->n_piv = n < P.B ? n : P.B;
+    }
+    for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < n && b < P.B;
+         b += (long long)gridDim.x * blockDim.x) {
+        const int i = P.pivpos[b];
+        const int slot = P.oS[cur][i];
+        P.piv[b] = slot;
+        P.oE[cur][i] = DEAD;
+        P.H.state[slot] = ST_CLOSED;
     }
 }
 
@@ -1788,7 +1775,17 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
             }
             cnt += keep[k] ? 1 : 0;
         }
+        // the next round's pivots: every survivor (dual_all) or those of flag bit 1
+        bool pv[kKeepItems];
+        int npv = 0;
+#pragma unroll
+        for (int k = 0; k < kKeepItems; ++k) {
+            const long long i = base + threadIdx.x + (long long)k * blockDim.x;
+            pv[k] = dual && keep[k] && (dual_all || ((P.flag[i] >> 1) & 1u));
+            npv += pv[k] ? 1 : 0;
+        }
         long long o = block_append_n(&c->survivors, cnt);
+        long long op = dual ? block_append_n(&c->n_pivpos, npv) : 0;   // dual is uniform
 #pragma unroll
         for (int k = 0; k < kKeepItems; ++k) {
             if (!keep[k]) continue;
@@ -1796,7 +1793,10 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
             P.oE[1 - cur][o] = P.oE[cur][i];
             P.oS[1 - cur][o] = slot[k];
             P.oZ[1 - cur][o] = P.oZ[cur][i];
-            if (dual) P.flagN[o] = dual_all ? 1u : (P.flag[i] >> 1) & 1u;
+            if (pv[k]) {
+                if (op < P.B) P.pivpos[op] = (int32_t)o;
+                ++op;
+            }
             ++o;
         }
     }
@@ -2004,7 +2004,7 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     t += 2 * align_up(sizeof(unsigned long long) * lo.cap_o, 256);     // candz
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // cand2
     t += 2 * align_up(sizeof(unsigned long long) * lo.cap_o, 256);     // candz2
-    t += align_up(sizeof(uint32_t) * lo.cap_o, 256);                   // flagN
+    t += align_up(sizeof(int32_t) * c.batch, 256);                     // pivpos
     t += align_up(sizeof(int32_t) * c.batch, 256);                     // piv
     t += align_up(sizeof(uint32_t) * kSelBins, 256);                   // select histogram
     t += align_up(sizeof(uint32_t) * 32, 256);                         // best sequence
@@ -2075,7 +2075,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     for (int b = 0; b < 2; ++b) P.candz[b] = cv.take<unsigned long long>(lo.cap_o);
     for (int b = 0; b < 2; ++b) P.cand2[b] = cv.take<int32_t>(lo.cap_o);
     for (int b = 0; b < 2; ++b) P.candz2[b] = cv.take<unsigned long long>(lo.cap_o);
-    P.flagN = cv.take<uint32_t>(lo.cap_o);
+    P.pivpos = cv.take<int32_t>(cfg.batch);
     P.piv = cv.take<int32_t>(cfg.batch);
     P.ghist = cv.take<uint32_t>((size_t)kSelBins);
     P.best_seq = cv.take<uint32_t>(32);
