@@ -150,7 +150,10 @@ struct Params {
     int32_t* bmin;         // [B] their least energy
     int32_t* bmax;         // [B] their greatest energy
     // [B*L] 1 when neighbour (b, i) repeats a neighbour of a lower-numbered pivot
+    // (the direct expansion only; the bit-sliced one finds its repeats itself)
     uint8_t* repeat;
+    int32_t direct;        // the direct expansion is in use
+    uint32_t* pseq;        // [B*W] packed sequences of the round's pivots
     // MAKE_ROTATIONS: rotation q of pivot b sits at Open position batch_begin +
     // n_piv*L + b*R2 + q (after every single flip of the round); q < Tr rotates
     // left by q+1, else right by q-Tr+1.
@@ -335,15 +338,15 @@ __device__ __forceinline__ void push_pending(const Params& P, bool take, const P
 // A generated neighbour (flip position `flip` of the block's pivot, slot ps;
 // energy En; Zobrist key): its Open position is fixed by (pivot, flip).  It is
 // DEAD when a lower-numbered pivot of the round produces the same sequence
-// (k_repeats) or when H holds its sequence as OPEN or CLOSED; otherwise it is a
+// (`repeated`) or when H holds its sequence as OPEN or CLOSED; otherwise it is a
 // new entry.  `taken`, `mn` and `mx` accumulate per thread.
-__device__ void stage_neighbour(const Params& P, bool valid, unsigned long long key, int ps, int flip,
-                                int32_t En, int& taken, int32_t& mn, int32_t& mx) {
+__device__ void stage_neighbour(const Params& P, bool valid, bool repeated, unsigned long long key, int ps,
+                                int flip, int32_t En, int& taken, int32_t& mn, int32_t& mx) {
     if (!valid) return;
     Ctl* c = P.ctl;
     const long long j = (long long)blockIdx.x * P.L + (flip - 1);
     int tomb = -1;
-    bool take = !P.repeat[j];
+    bool take = !repeated;
     if (take) {
         const Table& H = P.H;
         const uint8_t tg = tag_of(key);
@@ -519,6 +522,7 @@ __global__ void k_slow(Params P) {
 // (y equal to a pivot itself is a CLOSED entry of H).  Block b compares its pivot
 // with every lower-numbered pivot and marks its copies of the shared neighbours,
 // so of every repeated sequence exactly the copy of the lowest pivot is kept.
+// The direct expansion's repeat map (the bit-sliced one compares in its own block).
 constexpr int kRepTile = 64;
 
 __global__ __launch_bounds__(256) void k_repeats(Params P) {
@@ -1181,7 +1185,7 @@ __global__ __launch_bounds__(kSelThreads) void k_pop(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
     // this round's repeat map starts clear
-    {
+    if (P.direct) {
         uint32_t* rw = (uint32_t*)P.repeat;
         const long long nw = ((long long)P.B * P.L + 3) / 4;
         for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
@@ -1196,13 +1200,21 @@ __global__ __launch_bounds__(kSelThreads) void k_pop(Params P) {
         if (n > P.B) atomicExch(&c->error, 3);
         c->n_piv = n < P.B ? n : P.B;
     }
-    for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < n && b < P.B;
-         b += (long long)gridDim.x * blockDim.x) {
+    // one thread per (pivot, word) of the copied sequences
+    const int W = P.W;
+    const long long nb = n < P.B ? n : P.B;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nb * W;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long b = e / W;
+        const int w = (int)(e - b * W);
         const int i = P.pivpos[b];
         const int slot = P.oS[cur][i];
-        P.piv[b] = slot;
-        P.oE[cur][i] = DEAD;
-        P.H.state[slot] = ST_CLOSED;
+        P.pseq[e] = P.H.seq[(size_t)slot * W + w];
+        if (w == 0) {
+            P.piv[b] = slot;
+            P.oE[cur][i] = DEAD;
+            P.H.state[slot] = ST_CLOSED;
+        }
     }
 }
 
@@ -1250,7 +1262,8 @@ __global__ __launch_bounds__(64) void k_expand_direct(Params P) {
             En = Ep - 4 * si * g + 4 * q;
             key = (hp ^ zob(i - 1)) | 1ull;
         }
-        stage_neighbour(P, valid, key, ps, i, En, taken, mn, mx);
+        stage_neighbour(P, valid, valid && P.repeat[(long long)blockIdx.x * L + (i - 1)], key, ps, i, En,
+                        taken, mn, mx);
     }
     stage_finish(P, taken, mn, mx);
 }
@@ -1272,23 +1285,46 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
     __shared__ uint32_t V[NVW], VR[NVW], pk[32];
     __shared__ int32_t Cl[32 * NW2 + 1], PC[32 * NW2 + 1];
     __shared__ unsigned long long hpart[kExThreads / 64];
+    __shared__ uint8_t srep[32 * NW2 + 4];   // flip i repeats a lower-numbered pivot's neighbour
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int L = P.L, W = P.W;
     const int ps = P.piv[blockIdx.x];
     const int32_t Ep = P.H.E[ps];
+    const uint32_t* pw = P.pseq + (size_t)blockIdx.x * W;
     // V bit j = digit of s_{j+1} (LSB first): word w is the bit-reversed packed word;
     // VR (reversal over N = 32W bits): word W-1-w is the packed word itself.
     for (int w = tid; w < NVW; w += kExThreads) {
         uint32_t x = 0, y = 0;
         if (w < W) {
-            x = P.H.seq[(size_t)ps * W + w];
+            x = pw[w];
             pk[w] = x;
-            y = P.H.seq[(size_t)ps * W + (W - 1 - w)];
+            y = pw[W - 1 - w];
         }
         V[w] = __builtin_bitreverse32(x);
         VR[w] = y;
     }
+    for (int x = tid; x < 32 * NW2 + 4; x += kExThreads) srep[x] = 0;
     __syncthreads();
+    // In-round repeats: the neighbour p_b (+) e_i equals a neighbour of pivot q
+    // exactly when p_b and p_q are at Hamming distance 2 and i is one of the two
+    // positions where they differ (p_b (+) e_i = p_q (+) e_i' with i' the other).
+    // Of every repeated sequence the copy of the lowest-numbered pivot is kept, so
+    // pivot b compares itself with every q < b.
+    for (int q = tid; q < (int)blockIdx.x; q += kExThreads) {
+        const uint32_t* row = P.pseq + (size_t)q * W;
+        int d = 0;
+        for (int w = 0; w < W; ++w) d += __popc(row[w] ^ pk[w]);
+        if (d != 2) continue;
+        for (int w = 0; w < W; ++w) {
+            uint32_t x = row[w] ^ pk[w];
+            while (x) {
+                const int k = __clz((int)x);
+                const int pos = 32 * w + k + 1;   // 1-based position, MSB first
+                if (pos <= L) srep[pos - 1] = 1;
+                x &= ~(0x80000000u >> k);
+            }
+        }
+    }
     for (int d = 1 + tid; d <= 32 * NW2; d += kExThreads) {
         int cd = 0;
         if (d <= L - 1) {
@@ -1391,7 +1427,7 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
         const int Q = (L - 1) + 2 * (M - 2 * dis);
         const int32_t En = Ep - 4 * si * G + 4 * Q;
         const unsigned long long key = (hp ^ zob(i - 1)) | 1ull;
-        stage_neighbour(P, valid, key, ps, i, En, taken, mn, mx);
+        stage_neighbour(P, valid, srep[i - 1] != 0, key, ps, i, En, taken, mn, mx);
     }
     stage_finish(P, taken, mn, mx);
 }
@@ -1992,6 +2028,7 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     t += align_up(sizeof(int32_t) * lo.cap_new, 256);                  // ntomb
     t += 3 * align_up(sizeof(int32_t) * c.batch, 256);                 // bcnt, bmin, bmax
     t += align_up(lo.cap_new + 4, 256);                                // repeat
+    t += align_up(sizeof(uint32_t) * c.batch * words_of(c.L), 256);      // pseq
     t += align_up(sizeof(unsigned long long) * (2 * c.T_r * c.batch + 1), 256);   // rotation keys
     t += align_up(sizeof(int32_t) * (2 * c.T_r * c.batch + 1), 256);              // rotation energies
     t += align_up(sizeof(uint32_t) * c.batch, 256);                                // pivots' first words
@@ -2059,6 +2096,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.bmin = cv.take<int32_t>(cfg.batch);
     P.bmax = cv.take<int32_t>(cfg.batch);
     P.repeat = cv.take<uint8_t>(lo.cap_new + 4);
+    P.pseq = cv.take<uint32_t>((size_t)cfg.batch * P.W);
     P.Tr = cfg.T_r;
     P.R2 = 2 * cfg.T_r;
     P.rkey = cv.take<unsigned long long>((size_t)P.R2 * cfg.batch + 1);
@@ -2120,13 +2158,15 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     labs_status s;
     unsigned eth = 64;
     const expand_kernel_t ek = pick_expand(cfg.L, &eth);
-    // A round: pop selection, pop (also clears the repeat map), in-round
-    // repeats, expansion, counts / statistics / best, cut selection, cut, then
-    // the end of the round together with the start of the next.
+    P.direct = ek == k_expand_direct ? 1 : 0;
+    // A round: pop (also clears the direct expansion's repeat map), in-round
+    // repeats (the bit-sliced expansion finds its own), expansion, counts /
+    // statistics / best, cut selection, cut, then the end of the round together
+    // with the start of the next.
     hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, P);
     for (long long r = 0;; ++r) {
         hipLaunchKernelGGL(k_pop, gS, tS, 0, st, P);
-        {
+        if (P.direct) {
             const unsigned nt = (unsigned)((cfg.batch + kRepTile - 1) / kRepTile);
             hipLaunchKernelGGL(k_repeats, dim3(nt, nt), dim3(256), 0, st, P);
         }
