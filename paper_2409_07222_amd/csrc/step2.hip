@@ -69,6 +69,7 @@ constexpr int kMaxL = 1023;
 constexpr int kPad = 1024;
 constexpr int kSv = kMaxL + 2 * kPad + 2;
 constexpr int kExThreads = 256;
+constexpr int kExWaves = kExThreads / 64;
 constexpr int kItems = 8;                            // list entries per thread per pass (filters)
 constexpr int kKeepItems = 2;                        // the cut: fewer, so inserts overlap across threads
 
@@ -1376,7 +1377,7 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
     uint32_t F[R2][NW2], B[R2][NW2];
 #pragma unroll
     for (int r = 0; r < R2; ++r) {
-        int i = 1 + lane + 64 * (wv + 4 * r);
+        int i = 1 + lane + 64 * (wv + kExWaves * r);
         if (i > L) i = L;
         const int qf = i >> 5, hf = i & 31;
         const int sb = N - i + 1, qb = sb >> 5, hb = sb & 31;
@@ -1411,7 +1412,7 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
     int32_t mn = INT32_MAX, mx = 0;
 #pragma unroll
     for (int r = 0; r < R2; ++r) {
-        const int i0 = 1 + lane + 64 * (wv + 4 * r);
+        const int i0 = 1 + lane + 64 * (wv + kExWaves * r);
         const bool valid = i0 <= L;
         const int i = valid ? i0 : L;
         const int Mf = L - i, Mb = i - 1, M = Mf < Mb ? Mf : Mb;
