@@ -886,9 +886,11 @@ __device__ __forceinline__ int first_diff(const Params& P, int cur, long long a,
 constexpr int kTieLds = 2048;   // ties resolved on Zobrist bytes in LDS up to this count
 constexpr int kTieU = 8;        // candidates loaded ahead per thread in the global passes
 
-// which = 0: the selection's own threshold (flag bit 0); which = 1: the dual cut's
-// second threshold, the next round's pivots (flag bit 1).
-__global__ __launch_bounds__(1024) void k_sel_keys(Params P, int which) {
+// Block 0: the selection's own threshold (flag bit 0); block 1 (dual cuts): the
+// second threshold, the next round's pivots (flag bit 1).  The two blocks share no
+// state but the flag words, which they update by atomic ORs of different bits.
+__global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
+    const int which = blockIdx.x;
     Ctl* c = P.ctl;
     if (c->stop || !c->sel_enabled) return;
     if (which ? (!c->dual || c->dual_all) : c->sel_all) return;
@@ -2137,8 +2139,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
         hipLaunchKernelGGL(k_sel_hist, dim3(kSelBlocks), tS, 0, st, P);
         hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(1024), 0, st, P);
         hipLaunchKernelGGL(k_sel_classify, gS, tS, 0, st, P);
-        hipLaunchKernelGGL(k_sel_keys, dim3(1), dim3(1024), 0, st, P, 0);
-        if (dual) hipLaunchKernelGGL(k_sel_keys, dim3(1), dim3(1024), 0, st, P, 1);
+        hipLaunchKernelGGL(k_sel_keys, dim3(dual ? 2 : 1), dim3(1024), 0, st, P);
     };
 
     // seeding: insert the candidates (exact dedupe), cut to Q, best = minimum
