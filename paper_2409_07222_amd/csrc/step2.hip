@@ -28,9 +28,10 @@
 // only reads H (no writer runs beside it): a neighbour whose sequence H holds as
 // OPEN or CLOSED is a duplicate.  Two pivots of one round produce a common
 // neighbour exactly when they differ in two positions (each flips the other's
-// position), so the in-round repeats are found by comparing the pivots pairwise
-// (k_repeats, 64 x 64 tiles in LDS) before the expansion, which then skips the
-// second copy.  The capacity cut runs over old and new entries alike, and only
+// position), so the in-round repeats are found by comparing the pivots pairwise:
+// each expansion workgroup compares its pivot with the lower-numbered ones and
+// skips the copies they also produce (the direct expansion for long sequences
+// takes them from k_repeats, 64 x 64 tiles in LDS).  The capacity cut runs over old and new entries alike, and only
 // the new entries that survive it are written into H (the tombstone re-opened,
 // or an empty slot claimed by CAS).  Neighbours cut in their own round never
 // touch H, so H holds little more than Closed U Open and rarely needs a rebuild.
@@ -692,103 +693,105 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_hist(Params P) {
         if (h[b]) atomicAdd(&P.ghist[b], h[b]);
 }
 
-// The bin holding the T-th smallest entry: resolved when bins are single values
-// of D (ls = 0), else the bin [prefix << ls, (prefix + 1) << ls) is left to the
-// tie select.
-__global__ __launch_bounds__(1024) void k_sel_find(Params P) {
-    Ctl* c = P.ctl;
-    if (c->stop || !c->sel_enabled) return;
+// The cut from the histogram: the bin holding the T-th smallest entry (and, for a
+// dual cut, the T2-th).  A bin is resolved when bins are single values of D
+// (ls = 0); otherwise the bin [prefix << ls, (prefix + 1) << ls) is left to the tie
+// select.  Every workgroup of the classify pass computes it (the histogram is
+// read-only there); workgroup 0 stores it for the tie select and the cut.
+struct SelCut {
+    long long c_lt, c_lt2;
+    uint32_t prefix, prefix2, Dt, Dt2;
+    int32_t resolved, resolved2, hi_shift;
+};
+
+__device__ void find_cut(const Params& P, const Ctl* c, SelCut* out) {
+    __shared__ uint32_t part[kSelThreads];
     const int t = threadIdx.x;
-    if (c->emax == c->emin) {   // every live entry has one energy
-        if (t == 0) {
-            c->c_lt = 0;
-            c->resolved = 1;
-            c->Dt = 0;
-            c->c_lt2 = 0;
-            c->resolved2 = 1;
-            c->Dt2 = 0;
-        }
-        return;
+    if (t == 0) {
+        out->c_lt = 0;
+        out->c_lt2 = 0;
+        out->prefix = 0;
+        out->prefix2 = 0;
+        out->Dt = 0;
+        out->Dt2 = 0;
+        out->resolved = 1;
+        out->resolved2 = 1;
+        out->hi_shift = 0;
     }
-    constexpr int PER = kSelBins / 1024;
-    __shared__ uint32_t part[1024];
+    __syncthreads();
+    if (c->emax == c->emin) return;   // every live entry has one energy
     int hs, ls;
     digit_shifts(c, &hs, &ls);
-    uint32_t cnt[PER];
+    const int nb = 1 << (hs - ls);      // bins in use
+    const int per = (nb + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int b0 = t * per;
     uint32_t a = 0;
-    for (int k = 0; k < PER; ++k) {
-        cnt[k] = P.ghist[PER * t + k];
-        P.ghist[PER * t + k] = 0;   // the histogram is empty for the next selection
-        a += cnt[k];
-    }
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < nb) a += P.ghist[b0 + k];
     part[t] = a;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        uint32_t x = t >= o ? part[t - o] : 0;
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        const uint32_t x = t >= o ? part[t - o] : 0u;
         __syncthreads();
         part[t] += x;
         __syncthreads();
     }
-    const long long need = c->T;
-    long long before = (long long)part[t] - a;
-    if (!c->sel_all && before < need && need <= before + a) {
-        int v = PER * t;
-        for (int k = 0; k < PER; ++k) {
-            if (before + cnt[k] >= need) {
-                v = PER * t + k;
+    const long long first = (long long)part[t] - a;   // entries in the bins before this chunk
+    if (t == 0) out->hi_shift = ls;
+    // the chunk holding the need-th smallest entry finds its bin
+    auto locate = [&](long long need, long long* c_lt, uint32_t* prefix, uint32_t* Dt, int32_t* resolved) {
+        if (!(first < need && need <= first + a)) return;
+        long long before = first;
+        int v = b0;
+        for (int k = 0; k < per && b0 + k < nb; ++k) {
+            const uint32_t cnt = P.ghist[b0 + k];
+            if (before + cnt >= need) {
+                v = b0 + k;
                 break;
             }
-            before += cnt[k];
+            before += cnt;
         }
-        c->c_lt = before;
-        c->prefix = (uint32_t)v;
-        if (ls == 0) {
-            c->resolved = 1;
-            c->Dt = (uint32_t)v;
-        } else {
-            c->resolved = 0;
-        }
-        c->hi_shift = ls;
-    }
-    if (t == 0) c->hi_shift = ls;
-    if (c->dual && !c->dual_all) {   // the next round's pivots from the same histogram
-        const long long need2 = c->T2;
-        long long before2 = (long long)part[t] - a;
-        if (before2 < need2 && need2 <= before2 + a) {
-            int v = PER * t;
-            for (int k = 0; k < PER; ++k) {
-                if (before2 + cnt[k] >= need2) {
-                    v = PER * t + k;
-                    break;
-                }
-                before2 += cnt[k];
-            }
-            c->c_lt2 = before2;
-            c->prefix2 = (uint32_t)v;
-            c->resolved2 = ls == 0;
-            c->Dt2 = (uint32_t)v;
-        }
-    }
+        *c_lt = before;
+        *prefix = (uint32_t)v;
+        *Dt = (uint32_t)v;
+        *resolved = ls == 0 ? 1 : 0;
+    };
+    if (!c->sel_all) locate(c->T, &out->c_lt, &out->prefix, &out->Dt, &out->resolved);
+    if (c->dual && !c->dual_all) locate(c->T2, &out->c_lt2, &out->prefix2, &out->Dt2, &out->resolved2);
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
     Ctl* c = P.ctl;
     if (c->stop || !c->sel_enabled) return;
+    __shared__ SelCut cut;
+    find_cut(P, c, &cut);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c->c_lt = cut.c_lt;
+        c->prefix = cut.prefix;
+        c->Dt = cut.Dt;
+        c->resolved = cut.resolved;
+        c->hi_shift = cut.hi_shift;
+        c->c_lt2 = cut.c_lt2;
+        c->prefix2 = cut.prefix2;
+        c->Dt2 = cut.Dt2;
+        c->resolved2 = cut.resolved2;
+    }
     const int cur = c->which;
     const bool all = c->sel_all;
     // resolved: the threshold energy Et; otherwise the threshold bin [Dlo, Dhi) of D
-    const bool res = c->resolved;
-    const uint32_t Et = c->emin + (c->Dt << 2);
+    const bool res = cut.resolved;
+    const uint32_t Et = c->emin + (cut.Dt << 2);
     const uint32_t emin = c->emin;
-    const uint32_t Dlo = res ? 0u : c->prefix << c->hi_shift;
-    const uint32_t Dhi = res ? 0u : (c->prefix + 1u) << c->hi_shift;
+    const uint32_t Dlo = res ? 0u : cut.prefix << cut.hi_shift;
+    const uint32_t Dhi = res ? 0u : (cut.prefix + 1u) << cut.hi_shift;
     // the dual cut's second threshold (bit 1 of flag: the next round's pivots)
     const bool dual = c->dual;
     const bool dual_all = c->dual_all;
-    const bool res2 = c->resolved2;
-    const uint32_t Et2 = c->emin + (c->Dt2 << 2);
-    const uint32_t D2lo = c->prefix2 << c->hi_shift;
-    const uint32_t D2hi = (c->prefix2 + 1u) << c->hi_shift;
+    const bool res2 = cut.resolved2;
+    const uint32_t Et2 = c->emin + (cut.Dt2 << 2);
+    const uint32_t D2lo = cut.prefix2 << cut.hi_shift;
+    const uint32_t D2hi = (cut.prefix2 + 1u) << cut.hi_shift;
     const long long n_tot = c->n_tot;
     const long long stride = (long long)gridDim.x * blockDim.x * kItems;
     for (long long base = (long long)blockIdx.x * blockDim.x * kItems; base < n_tot; base += stride) {
@@ -1759,6 +1762,10 @@ __global__ __launch_bounds__(1024) void k_best(Params P, int initial) {
 __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
+    // the classify pass has read the select histogram: empty it for the next selection
+    for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < kSelBins;
+         b += (long long)gridDim.x * blockDim.x)
+        P.ghist[b] = 0u;
     const int cur = c->which;
     const bool cut = !c->sel_all;           // entries are evicted
     const bool dual = c->dual;
@@ -2137,7 +2144,6 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     auto select = [&](bool minmax, bool dual) {
         if (minmax) hipLaunchKernelGGL(k_sel_minmax, dim3(kSelBlocks), tS, 0, st, P);
         hipLaunchKernelGGL(k_sel_hist, dim3(kSelBlocks), tS, 0, st, P);
-        hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(1024), 0, st, P);
         hipLaunchKernelGGL(k_sel_classify, gS, tS, 0, st, P);
         hipLaunchKernelGGL(k_sel_keys, dim3(dual ? 2 : 1), dim3(1024), 0, st, P);
     };
