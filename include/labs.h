@@ -293,7 +293,8 @@ typedef struct {
     int64_t expansions;      /* pivots popped */
     int64_t pushes;          /* neighbours pushed (new or re-pushed after eviction) */
     int64_t dup_skips;       /* neighbours skipped as already present */
-    int64_t evictions;       /* entries cut by the capacity */
+    int64_t evictions;       /* entries cut by the capacity in the rounds (seeds beyond Q are
+                                not admitted, not evicted) */
     int64_t rounds;
     int64_t open_count;      /* Open entries at the end */
     int32_t best_E;

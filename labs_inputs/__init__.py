@@ -31,6 +31,14 @@ def random_pm1(seed: int, n: int, L: int) -> np.ndarray:
     return (g.integers(0, 2, size=(n, L), dtype=np.int8) * 2 - 1).astype(np.int8)
 
 
+def all_pm1_shuffled(seed: int, L: int) -> np.ndarray:
+    """Every +1/-1 sequence of length L (2^L of them), int8 [2^L, L], in a seeded
+    random order."""
+    idx = np.arange(1 << L, dtype=np.int64)
+    s = (1 - 2 * ((idx[:, None] >> np.arange(L)) & 1)).astype(np.int8)
+    return s[rng(seed).permutation(1 << L)]
+
+
 def skew_from_half(half: np.ndarray) -> np.ndarray:
     """Extend rows s_1..s_{k+1} to skew-symmetric rows of length 2k+1 (Eq. (2))."""
     h = np.asarray(half, dtype=np.int8)

@@ -1853,7 +1853,8 @@ __device__ void round_end(const Params& P, int count_round) {
     Ctl* c = P.ctl;
     if (c->stop) return;
     if (!c->sel_all) {   // the cut evicted entries
-        c->evictions += c->n_live - c->survivors;
+        // (the seeding cut admits the Q smallest candidates: no evictions)
+        if (count_round) c->evictions += c->n_live - c->survivors;
         c->blo = c->emin;
         c->bhi = c->emin + (c->Dt << 2);   // survivors lie at or below the cut's energy
     } else {

@@ -68,6 +68,18 @@ def test_step2_full_space(lb, orc):
     assert g["best_E"] == 13 and g["expansions"] == 1 << L
 
 
+def test_step2_large_tie_sets(lb, orc):
+    """Every sequence of length 18 as a seed: at this length many sequences share
+    each energy, so both of each cut's thresholds (the queue's 30,000th entry and
+    the 4,096th, the next round's pivots) fall inside tie sets of thousands of
+    entries, beyond what the tie select holds on chip; most neighbours re-push
+    evicted sequences (tombstones) or are duplicates."""
+    L = 18
+    cands = li.all_pm1_shuffled(3, L)
+    g, o = _run_both(lb, orc, L, cands, 4096, 30000, 2 * 4096, 1 << 40)
+    assert g["evictions"] > 50000 and g["pushes"] > 50000 and g["dup_skips"] > 50000
+
+
 def test_step2_duplicate_candidates(lb, orc):
     L = 21
     c = li.random_pm1(9, 4, L)
