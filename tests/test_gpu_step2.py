@@ -68,7 +68,8 @@ def test_step2_full_space(lb, orc):
     assert g["best_E"] == 13 and g["expansions"] == 1 << L
 
 
-def test_step2_large_tie_sets(lb, orc):
+@pytest.mark.parametrize("T_r", [0, 3])
+def test_step2_large_tie_sets(lb, orc, T_r):
     """Every sequence of length 18 as a seed: at this length many sequences share
     each energy, so both of each cut's thresholds (the queue's 30,000th entry and
     the 4,096th, the next round's pivots) fall inside tie sets of thousands of
@@ -76,8 +77,19 @@ def test_step2_large_tie_sets(lb, orc):
     evicted sequences (tombstones) or are duplicates."""
     L = 18
     cands = li.all_pm1_shuffled(3, L)
-    g, o = _run_both(lb, orc, L, cands, 4096, 30000, 2 * 4096, 1 << 40)
+    g, o = _run_both(lb, orc, L, cands, 4096, 30000, 2 * 4096, 1 << 40, T_r=T_r)
     assert g["evictions"] > 50000 and g["pushes"] > 50000 and g["dup_skips"] > 50000
+
+
+def test_step2_wide_range_large_bin(lb, orc):
+    """40,000 random seeds of length 301 and the all-ones sequence: the energy range
+    spans 2^22 values of (E - emin)/4, so the seeding cut's radix level leaves a bin
+    of 256 such values holding about 2,700 entries, which the tie select resolves
+    from device memory before the key bytes."""
+    L = 301
+    c = li.random_pm1(41, 40000, L)
+    cands = np.concatenate([c, np.ones((1, L), np.int8)])
+    _run_both(lb, orc, L, cands, 8, 10000, 32, 1 << 40)
 
 
 def test_step2_duplicate_candidates(lb, orc):
