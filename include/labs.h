@@ -273,6 +273,9 @@ labs_status labs_pool_topk(const labs_pool* pool, int32_t L, int32_t k, uint32_t
  *     batch = 1 this is Alg. 2's dynamic depth exactly);
  *   - cuts Open to the pq_capacity smallest (evicted sequences are forgotten
  *     and may be pushed again later).
+ * Alg. 2's queue has no capacity: that is the case pq_capacity >= n_cand +
+ * max_expansions (L + 2 T_r), where no cut ever evicts (Open cannot outgrow it),
+ * so a sequence is pushed at most once.
  * Results do not depend on scheduling.  The call synchronises `stream`.
  * Memory: the workspace holds two hash tables of next_pow2(4 x (n_cand +
  * max_expansions + pq_capacity + 9 batch (L + 2 T_r))) slots of 16 + 4W bytes

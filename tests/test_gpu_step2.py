@@ -92,6 +92,17 @@ def test_step2_wide_range_large_bin(lb, orc):
     _run_both(lb, orc, L, cands, 8, 10000, 32, 1 << 40)
 
 
+@pytest.mark.parametrize("T_r", [0, 2])
+def test_step2_unbounded_queue(lb, orc, T_r):
+    """A queue no cut reaches (Alg. 2's, without capacity): nothing is evicted and
+    Open and Closed hold exactly the distinct seeds and the pushes."""
+    L, B, X = 23, 8, 200
+    cands = li.random_pm1(12, 5, L)
+    g, o = _run_both(lb, orc, L, cands, B, 5 + X * (L + 2 * T_r), X, 1 << 40, T_r=T_r)
+    assert g["evictions"] == 0 and g["expansions"] == X
+    assert g["open_count"] + g["expansions"] == 5 + g["pushes"]
+
+
 def test_step2_duplicate_candidates(lb, orc):
     L = 21
     c = li.random_pm1(9, 4, L)

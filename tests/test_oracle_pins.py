@@ -475,6 +475,20 @@ def test_step2_capacity_eviction(orc):
     assert len(r["open_keys"]) <= 50
 
 
+@pytest.mark.parametrize("T_r", [0, 2])
+def test_step2_unbounded_queue(orc, T_r):
+    """Alg. 2's queue has no capacity: with Q >= seeds + X (L + 2 T_r) no cut ever
+    evicts, every pushed sequence is new to Open and Closed, and the two sets hold
+    exactly the distinct seeds and the pushes (Closed = the expansions)."""
+    L, B, X = 23, 8, 200
+    c = li.random_pm1(12, 5, L)
+    seeds = len({orc.seq_key(s) for s in c})
+    r = orc.step2(L, list(c), B, seeds + X * (L + 2 * T_r), X, 1 << 40, T_r=T_r)
+    assert r["evictions"] == 0 and r["expansions"] == X
+    assert len(r["open_keys"]) + r["expansions"] == seeds + r["pushes"]
+    assert len({k for _, k in r["open_keys"]}) == len(r["open_keys"])
+
+
 def test_zobrist_keys(orc):
     """Zobrist keys: XOR of SplitMix64 outputs over the +1 positions (low bit
     forced to 1), so one flip changes the key by exactly that position's output
