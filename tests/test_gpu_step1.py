@@ -181,6 +181,21 @@ def test_pool_sieve_cfg2_shape(lb, orc):
             assert (int(gw[i]), int(gt[i])) == first[key]
 
 
+def test_pool_topk_edges(lb, orc):
+    """k beyond the pool's distinct sequences returns all of them, in order; an
+    empty pool returns none."""
+    L, p, steps, n = 63, 4, 200, 40
+    pool = lb.PoolBuffers.empty(L, 1000)
+    lb.walk_step1(L, p, steps, 4, 9, 11, n, e_max=-1, pool=pool, pool_walker_best=True)
+    o = orc.walk(L, p, steps, 4, 9, 11, range(n))
+    ref, _ = orc.pool([(int(o["best_E"][j]), o["best"][j]) for j in range(n)], 1000)
+    s, E = lb.pool_topk(pool, len(ref) + 25)
+    assert [int(e) for e in E.cpu().numpy()] == [e for e, _ in ref]
+    assert [orc.seq_key(x) for x in _host_seqs(s, L)] == [k for _, k in ref]
+    s, E = lb.pool_topk(lb.PoolBuffers.empty(L, 16), 4)
+    assert len(E) == 0 and len(s) == 0
+
+
 def test_pool_topk_and_walker_best(lb, orc):
     L, p, steps, n = 63, 4, 200, 40
     pool = lb.PoolBuffers.empty(L, 1000)

@@ -48,6 +48,8 @@ def _run_both(lb, orc, L, cands, B, Q, X, T_u, T_r=0):
     (200, 2, 32, 500, 400, 1 << 40),
     (701, 2, 4, 200, 16, 1 << 40),         # direct expansion (lags beyond the bit-sliced kernels)
     (1023, 2, 2, 100, 8, 1 << 40),         # longest accepted length
+    (17, 4, 8, 2, 60, 1 << 40),            # queue smaller than the batch: every survivor is popped
+    (19, 6, 16, 5, 100, 1 << 40),
 ])
 def test_step2_parity(lb, orc, L, n, B, Q, X, T_u):
     cands = li.random_pm1(L * 7 + n, n, L)
