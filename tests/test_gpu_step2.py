@@ -50,6 +50,8 @@ def _run_both(lb, orc, L, cands, B, Q, X, T_u, T_r=0):
     (1023, 2, 2, 100, 8, 1 << 40),         # longest accepted length
     (17, 4, 8, 2, 60, 1 << 40),            # queue smaller than the batch: every survivor is popped
     (19, 6, 16, 5, 100, 1 << 40),
+    (2, 3, 2, 8, 10, 1 << 40),             # the shortest lengths: every energy ties, the
+    (3, 4, 2, 3, 12, 1 << 40),             # space is exhausted and Open ends empty
 ])
 def test_step2_parity(lb, orc, L, n, B, Q, X, T_u):
     cands = li.random_pm1(L * 7 + n, n, L)
@@ -129,6 +131,8 @@ def test_step2_zero_budget(lb, orc):
     (200, 2, 32, 500, 400, 1 << 40, 32),       # the largest T_r
     (701, 2, 4, 200, 16, 1 << 40, 4),          # direct expansion
     (1023, 2, 2, 100, 8, 1 << 40, 32),
+    (5, 5, 3, 6, 40, 1 << 40, 1),              # exhausted space with rotations
+    (6, 4, 2, 5, 30, 1 << 40, 2),              # even length, 2 T_r = L - 2
 ])
 def test_step2_rotations_parity(lb, orc, L, n, B, Q, X, T_u, T_r):
     cands = li.random_pm1(L * 11 + n, n, L)
