@@ -31,10 +31,18 @@
 // position), so the in-round repeats are found by comparing the pivots pairwise:
 // each expansion workgroup compares its pivot with the lower-numbered ones and
 // skips the copies they also produce (the direct expansion for long sequences
-// takes them from k_repeats, 64 x 64 tiles in LDS).  The capacity cut runs over old and new entries alike, and only
-// the new entries that survive it are written into H (the tombstone re-opened,
-// or an empty slot claimed by CAS).  Neighbours cut in their own round never
-// touch H, so H holds little more than Closed U Open and rarely needs a rebuild.
+// takes them from k_repeats, 64 x 64 tiles in LDS).  The capacity cut runs over
+// old and new entries alike, and only the new entries that survive it are
+// written into H (the tombstone re-opened, or an empty slot claimed by CAS).
+// Neighbours cut in their own round never touch H, so H holds little more than
+// Closed U Open and rarely needs a rebuild.
+//
+// A round's launches: k_pop (the pivots the last cut listed become CLOSED and
+// their words are copied), k_expand (repeats, then the single flips), the
+// rotation kernels when T_r > 0, k_round_mid (counts, best, cut setup),
+// k_sel_hist (radix level), k_sel_classify (threshold bins, flags, tie lists),
+// k_sel_keys (the two tie selects), k_keep (the cut; lists the next pivots),
+// k_round_next (end of this round, start of the next).
 // The seeding insertions are exact and use no fences: a candidate walks its
 // probe sequence with 64-bit CAS on the key word; an empty slot is claimed, a
 // slot already holding its key makes the candidate "pending".  After the kernel
