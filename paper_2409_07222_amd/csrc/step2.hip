@@ -681,10 +681,11 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_hist(Params P) {
     if (c->stop || !c->sel_enabled) return;
     if (c->emax == c->emin) return;
     __shared__ uint32_t h[kSelBins];
-    for (int b = threadIdx.x; b < kSelBins; b += blockDim.x) h[b] = 0;
-    __syncthreads();
     int hs, ls;
     digit_shifts(c, &hs, &ls);
+    const int nbins = 1 << (hs - ls);   // bins in use
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) h[b] = 0;
+    __syncthreads();
     const int cur = c->which;
     const uint32_t emin = c->emin;
     const uint32_t dmask = (1u << (hs - ls)) - 1u;
@@ -697,7 +698,7 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_hist(Params P) {
         atomicAdd(&h[(D >> ls) & dmask], 1u);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < kSelBins; b += blockDim.x)
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x)
         if (h[b]) atomicAdd(&P.ghist[b], h[b]);
 }
 
