@@ -714,7 +714,7 @@ struct SelCut {
 };
 
 __device__ void find_cut(const Params& P, const Ctl* c, SelCut* out) {
-    __shared__ uint32_t part[kSelThreads];
+    __shared__ uint32_t part[kSelThreads / 64];
     const int t = threadIdx.x;
     if (t == 0) {
         out->c_lt = 0;
@@ -737,15 +737,19 @@ __device__ void find_cut(const Params& P, const Ctl* c, SelCut* out) {
     uint32_t a = 0;
     for (int k = 0; k < per; ++k)
         if (b0 + k < nb) a += P.ghist[b0 + k];
-    part[t] = a;
-    __syncthreads();
-    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-        const uint32_t x = t >= o ? part[t - o] : 0u;
-        __syncthreads();
-        part[t] += x;
-        __syncthreads();
+    // exclusive prefix of the chunk sums: within the wave by shuffles, then the
+    // totals of the lower waves
+    const int lane = t & 63, wv = t >> 6;
+    uint32_t incl = a;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
     }
-    const long long first = (long long)part[t] - a;   // entries in the bins before this chunk
+    if (lane == 63) part[wv] = incl;
+    __syncthreads();
+    uint32_t below = 0;
+    for (int k = 0; k < wv; ++k) below += part[k];
+    const long long first = (long long)below + incl - a;   // entries in the bins before this chunk
     if (t == 0) out->hi_shift = ls;
     // the chunk holding the need-th smallest entry finds its bin
     auto locate = [&](long long need, long long* c_lt, uint32_t* prefix, uint32_t* Dt, int32_t* resolved) {
