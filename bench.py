@@ -561,8 +561,8 @@ def main():
         copy_calibration(a.copy_calibration)
         return
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(walkers shard across GPUs by walker-id range; only the one-GPU path is built)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(walkers would shard across GPUs by walker-id range)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2409_07222_amd import labs

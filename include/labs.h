@@ -55,7 +55,7 @@ enum {
     LABS_E_INVALID = -1,     /* bad argument; nothing enqueued */
     LABS_E_DEVICE = -2,      /* HIP runtime or launch failure */
     LABS_E_NOMEM = -3,       /* workspace too small */
-    LABS_E_UNSUPPORTED = -4  /* valid request outside what this build implements */
+    LABS_E_UNSUPPORTED = -4  /* valid request outside what the library implements */
 };
 
 int32_t labs_abi_version(void);
