@@ -53,8 +53,9 @@ def parse():
     ap.add_argument("--s2-batch", type=int, default=1024)
     ap.add_argument("--s2-capacity", type=int, default=1 << 20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
-                    help="host threads of the CPU baseline (the box's CPU share for one GPU is 16)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the CPU baseline (0: OMP_NUM_THREADS, else every core "
+                         "this process may use)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline-pass", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
@@ -136,30 +137,63 @@ def walk_valu_utilisation():
     return float(v) if v is not None else None
 
 
+def host_threads():
+    """Threads the CPU baseline runs on: the OpenMP thread count the host sets
+    (OMP_NUM_THREADS, the CPU share of one GPU on a shared box), else every core
+    this process may run on."""
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return min(int(env), avail) if env.isdigit() and int(env) > 0 else avail
+
+
 def cpu_baseline(budget_s: float, threads: int):
-    """The oracle's first-step walker (definitional energies) on a bounded sample of
-    the same walk: `threads` independent walkers at L = 501, p = 16 (walker ids
-    0..threads-1), one per host thread; the oracle's C walker runs outside the
-    interpreter lock, so the threads run in parallel."""
-    from concurrent.futures import ThreadPoolExecutor
+    """CPU baseline of the first step: the oracle's linear-time tabu walker
+    (oracle/labs_baseline.c: Sec. 3's O(L) neighbour evaluation, one walker per
+    OpenMP thread, gcc -O3 -march=native for this host) on a bounded sample of
+    the benchmark's walk (L = 501, p = 16, tenure [50, 100], seed 4): 4 walkers per
+    thread, steps sized to about `budget_s` seconds.  Beside it, the definitional
+    oracle walker (O(L^2) per neighbour) on one core, for reference."""
     import oracle
-    oracle.lib()
     k = (L - 1) // 2
     nf = k + 1 - P
     lo, hi = L // 10, L // 5
     t0 = time.perf_counter()
-    oracle.walk(L, P, 4, lo, hi, 4, [0], want_traj=False)
-    per_step = (time.perf_counter() - t0) / 4
-    steps = max(4, int(budget_s / max(per_step, 1e-6)))
+    oracle.baseline_lib(native=True)
+    t_build = time.perf_counter() - t0
+    n = 4 * threads
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(threads) as ex:
-        list(ex.map(lambda w: oracle.walk(L, P, steps, lo, hi, 4, [w], want_traj=False), range(threads)))
+    probe = oracle.baseline_walk(L, P, 64, lo, hi, 4, 0, n, threads=threads, native=True)
+    per_step = (time.perf_counter() - t0) / 64
+    steps = max(64, int(budget_s / max(per_step, 1e-9)))
+    t0 = time.perf_counter()
+    r = oracle.baseline_walk(L, P, steps, lo, hi, 4, 0, n, threads=threads, native=True)
     dt = time.perf_counter() - t0
-    n = threads * steps * nf
-    return {"value": n / dt, "unit": "flip-evals/s", "cores": threads, "kind": "oracle",
-            "sample": "%d walkers (one per thread) x %d steps of the L=501 p=16 first-step walk "
-                      "(%d flip-evals, %.1f s), definitional energy per neighbour"
-                      % (threads, steps, n, dt)}
+    # the definitional walker, one core, a few steps
+    t0 = time.perf_counter()
+    oracle.walk(L, P, 8, lo, hi, 4, [0], want_traj=False)
+    t_def = time.perf_counter() - t0
+    import platform
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": r["flip_evals"] / dt, "unit": "flip-evals/s", "cores": r["threads"],
+            "kind": "oracle",
+            "method": "linear-time tabu walker (Sec. 3), plain C, gcc -O3 -march=native -fopenmp, "
+                      "one walker per thread",
+            "sample": "%d walkers (%d per thread) x %d steps of the L=501 p=16 first-step walk "
+                      "(%d flip-evals in %.1f s)" % (n, n // max(1, r["threads"]), steps,
+                                                     r["flip_evals"], dt),
+            "host": {"cpu_model": model, "os_cpu_count": os.cpu_count(),
+                     "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                     else None, "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS"),
+                     "machine": platform.machine()},
+            "native_build_s": t_build,
+            "definitional_oracle_one_core": {"value": 8 * nf / t_def, "unit": "flip-evals/s",
+                                             "sample": "1 walker x 8 steps, energy of every "
+                                                       "neighbour from the definition"}}
 
 
 def step1_configs(a, labs, dev):
@@ -681,7 +715,7 @@ def main():
         s2_ws = None
         torch.cuda.empty_cache()
         ab = learned_ab(a, labs, dev)
-    cpu = None if a.no_cpu_baseline else cpu_baseline(a.cpu_seconds, a.cpu_threads)
+    cpu = None if a.no_cpu_baseline else cpu_baseline(a.cpu_seconds, a.cpu_threads or host_threads())
     value = evals / dt
     line = {
         "metric": METRIC, "value": value, "unit": "flip-evals/s", "n_gpus": 1,

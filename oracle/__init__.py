@@ -11,6 +11,10 @@ Layers:
     a tabu tenure, and with its Bloom filter), exhaustive enumeration,
     SplitMix64.  Every energy change is
     recomputed from the definition of E; no incremental formula is used.
+  * ``labs_baseline.c`` (built to ``liblabs_baseline.so`` with gcc -O3 and
+    OpenMP): the CPU baseline of the first step, the tabu walker with the
+    linear-time neighbour evaluation of Sec. 3, one walker per thread.  The
+    benchmark times it; a test pins its trajectories to the definitional walker.
   * this module: ctypes bindings, the candidate pool (set semantics, kept in
     (E, key) order), and the second step (Algorithm 2) as a batch-synchronous
     best-first search over Python sets and dicts.
@@ -50,7 +54,68 @@ def build(force: bool = True) -> str:
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-Wall",
                            "-o", tmp, _SRC])
     os.replace(tmp, _LIB_PATH)
+    build_baseline(native=False)
     return _LIB_PATH
+
+
+_BL_SRC = os.path.join(_HERE, "labs_baseline.c")
+_BL_PATH = os.path.join(_HERE, "liblabs_baseline.so")
+_bl_libs = {}
+
+
+def build_baseline(native: bool = False) -> str:
+    """Compile labs_baseline.c with gcc -O3 -fopenmp.  native=False: a portable
+    x86-64-v2 build in-tree (what the tests load); native=True: -march=native
+    for the host that runs it, into a temporary directory (the benchmark's CPU
+    baseline is timed with this one)."""
+    import tempfile
+    if native:
+        path = os.path.join(tempfile.mkdtemp(prefix="labs_baseline_"), "liblabs_baseline_native.so")
+        arch = "-march=native"
+    else:
+        path = _BL_PATH
+        arch = "-march=x86-64-v2"
+    tmp = path + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O3", arch, "-fopenmp", "-std=c99", "-shared", "-fPIC", "-Wall",
+                           "-o", tmp, _BL_SRC])
+    os.replace(tmp, path)
+    return path
+
+
+def baseline_lib(native: bool = False):
+    with _lock:
+        if native not in _bl_libs:
+            if native:
+                path = build_baseline(native=True)
+            else:
+                path = _BL_PATH
+                if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_BL_SRC):
+                    build_baseline(native=False)
+            L = ctypes.CDLL(path)
+            L.bl_walk.restype = ctypes.c_int32
+            L.bl_walk.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                  ctypes.c_int32, _i32p, _i32p, _i32p, _i64p]
+            _bl_libs[native] = L
+        return _bl_libs[native]
+
+
+def baseline_walk(L: int, p: int, steps: int, tenure_lo: int, tenure_hi: int, seed: int,
+                  walker_begin: int, n: int, threads: int = 0, want_traj: bool = False,
+                  native: bool = False) -> dict:
+    """The CPU baseline walker (labs_baseline.c) over walkers walker_begin..+n-1 on
+    `threads` OpenMP threads (0: the runtime default).  Returns final and best
+    energies, the trajectories when asked, flip-evals and the threads used."""
+    lb = baseline_lib(native)
+    traj = np.zeros((n, steps), dtype=np.int32) if want_traj else None
+    fin = np.zeros(n, dtype=np.int32)
+    best = np.zeros(n, dtype=np.int32)
+    fe = ctypes.c_int64(0)
+    used = lb.bl_walk(L, p, steps, tenure_lo, tenure_hi, seed, walker_begin, n, threads,
+                      _p(traj, _i32p) if want_traj else None, _p(fin, _i32p), _p(best, _i32p),
+                      ctypes.byref(fe))
+    return {"traj": traj, "final_E": fin, "best_E": best, "flip_evals": int(fe.value),
+            "threads": int(used)}
 
 
 def lib():
