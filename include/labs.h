@@ -133,12 +133,13 @@ typedef struct {
  * it, the pool holds the min(capacity, D) smallest, in key order, of the D
  * distinct sequences in (its previous contents) U (this call's offers), sorted
  * ascending; `walker`/`step` of an entry are those of its earliest offer in
- * (walker, step) order.  Overflow is not an error: *dropped grows by the number
- * of distinct sequences that reached the pool and were cut by the capacity.
- * Once the pool is full a walker no longer hands over a sequence whose energy
- * is above the pool's largest (it could not enter), so such sequences are not
- * counted: *dropped is a lower bound on the distinct offers the pool lacks, and
- * exact while the pool is not full. */
+ * (walker, step) order.  Overflow is not an error: *dropped grows by D minus
+ * the entries kept, the number of distinct sequences the capacity cut (a
+ * sequence offered again after it was cut counts once).  The library keeps the
+ * cut sequences of the call in a set inside the workspace, exact for up to
+ * capacity + staging (>= capacity + 65536) distinct cut sequences per call;
+ * beyond that the call completes the walk and the pool but returns
+ * LABS_E_NOMEM, since *dropped is then not exact. */
 typedef struct {
     uint32_t* seqs;     /* [capacity*W] */
     int32_t* E;         /* [capacity] */

@@ -192,6 +192,7 @@ WalkLayout walk_layout(const labs_step1_cfg& c, int64_t pool_cap, bool pool,
         total += align_up(sizeof(uint32_t) * lo.KW * (lo.S + lo.cap), 256);   // records
         total += 512;                                                         // counters
         total += compact_workspace_bytes(lo.S + lo.cap, lo.KW);
+        total += cutset_bytes(cutset_slots(lo.cap, lo.S), W);
     }
     lo.total = total + 4096;
     return lo;
@@ -352,7 +353,6 @@ labs_status walk_single(const labs_step1_cfg& c, const labs_bloom* bloom, labs_p
     A.bestSeq = (uint32_t*)(base + lo.off_bS);
     A.traj = o.traj_E;
     A.e_max = c.e_max;
-    A.thr = nullptr;
     if (bloom) {
         A.tabu = nullptr;
         A.zh = (uint64_t*)(base + lo.off_zh);
@@ -390,17 +390,14 @@ labs_status walk_single(const labs_step1_cfg& c, const labs_bloom* bloom, labs_p
     rb.stride = lo.S + lo.cap;
     rb.rec = cv.take<uint32_t>((size_t)rb.KW * rb.stride);
     uint32_t* st_count = cv.take<uint32_t>(16);
-    int32_t* thr = (int32_t*)(st_count + 8);
     const size_t cws_bytes = compact_workspace_bytes(lo.S + lo.cap, lo.KW);
     void* cws = cv.take<char>(cws_bytes);
+    const CutSet cut = cutset_carve(cv, cutset_slots(lo.cap, lo.S), W);
     if (!cv.ok()) return invalid("workspace layout overflow");
-    A.thr = thr;
     A.rec = rb.rec;
     A.rec_stride = rb.stride;
     A.st_count = st_count;
     A.st_cap = (uint32_t)lo.S;
-    const int32_t e_max_eff = c.e_max >= 0 ? c.e_max : INT32_MAX;
-
     HostPair hp{};
     auto read_counts = [&]() -> labs_status {
         LABS_HIP(hipMemcpyAsync(&hp.st_count, st_count, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -408,13 +405,14 @@ labs_status walk_single(const labs_step1_cfg& c, const labs_bloom* bloom, labs_p
         LABS_HIP(hipStreamSynchronize(st));
         return LABS_OK;
     };
-    // initial compaction: normalise the pool's previous contents, set the threshold
+    // initial compaction: normalise the pool's previous contents
     LABS_HIP(hipMemsetAsync(st_count, 0, 64, st));
+    if ((s = cutset_clear(cut, st)) != LABS_OK) return s;
     if ((s = read_counts()) != LABS_OK) return s;
     if (hp.pool_count < 0 || hp.pool_count > pl.capacity) return invalid("pool count out of range");
     if ((s = pool_to_rec(pl, hp.pool_count, W, rb, 0, st)) != LABS_OK) return s;
     if ((s = compact_records(rb, W, hp.pool_count, pl.capacity, pl.seqs, pl.E, pl.walker, pl.step,
-                             pl.count, pl.dropped, nullptr, thr, e_max_eff, cws, cws_bytes, st)) != LABS_OK)
+                             pl.count, pl.dropped, nullptr, &cut, cws, cws_bytes, st)) != LABS_OK)
         return s;
 
     int seg = kSegPool0;
@@ -437,7 +435,7 @@ labs_status walk_single(const labs_step1_cfg& c, const labs_bloom* bloom, labs_p
         const int64_t nst = hp.st_count;
         if ((s = pool_to_rec(pl, hp.pool_count, W, rb, nst, st)) != LABS_OK) return s;
         if ((s = compact_records(rb, W, nst + hp.pool_count, pl.capacity, pl.seqs, pl.E, pl.walker,
-                                 pl.step, pl.count, pl.dropped, nullptr, thr, e_max_eff, cws, cws_bytes,
+                                 pl.step, pl.count, pl.dropped, nullptr, &cut, cws, cws_bytes,
                                  st)) != LABS_OK)
             return s;
         t += len;
@@ -457,12 +455,21 @@ labs_status walk_single(const labs_step1_cfg& c, const labs_bloom* bloom, labs_p
         const int64_t nst = hp.st_count;
         if ((s = pool_to_rec(pl, hp.pool_count, W, rb, nst, st)) != LABS_OK) return s;
         if ((s = compact_records(rb, W, nst + hp.pool_count, pl.capacity, pl.seqs, pl.E, pl.walker,
-                                 pl.step, pl.count, pl.dropped, nullptr, thr, e_max_eff, cws, cws_bytes,
+                                 pl.step, pl.count, pl.dropped, nullptr, &cut, cws, cws_bytes,
                                  st)) != LABS_OK)
             return s;
     }
     A.t1 = steps;
     if ((s = launch_walk_outputs(A, o, st)) != LABS_OK) return s;
+    uint32_t cut_status[2] = {0, 0};
+    LABS_HIP(hipMemcpyAsync(cut_status, cut.status, sizeof cut_status, hipMemcpyDeviceToHost, st));
+    LABS_HIP(hipStreamSynchronize(st));
+    if (cut_status[0]) {
+        set_error("more than %lld distinct sequences were cut from the pool in one call: the pool "
+                  "is complete but its dropped count is not exact",
+                  (long long)(cut.slots >> 1));
+        return LABS_E_NOMEM;
+    }
     return tw.flush();
 }
 
@@ -698,7 +705,7 @@ labs_status labs_pool_topk(const labs_pool* pool, int32_t L, int32_t k, uint32_t
     if (!cv.ok()) return invalid("workspace layout overflow");
     if ((s = pool_to_rec(*pool, n, W, rb, 0, st)) != LABS_OK) return s;
     return compact_records(rb, W, n, k, out_seqs, out_E, nullptr, nullptr, nullptr, nullptr, out_n, nullptr,
-                           INT32_MAX, cws, cws_bytes, st);
+                           cws, cws_bytes, st);
 }
 
 }  // extern "C"

@@ -97,11 +97,33 @@ struct RecBuf {
     int32_t KW;
 };
 
+// The distinct sequences a pool's capacity cut within one call (the pool's
+// `dropped` count): an open-addressing set of packed sequences, a non-zero
+// 64-bit hash per slot (0 = empty) and the sequence's words beside it.
+// status[0] is set when an insert found the set too full, status[1] counts
+// the entries.
+struct CutSet {
+    uint64_t* keys;      // [slots]
+    uint32_t* words;     // [slots * W]
+    uint32_t* status;    // [2]
+    int64_t slots;       // power of two
+};
+// Slots for a pool of capacity `cap` fed by staging batches of up to `staged`
+// records: one batch always fits while the set is at most half full.
+int64_t cutset_slots(int64_t cap, int64_t staged);
+size_t cutset_bytes(int64_t slots, int32_t W);
+CutSet cutset_carve(Carve& cv, int64_t slots, int32_t W);
+labs_status cutset_clear(const CutSet& cs, hipStream_t st);
+
 size_t sort_workspace_bytes(int64_t nmax, int32_t KW);
 size_t compact_workspace_bytes(int64_t nmax, int32_t KW);
+// Sort records [0, n) of rb, keep the first min(cap, D) distinct sequences in the
+// output arrays and set count / out_n.  With `cut`, every distinct sequence beyond
+// the capacity that the set does not hold yet is added to it and counted in
+// *dropped (so a sequence cut in several compactions of one call counts once).
 labs_status compact_records(const RecBuf& rb, int32_t W, int64_t n, int64_t cap, uint32_t* out_seqs,
                             int32_t* out_E, int64_t* out_walker, int32_t* out_step, int64_t* count,
-                            int64_t* dropped, int64_t* out_n, int32_t* thr, int32_t e_max, void* ws,
+                            int64_t* dropped, int64_t* out_n, const CutSet* cut, void* ws,
                             size_t ws_bytes, hipStream_t st);
 labs_status pool_to_rec(const labs_pool& pool, int64_t n, int32_t W, const RecBuf& rb, int64_t off,
                         hipStream_t st);
@@ -123,7 +145,6 @@ struct WalkArgs {
     uint32_t* bestSeq;  // [n*W]
     int32_t* traj;      // [n*steps_total] or null
     int32_t e_max;      // < 0: sieve off
-    const int32_t* thr; // device scalar: current pool threshold (E <= thr may enter)
     uint32_t* rec;      // staging records, word-major
     int64_t rec_stride;
     uint32_t* st_count;

@@ -9,8 +9,6 @@
 // found up front and skipped.
 #include "labs_internal.h"
 
-#include <vector>
-
 namespace labsdev {
 
 namespace {
@@ -19,6 +17,7 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kRounds = 32;                              // rounds of 64 items per wave
 constexpr int kTile = kThreads * kRounds;                // 8192 items per block
+constexpr int kMaxKeyWords = 40;                         // W + 3 <= 35 for L <= 1023
 
 __global__ void k_iota(uint32_t* p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -194,16 +193,93 @@ __global__ void k_gather_unique(const uint32_t* rec, int64_t stride, int W, cons
     if (out_step) out_step[o] = (int32_t)rec[(W + 2) * stride + a];
 }
 
+// dropped (when not null) grows by the distinct sequences beyond the capacity;
+// with a cut set the set's inserts count them instead.
 __global__ void k_finish_counts(const uint32_t* distinct, int64_t cap, int64_t* count,
-                                int64_t* dropped, int64_t* out_n, const int32_t* E_sorted,
-                                int32_t* thr, int32_t e_max) {
+                                int64_t* dropped, int64_t* out_n) {
     if (threadIdx.x || blockIdx.x) return;
     const int64_t D = *distinct;
     const int64_t keep = D < cap ? D : cap;
     if (count) *count = keep;
     if (dropped) *dropped += D - keep;
     if (out_n) *out_n = keep;
-    if (thr) *thr = (keep == cap && keep > 0) ? min(E_sorted[keep - 1], e_max) : e_max;
+}
+
+// ---------------------------------------------------------------- cut set
+// Hash of record a's sequence words (a SplitMix64 finaliser chain), never 0.
+__device__ __forceinline__ uint64_t rec_seq_hash(const uint32_t* rec, int64_t stride, int W, uint32_t a) {
+    uint64_t h = 0x243F6A8885A308D3ull;
+    for (int q = 1; q <= W; ++q) h = sm64_mix(h ^ ((uint64_t)rec[q * stride + a] << 16) ^ (uint64_t)q);
+    return h | 1ull;
+}
+
+// Sorted record i is a candidate when it starts a run of equal sequences
+// (flag[i] = 1) at a position beyond the capacity.  Candidates the set already
+// holds (from an earlier compaction of the call) are cleared in flag; the set
+// is not written here, so every comparison sees whole entries.
+__global__ void k_cut_lookup(const uint32_t* rec, int64_t stride, int W, const uint32_t* perm,
+                             uint32_t* flag, const uint32_t* pos, int64_t n, int64_t cap, CutSet cs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    if ((int64_t)pos[i] < cap) {
+        flag[i] = 0;
+        return;
+    }
+    if (cs.status[1] > (uint32_t)(cs.slots >> 1)) {
+        // more than half full before this batch: the count cannot stay exact
+        flag[i] = 0;
+        atomicOr(&cs.status[0], 1u);
+        return;
+    }
+    const uint32_t a = perm[i];
+    const uint64_t key = rec_seq_hash(rec, stride, W, a);
+    const uint64_t mask = (uint64_t)cs.slots - 1;
+    uint64_t slot = key & mask;
+    for (int64_t probe = 0; probe < cs.slots; ++probe, slot = (slot + 1) & mask) {
+        const uint64_t k = cs.keys[slot];
+        if (k == 0) return;                               // absent: stays a candidate
+        if (k != key) continue;
+        const uint32_t* w = cs.words + slot * (uint64_t)W;
+        bool eq = true;
+        for (int q = 0; q < W && eq; ++q) eq = w[q] == rec[(q + 1) * stride + a];
+        if (eq) {
+            flag[i] = 0;                                  // cut earlier in this call
+            return;
+        }
+    }
+}
+
+// Inserts the remaining candidates.  They are distinct sequences that the set
+// does not hold, so a claimed slot is never compared: an insert takes the first
+// empty slot it wins.  Each insert adds one to *dropped.  The set was at most
+// half full before the batch and a batch holds at most half its slots, so
+// every insert finds a slot.
+__global__ void k_cut_insert(const uint32_t* rec, int64_t stride, int W, const uint32_t* perm,
+                             const uint32_t* flag, int64_t n, CutSet cs, int64_t* dropped) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool added = false;
+    if (i < n && flag[i]) {
+        const uint32_t a = perm[i];
+        const uint64_t key = rec_seq_hash(rec, stride, W, a);
+        const uint64_t mask = (uint64_t)cs.slots - 1;
+        uint64_t slot = key & mask;
+        for (int64_t probe = 0; probe < cs.slots; ++probe, slot = (slot + 1) & mask) {
+            if (cs.keys[slot] != 0) continue;
+            if (atomicCAS((unsigned long long*)&cs.keys[slot], 0ull, (unsigned long long)key) != 0ull)
+                continue;
+            uint32_t* w = cs.words + slot * (uint64_t)W;
+            for (int q = 0; q < W; ++q) w[q] = rec[(q + 1) * stride + a];
+            added = true;
+            break;
+        }
+        if (!added) atomicOr(&cs.status[0], 1u);
+    }
+    const uint64_t b = __ballot(added);
+    if ((threadIdx.x & 63) == 0 && b) {
+        const int c = __popcll(b);
+        atomicAdd((unsigned long long*)dropped, (unsigned long long)c);
+        atomicAdd(&cs.status[1], (uint32_t)c);
+    }
 }
 
 // Copy a pool's records into a RecBuf at offset `off`.
@@ -233,6 +309,7 @@ size_t sort_workspace_bytes(int64_t nmax, int32_t KW) {
 
 labs_status radix_sort_records(const RecBuf& rb, int64_t n, int32_t nkeys, void* ws, size_t ws_bytes,
                                uint32_t** perm_out, hipStream_t st) {
+    if (rb.KW < 1 || rb.KW > kMaxKeyWords || nkeys > rb.KW) return invalid("record key words out of range");
     Carve cv(ws, ws_bytes);
     const int64_t nblk = (n + kTile - 1) / kTile;
     uint32_t* p0 = cv.take<uint32_t>((size_t)n);
@@ -247,8 +324,8 @@ labs_status radix_sort_records(const RecBuf& rb, int64_t n, int32_t nkeys, void*
     hipLaunchKernelGGL(k_varying, dim3(blocks_for(n, 256) < 1024u ? blocks_for(n, 256) : 1024u), dim3(256), 0, st,
                        rb.rec, rb.stride, n, rb.KW, var);
     LABS_LAUNCHED("k_varying");
-    std::vector<uint32_t> hv(rb.KW);
-    LABS_HIP(hipMemcpyAsync(hv.data(), var, sizeof(uint32_t) * rb.KW, hipMemcpyDeviceToHost, st));
+    uint32_t hv[kMaxKeyWords];   // host copy of the varying bits (no heap: used by the no-allocation top-k)
+    LABS_HIP(hipMemcpyAsync(hv, var, sizeof(uint32_t) * rb.KW, hipMemcpyDeviceToHost, st));
     LABS_HIP(hipStreamSynchronize(st));
     uint32_t* in = p0;
     uint32_t* out = p1;
@@ -281,11 +358,35 @@ size_t compact_workspace_bytes(int64_t nmax, int32_t KW) {
     return b;
 }
 
-// Sort records [0, n) of rb, keep the first min(cap, D) distinct sequences and
-// write them to the output arrays; update count/dropped/out_n/thr on device.
+int64_t cutset_slots(int64_t cap, int64_t staged) {
+    int64_t s = 1 << 12;
+    while (s < 2 * (cap + staged)) s <<= 1;
+    return s;
+}
+
+size_t cutset_bytes(int64_t slots, int32_t W) {
+    return align_up(sizeof(uint64_t) * (size_t)slots, 256) +
+           align_up(sizeof(uint32_t) * (size_t)slots * (size_t)W, 256) + 256 + 256;
+}
+
+CutSet cutset_carve(Carve& cv, int64_t slots, int32_t W) {
+    CutSet cs;
+    cs.keys = cv.take<uint64_t>((size_t)slots);
+    cs.words = cv.take<uint32_t>((size_t)slots * (size_t)W);
+    cs.status = cv.take<uint32_t>(2);
+    cs.slots = slots;
+    return cs;
+}
+
+labs_status cutset_clear(const CutSet& cs, hipStream_t st) {
+    LABS_HIP(hipMemsetAsync(cs.keys, 0, sizeof(uint64_t) * (size_t)cs.slots, st));
+    LABS_HIP(hipMemsetAsync(cs.status, 0, sizeof(uint32_t) * 2, st));
+    return LABS_OK;
+}
+
 labs_status compact_records(const RecBuf& rb, int32_t W, int64_t n, int64_t cap, uint32_t* out_seqs,
                             int32_t* out_E, int64_t* out_walker, int32_t* out_step, int64_t* count,
-                            int64_t* dropped, int64_t* out_n, int32_t* thr, int32_t e_max, void* ws,
+                            int64_t* dropped, int64_t* out_n, const CutSet* cut, void* ws,
                             size_t ws_bytes, hipStream_t st) {
     Carve cv(ws, ws_bytes);
     const size_t sort_bytes = sort_workspace_bytes(n > 0 ? n : 1, rb.KW);
@@ -310,9 +411,16 @@ labs_status compact_records(const RecBuf& rb, int32_t W, int64_t n, int64_t cap,
         hipLaunchKernelGGL(k_gather_unique, dim3(blocks_for(n, 256)), dim3(256), 0, st, rb.rec, rb.stride,
                            W, perm, flag, pos, n, cap, out_seqs, out_E, out_walker, out_step);
         LABS_LAUNCHED("pool compaction");
+        if (cut && dropped && n > cap) {
+            hipLaunchKernelGGL(k_cut_lookup, dim3(blocks_for(n, 256)), dim3(256), 0, st, rb.rec, rb.stride,
+                               W, perm, flag, pos, n, cap, *cut);
+            hipLaunchKernelGGL(k_cut_insert, dim3(blocks_for(n, 256)), dim3(256), 0, st, rb.rec, rb.stride,
+                               W, perm, flag, n, *cut, dropped);
+            LABS_LAUNCHED("cut set");
+        }
     }
-    hipLaunchKernelGGL(k_finish_counts, dim3(1), dim3(64), 0, st, total, cap, count, dropped, out_n,
-                       out_E, thr, e_max);
+    hipLaunchKernelGGL(k_finish_counts, dim3(1), dim3(64), 0, st, total, cap, count,
+                       cut ? nullptr : dropped, out_n);
     LABS_LAUNCHED("k_finish_counts");
     return LABS_OK;
 }

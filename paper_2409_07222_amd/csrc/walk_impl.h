@@ -195,8 +195,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
     int bestT = A.bestT[j];
     const int tenure = A.tenure[j];
     const bool sieve = A.e_max >= 0;
-    int thr = A.e_max;
-    if (sieve && A.thr) thr = min(thr, *A.thr);
+    const int thr = A.e_max;
     const int64_t wid = A.walker_begin + j;
     __syncthreads();
 

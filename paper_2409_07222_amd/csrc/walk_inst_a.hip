@@ -13,17 +13,30 @@ void fill(WalkKernels* o) {
     o->RB = RB;
 }
 
-// R in {ceil(NW/2), ceil(NW/2)+1}; RB in {R, ceil(R/2)}.
+template <int NW, int R>
+void fill_rb(int RB, WalkKernels* o) {
+    constexpr int H = (R + 1) / 2;
+    if (RB < R) fill<NW, R, H>(o); else fill<NW, R, R>(o);
+}
+
+// Slot groups R (64 free positions each) in {ceil(NW/2) - 1, ceil(NW/2),
+// ceil(NW/2) + 1}: with k in (32(NW-1), 32NW] and the prefixes in use these hold
+// R = ceil((k+1-p)/64) exactly, so no group of 64 slots is scanned for nothing;
+// a smaller R (a long prefix) runs in the smallest group count.  RB in {R, ceil(R/2)}.
 template <int NW>
 bool pick(int R, int RB, WalkKernels* o) {
-    constexpr int R0 = (NW + 1) / 2, R1 = R0 + 1;
-    constexpr int H0 = (R0 + 1) / 2, H1 = (R1 + 1) / 2;
-    if (R <= R0) {
-        if (RB < R0) fill<NW, R0, H0>(o); else fill<NW, R0, R0>(o);
+    constexpr int R0 = (NW + 1) / 2;
+    constexpr int Rm = R0 > 1 ? R0 - 1 : 1;
+    if (R <= Rm) {
+        fill_rb<NW, Rm>(RB, o);
         return true;
     }
-    if (R == R1) {
-        if (RB < R1) fill<NW, R1, H1>(o); else fill<NW, R1, R1>(o);
+    if (R == R0) {
+        fill_rb<NW, R0>(RB, o);
+        return true;
+    }
+    if (R == R0 + 1) {
+        fill_rb<NW, R0 + 1>(RB, o);
         return true;
     }
     return false;

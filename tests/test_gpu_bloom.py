@@ -98,10 +98,7 @@ def test_bloom_pool_sieve(lb, orc):
         ref, dropped = orc.pool(o["emits"], cap)
         cnt = int(pool.count.item())
         assert len(ref) >= 20 and cnt == len(ref)
-        # sequences above a full pool's largest energy are not handed over, so
-        # the device count is a lower bound, exact while nothing is cut
-        got_dropped = int(pool.dropped.item())
-        assert got_dropped <= dropped and (dropped > 0 or got_dropped == 0)
+        assert int(pool.dropped.item()) == dropped
         assert [int(e) for e in pool.E[:cnt].cpu().numpy()] == [e for e, _ in ref]
         assert [orc.seq_key(s) for s in _host_seqs(pool.seqs[:cnt], L)] == [k for _, k in ref]
 

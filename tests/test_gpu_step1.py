@@ -105,6 +105,10 @@ def test_walk_cfg1_trajectories(lb, orc):
     (101, 8, 600, 10, 20, 12),    # the second configuration's shape
     (131, 1, 400, 13, 26, 4),     # k = 65: two chunks of 64 lags, 65 free positions
     (301, 12, 60, 30, 60, 2),     # third configuration's range
+    (301, 120, 40, 3, 6, 2),      # long prefix: 31 free positions in the smallest slot group
+    (385, 12, 30, 38, 77, 2),     # k = 192: six even-lag words, three slot groups
+    (387, 12, 30, 38, 77, 2),     # k = 193: one lag into a seventh word, still three groups
+    (527, 16, 20, 52, 105, 2),    # k = 263: nine words, four slot groups
 ])
 def test_walk_shapes(lb, orc, L, p, steps, lo, hi, n):
     _compare_walk(lb, orc, L, p, steps, lo, hi, 7 + L, n)
@@ -161,10 +165,7 @@ def test_pool_sieve_cfg2_shape(lb, orc):
         cnt = int(pool.count.item())
         assert len(ref) >= 20
         assert cnt == len(ref)
-        # sequences above a full pool's largest energy are not handed over, so
-        # the device count is a lower bound, exact while nothing is cut
-        got_dropped = int(pool.dropped.item())
-        assert got_dropped <= dropped and (dropped > 0 or got_dropped == 0)
+        assert int(pool.dropped.item()) == dropped
         got_E = pool.E[:cnt].cpu().numpy()
         got_S = _host_seqs(pool.seqs[:cnt], L)
         assert [int(e) for e in got_E] == [e for e, _ in ref]
@@ -179,6 +180,33 @@ def test_pool_sieve_cfg2_shape(lb, orc):
         gt = pool.step[:cnt].cpu().numpy()
         for i, (_, key) in enumerate(ref):
             assert (int(gw[i]), int(gt[i])) == first[key]
+
+
+def test_pool_dropped_repeats_across_segments(lb, orc):
+    """At L = 21 the walkers revisit sequences often, so the same sequence is
+    offered in several compaction segments (the pool path starts with 256-step
+    segments) and is cut each time the capacity is reached: `dropped` counts it
+    once.  A second call on the same pool counts the distinct sequences of (its
+    previous contents) U (the new offers) beyond the capacity."""
+    L, p, steps, n, cap = 21, 0, 3000, 48, 30
+    em = orc.e_max_for_tau(L, 3, 1)
+    pool = lb.PoolBuffers.empty(L, cap)
+    lb.walk_step1(L, p, steps, 1, 3, 7, n, e_max=em, pool=pool)
+    o = orc.walk(L, p, steps, 1, 3, 7, range(n), e_max=em, want_traj=False)
+    ref, dropped = orc.pool(o["emits"], cap)
+    assert len(o["emits"]) > 2 * (len(ref) + dropped)      # the case has many repeats
+    assert dropped > 0
+    cnt = int(pool.count.item())
+    assert cnt == cap
+    assert int(pool.dropped.item()) == dropped
+    assert [orc.seq_key(s) for s in _host_seqs(pool.seqs[:cnt], L)] == [k for _, k in ref]
+    # a second call adds to the same pool
+    lb.walk_step1(L, p, 700, 1, 3, 8, n, e_max=em, pool=pool)
+    o2 = orc.walk(L, p, 700, 1, 3, 8, range(n), e_max=em, want_traj=False)
+    prev = [(E, orc.key_seq(k, L)) for E, k in ref]
+    ref2, dropped2 = orc.pool(prev + o2["emits"], cap)
+    assert int(pool.dropped.item()) == dropped + dropped2
+    assert [orc.seq_key(s) for s in _host_seqs(pool.seqs[:cap], L)] == [k for _, k in ref2]
 
 
 def test_pool_topk_edges(lb, orc):
