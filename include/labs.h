@@ -247,6 +247,20 @@ labs_status labs_pool_topk(const labs_pool* pool, int32_t L, int32_t k, uint32_t
                            int32_t* out_E, int64_t* out_n, void* ws, size_t ws_bytes,
                            void* stream);
 
+/* labs_pool_topk_noalloc -- labs_pool_topk for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, results and ordering, without the
+ * workspace: the sort's scratch is a fixed 64 MiB device array inside the
+ * library, one per GPU, held until the process ends.  A pool whose count needs
+ * more scratch than that (about 700,000 entries at L = 501) is rejected with
+ * LABS_E_INVALID before any launch.  Calls on one GPU share that array, so calls
+ * that overlap in time on one GPU (several streams or host threads) race; the
+ * library keeps no state between calls in it.  Allocates nothing; synchronises
+ * `stream` (it reads pool->count).
+ */
+labs_status labs_pool_topk_noalloc(const labs_pool* pool, int32_t L, int32_t k, uint32_t* out_seqs,
+                                   int32_t* out_E, int64_t* out_n, void* stream);
+
 /* ----------------------------------------------------------------------------
  * Second step (Alg. 2) as a batch-synchronous best-first search.
  *

@@ -148,6 +148,8 @@ def lib():
             L.labs_pool_topk_workspace.argtypes = [i64, i32, ctypes.POINTER(sz)]
             L.labs_pool_topk.restype = i32
             L.labs_pool_topk.argtypes = [ctypes.POINTER(Pool), i32, i32, vp, vp, vp, vp, sz, vp]
+            L.labs_pool_topk_noalloc.restype = i32
+            L.labs_pool_topk_noalloc.argtypes = [ctypes.POINTER(Pool), i32, i32, vp, vp, vp, vp]
             L.labs_refine_step2_workspace.restype = i32
             L.labs_refine_step2_workspace.argtypes = [ctypes.POINTER(Step2Cfg), i64,
                                                       ctypes.POINTER(sz)]
@@ -321,6 +323,22 @@ def pool_topk(pool: PoolBuffers, k: int):
     ps = pool.struct()
     _check(lib().labs_pool_topk(ctypes.byref(ps), pool.L, k, _ptr(out_s), _ptr(out_E), _ptr(out_n),
                                 _ptr(ws), ws.numel(), _stream(dev)))
+    n = int(out_n.item())
+    return out_s[:n], out_E[:n]
+
+
+def pool_topk_noalloc(pool: PoolBuffers, k: int):
+    """labs_pool_topk_noalloc: as pool_topk, with the library's fixed scratch
+    array in place of a workspace (only the outputs are allocated here)."""
+    torch = _torch()
+    dev = pool.seqs.device
+    W = words(pool.L)
+    out_s = torch.zeros((k, W), dtype=torch.int32, device=dev)
+    out_E = torch.zeros(k, dtype=torch.int32, device=dev)
+    out_n = torch.zeros(1, dtype=torch.int64, device=dev)
+    ps = pool.struct()
+    _check(lib().labs_pool_topk_noalloc(ctypes.byref(ps), pool.L, k, _ptr(out_s), _ptr(out_E), _ptr(out_n),
+                                        _stream(dev)))
     n = int(out_n.item())
     return out_s[:n], out_E[:n]
 
