@@ -102,9 +102,12 @@ def masked_ce(z: np.ndarray, mask: np.ndarray, labels: np.ndarray):
     return float(loss), dz / n
 
 
-def backward(P: dict, cache: dict, dz: np.ndarray, exact: bool = False) -> dict:
+def backward(P: dict, cache: dict, dz: np.ndarray, exact: bool = False, operands: dict = None) -> dict:
     """Gradients of the loss for every parameter; the products use the same
-    rounded operands as the forward pass (and a rounded upstream gradient)."""
+    rounded operands as the forward pass (and a rounded upstream gradient).
+    When `operands` is a dict, it receives, per parameter, the two factors whose
+    products over the batch rows the gradient sums ((upstream, input) for a
+    weight, (upstream, None) for a bias)."""
     q = (lambda a: _q(a, exact))
     dzq = q(dz)
     g = {}
@@ -120,13 +123,27 @@ def backward(P: dict, cache: dict, dz: np.ndarray, exact: bool = False) -> dict:
     da1q = q(da1)
     g["W1"] = _mm(da1q.T, cache["x"], exact)
     g["b1"] = da1.sum(axis=0)
+    if operands is not None:
+        operands.update(W3=(dzq, cache["h2q"]), b3=(dz, None), W2=(da2q, cache["h1q"]), b2=(da2, None),
+                        W1=(da1q, cache["x"]), b1=(da1, None))
     return g
 
 
-def loss_and_grads(P, X, mask, labels, exact=False):
+def loss_and_grads(P, X, mask, labels, exact=False, operands=None):
     z, cache = forward(P, X, exact)
     loss, dz = masked_ce(z, mask, labels)
-    return loss, backward(P, cache, dz, exact)
+    return loss, backward(P, cache, dz, exact, operands)
+
+
+def term_norms(operands: dict) -> dict:
+    """Per gradient element, the 2-norm over batch rows of the products the
+    element sums: sqrt(sum_n (u_nj v_ni)^2) for a weight, sqrt(sum_n u_nj^2) for a
+    bias.  It scales the rounding a batch sum of bf16 products can carry."""
+    out = {}
+    for key, (u, v) in operands.items():
+        u2 = np.asarray(u, dtype=np.float64) ** 2
+        out[key] = np.sqrt(u2.sum(axis=0) if v is None else u2.T @ (np.asarray(v, dtype=np.float64) ** 2))
+    return out
 
 
 def adam(P: dict, G: dict, M: dict, V: dict, t: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

@@ -60,6 +60,14 @@ def test_step1_full_size_sampled(lb, orc, step1):
     # the first steps of two walkers, replayed by the oracle
     o = orc.walk(L, P, 40, LO, HI, 4, [int(sample[0]), int(sample[-1])])
     assert np.array_equal(traj[[0, -1], :40], o["traj"])
+    # three walkers replayed whole (50,000 steps: every pool segment and launch
+    # boundary of the run) by the oracle's linear-time walker, which the CPU suite
+    # pins step for step to the definitional one
+    for w in (int(sample[0]), int(sample[len(sample) // 2]), int(sample[-1])):
+        b = orc.baseline_walk(L, P, STEPS, LO, HI, 4, w, 1, threads=1, want_traj=True)
+        j = int(np.flatnonzero(sample == w)[0])
+        assert np.array_equal(traj[j], b["traj"][0]), w
+        assert int(b["final_E"][0]) == fE[j] and int(b["best_E"][0]) == bE[j]
 
 
 def test_pool_and_topk_full_size(lb, orc, step1):

@@ -1,7 +1,7 @@
 """GPU parity of the learned-proposal network through the C ABI against the
 CPU reference (oracle/mlp.py): features bit for bit, logits within 1e-2
-relative, gradients within 2e-2 of the largest entry of each tensor, Adam bit
-for bit."""
+relative, every gradient element within a tolerance of its own (relative to
+the element, with a floor from the products it sums), Adam bit for bit."""
 import numpy as np
 import pytest
 
@@ -77,8 +77,31 @@ def test_forward_logits(lb, orc, L, hidden, n):
     assert err.max() <= 1e-2, err.max()
 
 
-@pytest.mark.parametrize("L,hidden,n", [(37, 64, 100), (101, 64, 257), (501, 256, 512)])
+def test_forward_logits_128_tiles(lb, orc):
+    """33,000 rows at L = 501, hidden 256: the grid of 128 x 128 tiles holds 516
+    workgroups, so the forward runs the 128-tile kernel; its last row tile is
+    ragged (104 rows).  The oracle scores sampled rows one by one: the first and
+    last tiles whole and 1,500 rows between."""
+    L, hidden, n = 501, 256, 33_000
+    lay, P, blob, pb = _params(lb, L, hidden, 60)
+    S = li.random_skew(4242, n, L, 0)
+    X = lb.mlp_features(L, _dev_i32(li.pack(S)))
+    z = lb.mlp_forward(lay, blob, pb, X).cpu().numpy()[:, :lay.d_out]
+    rows = np.unique(np.concatenate([np.arange(128), np.arange(n - 232, n),
+                                     li.rng(61).choice(n, 1500, replace=False)]))
+    Sr = S[rows]
+    zr, _ = omlp.forward(P, omlp.features(Sr, _c_even(orc, Sr)), exact=False)
+    err = np.abs(z[rows] - zr) / np.maximum(np.abs(zr), 1.0)
+    assert err.max() <= 1e-2, err.max()
+
+
+@pytest.mark.parametrize("L,hidden,n", [(37, 64, 100), (101, 64, 257), (501, 256, 512), (501, 256, 4096)])
 def test_gradients(lb, orc, L, hidden, n):
+    """Every gradient element against the oracle's, with a tolerance of its own:
+    1e-2 of the element plus 2^-7 of the 2-norm of the batch products it sums
+    (one bf16 rounding step of each product, the scale at which a flipped
+    rounding of an operand shows).  n = 4096 is the training batch: the weight
+    gradients split K = 4096 over 11-16 slices."""
     import torch
     lay, P, blob, pb = _params(lb, L, hidden, 56)
     S = li.random_skew(13 * L, n, L, 0)
@@ -87,12 +110,16 @@ def test_gradients(lb, orc, L, hidden, n):
     G, loss = lb.mlp_grads(lay, blob, pb, X, _dev_i32(words),
                            torch.from_numpy(labels).cuda())
     Gd = lb.mlp_dict_from_blob(lay, G.cpu().numpy())
-    lr, Gr = omlp.loss_and_grads(P, omlp.features(S, _c_even(orc, S)), adm, labels, exact=False)
+    ops = {}
+    lr, Gr = omlp.loss_and_grads(P, omlp.features(S, _c_even(orc, S)), adm, labels, exact=False,
+                                 operands=ops)
+    norms = omlp.term_norms(ops)
     assert abs(float(loss.item()) - lr) <= 1e-3 * max(1.0, abs(lr))
     for key in omlp_keys():
         ref = Gr[key]
-        scale = np.abs(ref).max()
-        assert np.abs(Gd[key] - ref).max() <= 2e-2 * scale + 1e-7, key
+        tol = 1e-2 * np.abs(ref) + 2.0 ** -7 * norms[key] + 1e-9
+        bad = np.abs(Gd[key] - ref) > tol
+        assert not bad.any(), (key, int(bad.sum()), float((np.abs(Gd[key] - ref) / tol).max()))
     # pads of the gradient blob are zero
     full = G.cpu().numpy()
     W1 = full[lay.off_W1:lay.off_W1 + hidden * lay.ld_in].reshape(hidden, lay.ld_in)

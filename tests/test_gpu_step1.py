@@ -118,6 +118,43 @@ def test_walk_L501_cfg4_shape(lb, orc):
     _compare_walk(lb, orc, 501, 16, 40, 50, 100, 4, 3)
 
 
+def test_walk_long_no_pool(lb, orc):
+    """9,000 steps without a pool run as three launches of up to 4,096 steps; the
+    whole trajectories, final and best sequences equal the oracle's."""
+    L, p, steps, n = 37, 0, 9000, 12
+    r = lb.walk_step1(L, p, steps, 8, 8, 21, n, want_traj=True)
+    o = orc.walk(L, p, steps, 8, 8, 21, range(n))
+    assert np.array_equal(r.traj_E.cpu().numpy(), o["traj"])
+    assert np.array_equal(_host_seqs(r.final_seqs, L), o["final"])
+    assert np.array_equal(_host_seqs(r.best_seqs, L), o["best"])
+    assert np.array_equal(r.best_step.cpu().numpy(), o["best_step"])
+
+
+def test_walk_L501_across_pool_segments(lb, orc):
+    """L = 501 with the pool on: the walk runs in segments of 256, 512, ... steps
+    with a compaction between them.  Two walkers' 1,200-step trajectories equal the
+    oracle's linear-time walker (pinned to the definitional one in the CPU suite),
+    and the pool holds exactly the distinct sequences the walkers reached at
+    E <= e_max, each at an energy their trajectories show."""
+    L, p, steps, n = 501, 16, 1200, 2
+    em = orc.e_max_for_tau(L, 4, 1)
+    pool = lb.PoolBuffers.empty(L, 1 << 16)
+    r = lb.walk_step1(L, p, steps, 50, 100, 4, n, e_max=em, pool=pool, want_traj=True)
+    b = orc.baseline_walk(L, p, steps, 50, 100, 4, 0, n, threads=2, want_traj=True)
+    traj = r.traj_E.cpu().numpy()
+    assert np.array_equal(traj, b["traj"])
+    assert np.array_equal(r.final_E.cpu().numpy(), b["final_E"])
+    assert np.array_equal(r.best_E.cpu().numpy(), b["best_E"])
+    cnt = int(pool.count.item())
+    assert cnt > 0 and int(pool.dropped.item()) == 0
+    pw, ps, pe = (pool.walker[:cnt].cpu().numpy(), pool.step[:cnt].cpu().numpy(),
+                  pool.E[:cnt].cpu().numpy())
+    assert np.array_equal(traj[pw, ps - 1], pe)
+    assert np.array_equal(orc.energy_batch(_host_seqs(pool.seqs[:cnt], L)), pe)
+    # every step at or below e_max was offered; distinct sequences, so at most that many
+    assert cnt <= int((traj <= em).sum()) and pe.max() <= em
+
+
 def test_walk_halts(lb, orc):
     """Tenure = free count - 1 with p = k-1 leaves 2 free positions: the walker
     alternates; tenure equal to the free count is rejected, so check the edge
