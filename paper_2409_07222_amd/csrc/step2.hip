@@ -7,7 +7,8 @@
 //  * a hash set H keyed by the exact sequence (open addressing, linear probing,
 //    four slots per live entry).  A slot holds a 64-bit Zobrist key (0 = empty),
 //    a one-byte tag of the key that lets most probes stop without touching the
-//    key array, a state (OPEN, CLOSED, EVICTED), E and the packed sequence.
+//    key array, a state (OPEN, CLOSED, EVICTED), E and the packed sequence (key, E
+//    and state share one 16-byte record).
 //    Zobrist keys make a neighbour's key one XOR away from its pivot's (Alg. 2's
 //    HASH_FLIP).  H holds Closed U Open U evicted sequences; an EVICTED slot
 //    counts as absent and is re-opened when its sequence is pushed again.  When
@@ -37,12 +38,14 @@
 // Neighbours cut in their own round never touch H, so H holds little more than
 // Closed U Open and rarely needs a rebuild.
 //
-// A round's launches: k_pop (the pivots the last cut listed become CLOSED and
-// their words are copied), k_expand (repeats, then the single flips), the
-// rotation kernels when T_r > 0, k_round_mid (counts, best, cut setup),
-// k_sel_hist (radix level), k_sel_classify (threshold bins, flags, tie lists),
-// k_sel_keys (the two tie selects), k_keep (the cut; lists the next pivots),
-// k_round_next (end of this round, start of the next).
+// A round's launches: k_expand (repeats, then the single flips; the direct
+// expansion for long sequences adds k_clear_repeats and k_repeats), the rotation
+// kernels when T_r > 0, k_round_mid (counts, best, cut setup), k_sel_hist (radix
+// level), k_sel_classify (threshold bins, flags, tie lists, the tied entries' top
+// key bytes), k_sel_keys (the two tie selects), k_keep (the cut; it also takes the
+// next round's pivots out of Open: CLOSED in the table, their slots and words
+// copied to the next round's pivot arrays), k_round_next (end of this round,
+// start of the next).
 // The seeding insertions are exact and use no fences: a candidate walks its
 // probe sequence with 64-bit CAS on the key word; an empty slot is claimed, a
 // slot already holding its key makes the candidate "pending".  After the kernel
@@ -71,6 +74,10 @@ constexpr int kSelBits = 14;
 constexpr int kSubBits = 13;
 static_assert(kSelBits + kSubBits >= 27, "the sub-bins must cover (E - emin)/4 for L <= 1023");
 constexpr int kSelBins = 1 << kSelBits;
+// After the energy histogram, two 256-bin histograms of the top Zobrist-key byte of
+// the entries tied at the cut's energy (first) and at the pivots' energy (second).
+constexpr int kZBins = 256;
+constexpr int kHistWords = kSelBins + 2 * kZBins;
 constexpr int kSelBlocks = 256;
 constexpr int kSelThreads = 512;
 constexpr int kGridBlocks = 1024;                    // grid-stride kernels over the Open list
@@ -82,11 +89,18 @@ constexpr int kExWaves = kExThreads / 64;
 constexpr int kItems = 8;                            // list entries per thread per pass (filters)
 constexpr int kKeepItems = 2;                        // the cut: fewer, so inserts overlap across threads
 
+// A slot's key, energy and state in one 16-byte record, so that a claim (CAS on
+// the key) and the writes of E and state touch one cache line, as do a probe's
+// key compare and state read.
+struct SlotRec {
+    unsigned long long key;   // Zobrist key, 0 = empty
+    int32_t E;
+    uint32_t state;           // ST_OPEN, ST_CLOSED, ST_EVICTED
+};
+
 struct Table {
-    unsigned long long* hkey;
+    SlotRec* rec;
     uint8_t* tag;          // 0 for an empty slot, else tag_of(key): a byte-wide filter
-    uint32_t* state;
-    int32_t* E;
     uint32_t* seq;
     uint64_t mask;
     int32_t W;
@@ -119,11 +133,16 @@ struct Ctl {
     uint32_t blo, bhi;     // bounds of the live Open energies (blo is one of them)
     // A cut that also selects the next round's T2 pivots (the T2 smallest of the
     // survivors are the T2 smallest before the cut): their own threshold; the cut
-    // lists their new positions (pivpos, n_pivpos); presel: this round's pivots
+    // takes them out of Open for the next round (n_pivpos); presel: this round's pivots
     // were selected so.
     long long T2, c_lt2, out_count2, n_pivpos;
     uint32_t Dt2, prefix2;
     int32_t resolved2, dual, presel, dual_all;   // dual_all: T2 takes every survivor
+    // A tie select that split its tied entries on the top key byte first: the
+    // entries tied at the cut's (zv) / the pivots' (zv2) energy whose top byte is
+    // below the threshold byte are taken by the cut itself (flag bits 2 / 3 mark
+    // the tied entries); 0 when unused.
+    uint32_t zv, zv2;
 };
 
 // A pending insertion: the slot whose key matched, the source of the sequence
@@ -146,9 +165,9 @@ struct Params {
     unsigned long long* candz[2];   // [cap_o] each: their Zobrist keys
     int32_t* cand2[2];     // the same for the next round's pivots (dual cut)
     unsigned long long* candz2[2];
-    int32_t* pivpos;       // [B] Open positions of the next round's pivots (the cut)
-    int32_t* piv;          // [B]
-    uint32_t* ghist;       // [kSelBins], zero between selections
+    int32_t* piv;          // [B] table slots of this round's pivots
+    int32_t* pivn;         // [B] the next round's (written by the cut; the host alternates the two)
+    uint32_t* ghist;       // [kHistWords]: energy bins, then the two key-byte histograms; zero between selections
     uint32_t* best_seq;    // [W] copy of the best sequence
     Pend* pend;            // [cap_pend]
     Pend* slow;            // [cap_pend]
@@ -164,6 +183,10 @@ struct Params {
     uint8_t* repeat;
     int32_t direct;        // the direct expansion is in use
     uint32_t* pseq;        // [B*W] packed sequences of the round's pivots
+    uint32_t* pseqn;       // [B*W] the next round's (written by the cut)
+    int32_t* pivpos;       // [B] the next round's pivots' Open positions (the cut)
+    int32_t take_pivots;   // the cut takes its pivots out of Open (rounds; not the seeding cut,
+                           // whose pivots leave after the initial best is found)
     // MAKE_ROTATIONS: rotation q of pivot b sits at Open position batch_begin +
     // n_piv*L + b*R2 + q (after every single flip of the round); q < Tr rotates
     // left by q+1, else right by q-Tr+1.
@@ -237,7 +260,7 @@ __device__ __forceinline__ void atomic_min_batch(Ctl* c, bool take, int32_t E) {
 // Tie order between two slots of equal energy: Zobrist key, then the sequence
 // (words compared as unsigned).
 __device__ __forceinline__ bool key_less(const Table& H, int a, int b) {
-    if (H.hkey[a] != H.hkey[b]) return H.hkey[a] < H.hkey[b];
+    if (H.rec[a].key != H.rec[b].key) return H.rec[a].key < H.rec[b].key;
     for (int w = 0; w < H.W; ++w) {
         uint32_t x = H.seq[(size_t)a * H.W + w], y = H.seq[(size_t)b * H.W + w];
         if (x != y) return x < y;
@@ -306,12 +329,12 @@ __device__ int claim_or_pend(const Params& P, unsigned long long key, int src, i
     const Table& H = P.H;
     uint64_t s = key & H.mask;
     for (uint64_t probe = 0; probe <= H.mask; ++probe) {
-        const unsigned long long prev = atomicCAS(&H.hkey[s], 0ull, key);
+        const unsigned long long prev = atomicCAS(&H.rec[s].key, 0ull, key);
         if (prev == 0ull) {
             H.tag[s] = tag_of(key);
             for (int w = 0; w < H.W; ++w) H.seq[s * H.W + w] = src_word(P, src, flip, w);
-            H.E[s] = E;
-            H.state[s] = ST_OPEN;
+            H.rec[s].E = E;
+            H.rec[s].state = ST_OPEN;
             *slot_out = (int)s;
             return INS_CLAIMED;
         }
@@ -351,7 +374,8 @@ __device__ __forceinline__ void push_pending(const Params& P, bool take, const P
 // (`repeated`) or when H holds its sequence as OPEN or CLOSED; otherwise it is a
 // new entry.  `taken`, `mn` and `mx` accumulate per thread.
 __device__ void stage_neighbour(const Params& P, bool valid, bool repeated, unsigned long long key, int ps,
-                                int flip, int32_t En, int& taken, int32_t& mn, int32_t& mx) {
+                                int flip, int32_t En, int& taken, int32_t& mn, int32_t& mx,
+                                int home_tag = -1) {
     if (!valid) return;
     Ctl* c = P.ctl;
     const long long j = (long long)blockIdx.x * P.L + (flip - 1);
@@ -362,9 +386,10 @@ __device__ void stage_neighbour(const Params& P, bool valid, bool repeated, unsi
         const uint8_t tg = tag_of(key);
         uint64_t s = key & H.mask;
         for (uint64_t probe = 0; probe <= H.mask; ++probe, s = (s + 1) & H.mask) {
-            const uint8_t ts = H.tag[s];
+            // the home slot's tag may have been loaded ahead by the caller
+            const uint8_t ts = (probe == 0 && home_tag >= 0) ? (uint8_t)home_tag : H.tag[s];
             if (ts == 0) break;
-            if (ts != tg || H.hkey[s] != key) continue;
+            if (ts != tg || H.rec[s].key != key) continue;
             bool eq = true;
             for (int w = 0; w < H.W; ++w)
                 if (H.seq[s * H.W + w] != src_word(P, ps, flip, w)) {
@@ -372,7 +397,7 @@ __device__ void stage_neighbour(const Params& P, bool valid, bool repeated, unsi
                     break;
                 }
             if (!eq) continue;
-            if (H.state[s] == ST_EVICTED) tomb = (int)s;
+            if (H.rec[s].state == ST_EVICTED) tomb = (int)s;
             else take = false;
             break;
         }
@@ -470,11 +495,11 @@ __global__ __launch_bounds__(512) void k_resolve(Params P) {
                     break;
                 }
             if (!eq) coll = true;
-            else if (P.H.state[pd.slot] == ST_EVICTED &&
-                     atomicCAS(&P.H.state[pd.slot], ST_EVICTED, ST_OPEN) == ST_EVICTED)
+            else if (P.H.rec[pd.slot].state == ST_EVICTED &&
+                     atomicCAS(&P.H.rec[pd.slot].state, ST_EVICTED, ST_OPEN) == ST_EVICTED)
                 pushed = true;
         }
-        push_open(P, pushed, pd.E, pd.slot, pushed ? P.H.hkey[pd.slot] : 0ull);
+        push_open(P, pushed, pd.E, pd.slot, pushed ? P.H.rec[pd.slot].key : 0ull);
         const long long o = block_append(&c->n_slow, coll);
         if (coll && o < P.cap_pend) P.slow[o] = pd;
     }
@@ -488,15 +513,15 @@ __global__ void k_slow(Params P) {
     const long long n = c->n_slow < P.cap_pend ? c->n_slow : P.cap_pend;
     for (long long q = 0; q < n; ++q) {
         const Pend pd = P.slow[q];
-        const unsigned long long key = H.hkey[pd.slot];
+        const unsigned long long key = H.rec[pd.slot].key;
         uint64_t s = (pd.slot + 1) & H.mask;
         for (uint64_t probe = 0; probe <= H.mask; ++probe, s = (s + 1) & H.mask) {
-            if (H.hkey[s] == 0ull) {
-                H.hkey[s] = key;
+            if (H.rec[s].key == 0ull) {
+                H.rec[s].key = key;
                 H.tag[s] = tag_of(key);
                 for (int w = 0; w < H.W; ++w) H.seq[s * H.W + w] = src_word(P, pd.src, pd.flip, w);
-                H.E[s] = pd.E;
-                H.state[s] = ST_OPEN;
+                H.rec[s].E = pd.E;
+                H.rec[s].state = ST_OPEN;
                 const long long o = c->n_tot++;
                 if (o < P.cap_o) {
                     P.oE[c->which][o] = pd.E;
@@ -506,13 +531,13 @@ __global__ void k_slow(Params P) {
                 if (pd.E < c->batch_minE) c->batch_minE = pd.E;
                 break;
             }
-            if (H.hkey[s] != key) continue;
+            if (H.rec[s].key != key) continue;
             bool eq = true;
             for (int w = 0; w < H.W; ++w)
                 if (H.seq[s * H.W + w] != src_word(P, pd.src, pd.flip, w)) { eq = false; break; }
             if (!eq) continue;
-            if (H.state[s] == ST_EVICTED) {
-                H.state[s] = ST_OPEN;
+            if (H.rec[s].state == ST_EVICTED) {
+                H.rec[s].state = ST_OPEN;
                 const long long o = c->n_tot++;
                 if (o < P.cap_o) {
                     P.oE[c->which][o] = pd.E;
@@ -598,12 +623,26 @@ __device__ void cut_setup(const Params& P) {
     c->survivors = 0;
     c->n_pivpos = 0;
     c->out_count = 0;
+    c->zv = 0;
+    c->zv2 = 0;
 }
 
-__device__ void round_begin(const Params& P) {
+// next_piv: the table slots of the pivots the last cut took out of Open for the
+// coming round.  One thread.
+__device__ void round_begin(const Params& P, const int32_t* next_piv) {
     Ctl* c = P.ctl;
     if (c->stop) return;
     if (c->n_live == 0 || c->expansions >= P.X || c->u >= P.T_u) {
+        // the search ends: pivots taken out for a round that does not run go back
+        // into Open (OPEN in the table, their energies in the list)
+        const int cur = c->which;
+        const long long n = c->n_pivpos < P.B ? c->n_pivpos : P.B;
+        for (long long b = 0; b < n; ++b) {
+            const int sl = next_piv[b];
+            P.H.rec[sl].state = ST_OPEN;
+            P.oE[cur][P.pivpos[b]] = P.H.rec[sl].E;
+        }
+        c->n_pivpos = 0;
         c->stop = 1;
         return;
     }
@@ -620,7 +659,10 @@ __device__ void round_begin(const Params& P) {
         c->stop = 1;
         return;
     }
-    c->n_piv = 0;
+    // the last cut took this round's pivots out of Open (CLOSED in the table, DEAD
+    // in the list) and copied their slots and words
+    if (c->n_pivpos > P.B) atomicExch(&c->error, 3);
+    c->n_piv = c->n_pivpos < P.B ? c->n_pivpos : P.B;
     c->n_pend = 0;
     c->n_slow = 0;
     c->batch_begin = c->n_tot;
@@ -631,7 +673,7 @@ __device__ void round_begin(const Params& P) {
     c->out_count = 0;
 }
 
-__global__ void k_round_begin(Params P) { round_begin(P); }
+__global__ void k_round_begin(Params P) { round_begin(P, P.piv); }
 
 // ---------------------------------------------------------------- selection
 // Selects the T smallest live Open entries in key order into flag[].
@@ -806,6 +848,10 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
     const uint32_t D2lo = cut.prefix2 << cut.hi_shift;
     const uint32_t D2hi = (cut.prefix2 + 1u) << cut.hi_shift;
     const long long n_tot = c->n_tot;
+    // top key bytes of the entries tied at a resolved threshold energy
+    __shared__ uint32_t zh[2 * kZBins];
+    for (int b = threadIdx.x; b < 2 * kZBins; b += blockDim.x) zh[b] = 0;
+    __syncthreads();
     const long long stride = (long long)gridDim.x * blockDim.x * kItems;
     for (long long base = (long long)blockIdx.x * blockDim.x * kItems; base < n_tot; base += stride) {
         bool tie[kItems], tie2[kItems];
@@ -824,7 +870,10 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
                         f = 1;
                     } else if (res) {
                         if ((uint32_t)e < Et) f = 1;
-                        else if ((uint32_t)e == Et) tie[k] = true;
+                        else if ((uint32_t)e == Et) {
+                            tie[k] = true;
+                            f = 4u;
+                        }
                     } else {
                         if (D < Dlo) f = 1;
                         else if (D < Dhi) tie[k] = true;
@@ -834,7 +883,10 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
                     } else if (dual) {
                         if (res2) {
                             if ((uint32_t)e < Et2) f |= 2u;
-                            else if ((uint32_t)e == Et2) tie2[k] = true;
+                            else if ((uint32_t)e == Et2) {
+                                tie2[k] = true;
+                                f |= 8u;
+                            }
                         } else {
                             if (D < D2lo) f |= 2u;
                             else if (D < D2hi) tie2[k] = true;
@@ -851,8 +903,10 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
         for (int k = 0; k < kItems; ++k)
             if (tie[k]) {
                 const long long i = base + threadIdx.x + (long long)k * blockDim.x;
+                const unsigned long long z = P.oZ[cur][i];
                 P.cand[0][o] = (int32_t)i;
-                P.candz[0][o] = P.oZ[cur][i];
+                P.candz[0][o] = z;
+                if (res) atomicAdd(&zh[z >> 56], 1u);
                 ++o;
             }
         if (dual && !dual_all) {   // uniform
@@ -861,12 +915,17 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
             for (int k = 0; k < kItems; ++k)
                 if (tie2[k]) {
                     const long long i = base + threadIdx.x + (long long)k * blockDim.x;
+                    const unsigned long long z = P.oZ[cur][i];
                     P.cand2[0][o2] = (int32_t)i;
-                    P.candz2[0][o2] = P.oZ[cur][i];
+                    P.candz2[0][o2] = z;
+                    if (res2) atomicAdd(&zh[kZBins + (z >> 56)], 1u);
                     ++o2;
                 }
         }
     }
+    __syncthreads();
+    for (int b = threadIdx.x; b < 2 * kZBins; b += blockDim.x)
+        if (zh[b]) atomicAdd(&P.ghist[kSelBins + b], zh[b]);
 }
 
 // Tie digits of Open entry o: bytes 0..7 are its Zobrist key (most significant
@@ -1005,6 +1064,62 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         m = s_m2;
         r = s_r;
         src = 1 - src;
+        __syncthreads();
+    }
+    if (!unres && m > kTieLds && r > 0 && r < m) {
+        // The classify pass counted the tied entries' top key bytes: the threshold
+        // byte v comes from that histogram, the tied entries below it are taken by
+        // the cut itself (zv / zv2, flag bits 2 / 3), and one pass over the tied
+        // entries keeps those of byte v.
+        const uint32_t* zhg = P.ghist + kSelBins + kZBins * which;
+        if (t < 256) h[t] = zhg[t];
+        if (t == 0) s_m2 = 0;
+        __syncthreads();
+        if (t < 64) {
+            const uint32_t c0 = h[4 * t], c1 = h[4 * t + 1], c2 = h[4 * t + 2], c3 = h[4 * t + 3];
+            uint32_t inc = c0 + c1 + c2 + c3;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(inc, o, 64);
+                if (t >= o) inc += y;
+            }
+            long long cum = (long long)inc - (c0 + c1 + c2 + c3);
+            const uint32_t cs[4] = {c0, c1, c2, c3};
+            for (int k = 0; k < 4; ++k) {
+                if (cum < r && r <= cum + cs[k]) {
+                    s_v = 4 * t + k;
+                    s_r = r - cum;
+                }
+                cum += cs[k];
+            }
+        }
+        __syncthreads();
+        const int v = s_v;
+        if (t == 0) {
+            if (which) c->zv2 = (uint32_t)v;
+            else c->zv = (uint32_t)v;
+        }
+        for (int q0 = t; q0 < m; q0 += kTieU * blockDim.x) {
+            unsigned long long z[kTieU];
+#pragma unroll
+            for (int u = 0; u < kTieU; ++u) {
+                const int q = q0 + u * blockDim.x;
+                z[u] = q < m ? CZ[src][q] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < kTieU; ++u) {
+                const int q = q0 + u * blockDim.x;
+                if (q < m && (int)(z[u] >> 56) == v) {
+                    const int o2 = atomicAdd(&s_m2, 1);
+                    CA[1 - src][o2] = CA[src][q];
+                    CZ[1 - src][o2] = z[u];
+                }
+            }
+        }
+        __syncthreads();
+        m = s_m2;
+        r = s_r;
+        src = 1 - src;
+        pos = 1;
         __syncthreads();
     }
     // Large tie sets: partition on key bytes read from the Open list until the
@@ -1200,41 +1315,15 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
 }
 
 // ---------------------------------------------------------------- pop / expand
-__global__ __launch_bounds__(kSelThreads) void k_pop(Params P) {
+// The direct expansion's repeat map starts each round clear.
+__global__ __launch_bounds__(kSelThreads) void k_clear_repeats(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
-    // this round's repeat map starts clear
-    if (P.direct) {
-        uint32_t* rw = (uint32_t*)P.repeat;
-        const long long nw = ((long long)P.B * P.L + 3) / 4;
-        for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
-             i += (long long)gridDim.x * blockDim.x)
-            rw[i] = 0u;
-    }
-    // the last cut listed this round's pivots (round_begin stops the search when
-    // it did not)
-    const int cur = c->which;
-    const long long n = c->n_pivpos;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (n > P.B) atomicExch(&c->error, 3);
-        c->n_piv = n < P.B ? n : P.B;
-    }
-    // one thread per (pivot, word) of the copied sequences
-    const int W = P.W;
-    const long long nb = n < P.B ? n : P.B;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nb * W;
-         e += (long long)gridDim.x * blockDim.x) {
-        const long long b = e / W;
-        const int w = (int)(e - b * W);
-        const int i = P.pivpos[b];
-        const int slot = P.oS[cur][i];
-        P.pseq[e] = P.H.seq[(size_t)slot * W + w];
-        if (w == 0) {
-            P.piv[b] = slot;
-            P.oE[cur][i] = DEAD;
-            P.H.state[slot] = ST_CLOSED;
-        }
-    }
+    uint32_t* rw = (uint32_t*)P.repeat;
+    const long long nw = ((long long)P.B * P.L + 3) / 4;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
+         i += (long long)gridDim.x * blockDim.x)
+        rw[i] = 0u;
 }
 
 // Direct O(L^2) expansion, one wavefront per pivot: the fallback for L > 641.
@@ -1247,7 +1336,7 @@ __global__ __launch_bounds__(64) void k_expand_direct(Params P) {
     const int lane = threadIdx.x;
     const int L = P.L, W = P.W;
     const int ps = P.piv[blockIdx.x];
-    const int32_t Ep = P.H.E[ps];
+    const int32_t Ep = P.H.rec[ps].E;
     if (lane < W) pk[lane] = P.H.seq[(size_t)ps * W + lane];
     for (int i = lane; i < kSv; i += 64) sv[i] = 0;
     __syncthreads();
@@ -1308,7 +1397,7 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int L = P.L, W = P.W;
     const int ps = P.piv[blockIdx.x];
-    const int32_t Ep = P.H.E[ps];
+    const int32_t Ep = P.H.rec[ps].E;
     const uint32_t* pw = P.pseq + (size_t)blockIdx.x * W;
     // V bit j = digit of s_{j+1} (LSB first): word w is the bit-reversed packed word;
     // VR (reversal over N = 32W bits): word W-1-w is the packed word itself.
@@ -1381,6 +1470,16 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
     __syncthreads();
     unsigned long long hp = 0;
     for (int k = 0; k < kExThreads / 64; ++k) hp ^= hpart[k];
+    // the neighbours' keys, and their home slots' tags loaded now: the loads land
+    // while the energies are computed
+    unsigned long long nkey[R2];
+    int htag[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+        const int i0 = 1 + lane + 64 * (wv + kExWaves * r);
+        nkey[r] = (hp ^ zob((i0 <= L ? i0 : L) - 1)) | 1ull;
+        htag[r] = (i0 <= L && !srep[i0 - 1]) ? (int)P.H.tag[nkey[r] & P.H.mask] : 0;
+    }
     int32_t Cq[NQ2];
     uint32_t orv = 0;
 #pragma unroll
@@ -1445,8 +1544,7 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
         const int G = 2 * H[r] - PC[Mf] - PC[Mb];
         const int Q = (L - 1) + 2 * (M - 2 * dis);
         const int32_t En = Ep - 4 * si * G + 4 * Q;
-        const unsigned long long key = (hp ^ zob(i - 1)) | 1ull;
-        stage_neighbour(P, valid, srep[i - 1] != 0, key, ps, i, En, taken, mn, mx);
+        stage_neighbour(P, valid, srep[i - 1] != 0, nkey[r], ps, i, En, taken, mn, mx, htag[r]);
     }
     stage_finish(P, taken, mn, mx);
 }
@@ -1624,11 +1722,11 @@ __global__ __launch_bounds__(kRotThreads) void k_rot_stage(Params P) {
             for (uint64_t probe = 0; probe <= H.mask; ++probe, sl = (sl + 1) & H.mask) {
                 const uint8_t ts = H.tag[sl];
                 if (ts == 0) break;
-                if (ts != tg || H.hkey[sl] != key) continue;
+                if (ts != tg || H.rec[sl].key != key) continue;
                 bool eq = true;
                 for (int w = 0; w < W && eq; ++w) eq = H.seq[sl * W + w] == rw[q][w];
                 if (!eq) continue;
-                if (H.state[sl] == ST_EVICTED) tomb = (int)sl;
+                if (H.rec[sl].state == ST_EVICTED) tomb = (int)sl;
                 else take = false;
                 break;
             }
@@ -1775,11 +1873,13 @@ __global__ __launch_bounds__(1024) void k_best(Params P, int initial) {
 __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
-    // the classify pass has read the select histogram: empty it for the next selection
-    for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < kSelBins;
+    // the classify pass and the tie select have read the histograms: empty them for
+    // the next selection
+    for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < kHistWords;
          b += (long long)gridDim.x * blockDim.x)
         P.ghist[b] = 0u;
     const int cur = c->which;
+    const uint32_t zv = c->zv, zv2 = c->zv2;
     const bool cut = !c->sel_all;           // entries are evicted
     const bool dual = c->dual;
     const bool dual_all = c->dual_all;
@@ -1797,10 +1897,12 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
             keep[k] = false;
             slot[k] = -1;
             if (i < n_tot && P.oE[cur][i] != DEAD) {
-                keep[k] = !cut || (P.flag[i] & 1u);
+                const uint32_t f = P.flag[i];
+                // tied at the cut's energy below the threshold key byte: taken
+                keep[k] = !cut || (f & 1u) || ((f & 4u) && (uint32_t)(P.oZ[cur][i] >> 56) < zv);
                 slot[k] = P.oS[cur][i];
                 if (slot[k] >= 0) {
-                    if (!keep[k]) H.state[slot[k]] = ST_EVICTED;
+                    if (!keep[k]) H.rec[slot[k]].state = ST_EVICTED;
                 } else if (keep[k]) {
                     // A surviving new entry enters H: its tombstone is re-opened, or
                     // an empty slot is claimed.  A slot already holding its key holds
@@ -1810,11 +1912,11 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
                     const unsigned long long key = P.oZ[cur][i];
                     if (P.ntomb[j] >= 0) {
                         slot[k] = P.ntomb[j];
-                        H.state[slot[k]] = ST_OPEN;
+                        H.rec[slot[k]].state = ST_OPEN;
                     } else {
                         uint64_t s2 = key & H.mask;
                         for (uint64_t probe = 0; probe <= H.mask; ++probe, s2 = (s2 + 1) & H.mask)
-                            if (atomicCAS(&H.hkey[s2], 0ull, key) == 0ull) {
+                            if (atomicCAS(&H.rec[s2].key, 0ull, key) == 0ull) {
                                 slot[k] = (int)s2;
                                 H.tag[s2] = tag_of(key);
                                 break;
@@ -1825,8 +1927,8 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
                         } else {
                             for (int w = 0; w < H.W; ++w)
                                 H.seq[(size_t)slot[k] * H.W + w] = new_word(P, j, w);
-                            H.E[slot[k]] = P.oE[cur][i];
-                            H.state[slot[k]] = ST_OPEN;
+                            H.rec[slot[k]].E = P.oE[cur][i];
+                            H.rec[slot[k]].state = ST_OPEN;
                             ++claims;
                         }
                     }
@@ -1840,7 +1942,12 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
 #pragma unroll
         for (int k = 0; k < kKeepItems; ++k) {
             const long long i = base + threadIdx.x + (long long)k * blockDim.x;
-            pv[k] = dual && keep[k] && (dual_all || ((P.flag[i] >> 1) & 1u));
+            if (dual && keep[k] && !dual_all) {
+                const uint32_t f = P.flag[i];
+                pv[k] = (f & 2u) || ((f & 8u) && (uint32_t)(P.oZ[cur][i] >> 56) < zv2);
+            } else {
+                pv[k] = dual && keep[k];
+            }
             npv += pv[k] ? 1 : 0;
         }
         long long o = block_append_n(&c->survivors, cnt);
@@ -1853,7 +1960,18 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
             P.oS[1 - cur][o] = slot[k];
             P.oZ[1 - cur][o] = P.oZ[cur][i];
             if (pv[k]) {
-                if (op < P.B) P.pivpos[op] = (int32_t)o;
+                // a pivot of the next round: out of Open (CLOSED, DEAD in the list),
+                // its slot and words copied for the expansion
+                if (op < P.B) {
+                    const int sl = slot[k];
+                    P.pivn[op] = sl;
+                    P.pivpos[op] = (int32_t)o;
+                    if (P.take_pivots) {
+                        P.oE[1 - cur][o] = DEAD;
+                        H.rec[sl].state = ST_CLOSED;
+                    }
+                    for (int w = 0; w < H.W; ++w) P.pseqn[(size_t)op * H.W + w] = H.seq[(size_t)sl * H.W + w];
+                }
                 ++op;
             }
             ++o;
@@ -1886,7 +2004,7 @@ __global__ void k_round_end(Params P, int count_round) { round_end(P, count_roun
 // The end of a round and the start of the next in one launch.
 __global__ void k_round_next(Params P) {
     round_end(P, 1);
-    round_begin(P);
+    round_begin(P, P.pivn);
 }
 
 __global__ void k_outputs(Params P, uint32_t* best_seq, int32_t* best_E, labs_step2_stats* st,
@@ -1924,18 +2042,18 @@ __global__ void k_outputs(Params P, uint32_t* best_seq, int32_t* best_E, labs_st
 __global__ void k_rebuild(Table src, Table dst, uint32_t* remap, Ctl* c) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= src.mask;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t st = src.state[i];
-        if (src.hkey[i] == 0ull || (st != ST_OPEN && st != ST_CLOSED)) continue;
-        const unsigned long long key = src.hkey[i];
+        const uint32_t st = src.rec[i].state;
+        if (src.rec[i].key == 0ull || (st != ST_OPEN && st != ST_CLOSED)) continue;
+        const unsigned long long key = src.rec[i].key;
         uint64_t s = key & dst.mask;
         for (uint64_t probe = 0; probe <= dst.mask; ++probe) {
-            if (atomicCAS(&dst.hkey[s], 0ull, key) == 0ull) break;
+            if (atomicCAS(&dst.rec[s].key, 0ull, key) == 0ull) break;
             s = (s + 1) & dst.mask;
         }
         dst.tag[s] = tag_of(key);
         for (int w = 0; w < src.W; ++w) dst.seq[s * dst.W + w] = src.seq[i * src.W + w];
-        dst.E[s] = src.E[i];
-        dst.state[s] = st;
+        dst.rec[s].E = src.rec[i].E;
+        dst.rec[s].state = st;
         remap[i] = (uint32_t)s;
         atomicAdd((unsigned long long*)&c->claimed_new, 1ull);
     }
@@ -1947,6 +2065,10 @@ __global__ void k_remap(Params P, const uint32_t* remap) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < c->n_tot;
          i += (long long)gridDim.x * blockDim.x)
         if (P.oE[cur][i] != DEAD) P.oS[cur][i] = (int32_t)remap[P.oS[cur][i]];
+    // the coming round's pivots (CLOSED, DEAD in the list)
+    for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < c->n_piv;
+         b += (long long)gridDim.x * blockDim.x)
+        P.piv[b] = (int32_t)remap[P.piv[b]];
 }
 
 __global__ void k_rebuild_fin(Ctl* c, const uint32_t* remap) {
@@ -1974,6 +2096,18 @@ __global__ void k_seed_fin(Params P) {
 }
 
 // Before the initial best: the whole (cut) Open list is the "batch".
+// After the seeding: round 0's pivots (listed by the seeding cut) leave Open.
+__global__ void k_take_pivots(Params P) {
+    Ctl* c = P.ctl;
+    const int cur = c->which;
+    const long long n = c->n_pivpos < P.B ? c->n_pivpos : P.B;
+    for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < n;
+         b += (long long)gridDim.x * blockDim.x) {
+        P.oE[cur][P.pivpos[b]] = DEAD;
+        P.H.rec[P.piv[b]].state = ST_CLOSED;
+    }
+}
+
 __global__ void k_seed_best_setup(Ctl* c) {
     c->batch_begin = 0;
     c->batch_minE = INT32_MAX;
@@ -2042,17 +2176,15 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     lo.cap_new = BL + 1024;
     size_t t = 0;
     for (int tb = 0; tb < 2; ++tb) {
-        t += align_up(sizeof(unsigned long long) * lo.cap_ht, 256);
+        t += align_up(sizeof(SlotRec) * lo.cap_ht, 256);                 // key, E, state
         t += align_up(lo.cap_ht, 256);                                   // tag
-        t += align_up(sizeof(uint32_t) * lo.cap_ht, 256);
-        t += align_up(sizeof(int32_t) * lo.cap_ht, 256);
         t += align_up(sizeof(uint32_t) * lo.cap_ht * W, 256);
     }
     t += align_up(sizeof(uint32_t) * lo.cap_ht, 256);                  // remap
     t += align_up(sizeof(int32_t) * lo.cap_new, 256);                  // ntomb
     t += 3 * align_up(sizeof(int32_t) * c.batch, 256);                 // bcnt, bmin, bmax
     t += align_up(lo.cap_new + 4, 256);                                // repeat
-    t += align_up(sizeof(uint32_t) * c.batch * words_of(c.L), 256);      // pseq
+    t += 2 * align_up(sizeof(uint32_t) * c.batch * words_of(c.L), 256);  // pseq, this round's and the next's
     t += align_up(sizeof(unsigned long long) * (2 * c.T_r * c.batch + 1), 256);   // rotation keys
     t += align_up(sizeof(int32_t) * (2 * c.T_r * c.batch + 1), 256);              // rotation energies
     t += align_up(sizeof(uint32_t) * c.batch, 256);                                // pivots' first words
@@ -2065,9 +2197,9 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     t += 2 * align_up(sizeof(unsigned long long) * lo.cap_o, 256);     // candz
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // cand2
     t += 2 * align_up(sizeof(unsigned long long) * lo.cap_o, 256);     // candz2
+    t += 2 * align_up(sizeof(int32_t) * c.batch, 256);                 // piv, this round's and the next's
     t += align_up(sizeof(int32_t) * c.batch, 256);                     // pivpos
-    t += align_up(sizeof(int32_t) * c.batch, 256);                     // piv
-    t += align_up(sizeof(uint32_t) * kSelBins, 256);                   // select histogram
+    t += align_up(sizeof(uint32_t) * kHistWords, 256);                 // select histograms
     t += align_up(sizeof(uint32_t) * 32, 256);                         // best sequence
     t += 2 * align_up(sizeof(Pend) * lo.cap_pend, 256);                // pending, collisions
     lo.total = t + 4096;
@@ -2106,10 +2238,8 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.cap_pend = lo.cap_pend;
     Table tabs[2];
     for (int tb2 = 0; tb2 < 2; ++tb2) {
-        tabs[tb2].hkey = cv.take<unsigned long long>(lo.cap_ht);
+        tabs[tb2].rec = cv.take<SlotRec>(lo.cap_ht);
         tabs[tb2].tag = cv.take<uint8_t>(lo.cap_ht);
-        tabs[tb2].state = cv.take<uint32_t>(lo.cap_ht);
-        tabs[tb2].E = cv.take<int32_t>(lo.cap_ht);
         tabs[tb2].seq = cv.take<uint32_t>(lo.cap_ht * P.W);
         tabs[tb2].mask = lo.cap_ht - 1;
         tabs[tb2].W = P.W;
@@ -2120,7 +2250,8 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.bmin = cv.take<int32_t>(cfg.batch);
     P.bmax = cv.take<int32_t>(cfg.batch);
     P.repeat = cv.take<uint8_t>(lo.cap_new + 4);
-    P.pseq = cv.take<uint32_t>((size_t)cfg.batch * P.W);
+    uint32_t* pseqb[2];
+    for (int b = 0; b < 2; ++b) pseqb[b] = cv.take<uint32_t>((size_t)cfg.batch * P.W);
     P.Tr = cfg.T_r;
     P.R2 = 2 * cfg.T_r;
     P.rkey = cv.take<unsigned long long>((size_t)P.R2 * cfg.batch + 1);
@@ -2138,19 +2269,28 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     for (int b = 0; b < 2; ++b) P.cand2[b] = cv.take<int32_t>(lo.cap_o);
     for (int b = 0; b < 2; ++b) P.candz2[b] = cv.take<unsigned long long>(lo.cap_o);
     P.pivpos = cv.take<int32_t>(cfg.batch);
-    P.piv = cv.take<int32_t>(cfg.batch);
-    P.ghist = cv.take<uint32_t>((size_t)kSelBins);
+    int32_t* pivb[2];
+    for (int b = 0; b < 2; ++b) pivb[b] = cv.take<int32_t>(cfg.batch);
+    // round r expands the pivots of buffer r & 1; its cut writes those of round r + 1
+    auto set_round = [&](long long r) {
+        P.piv = pivb[r & 1];
+        P.pseq = pseqb[r & 1];
+        P.pivn = pivb[(r + 1) & 1];
+        P.pseqn = pseqb[(r + 1) & 1];
+    };
+    set_round(-1);   // the seeding cut writes round 0's pivots
+    P.take_pivots = 0;
+    P.ghist = cv.take<uint32_t>((size_t)kHistWords);
     P.best_seq = cv.take<uint32_t>(32);
     P.pend = cv.take<Pend>(lo.cap_pend);
     P.slow = cv.take<Pend>(lo.cap_pend);
     P.cands = cand_seqs;
     if (!cv.ok()) return invalid("workspace layout overflow");
 
-    LABS_HIP(hipMemsetAsync(P.H.hkey, 0, sizeof(unsigned long long) * lo.cap_ht, st));
+    LABS_HIP(hipMemsetAsync(P.H.rec, 0, sizeof(SlotRec) * lo.cap_ht, st));
     LABS_HIP(hipMemsetAsync(P.H.tag, 0, lo.cap_ht, st));
-    LABS_HIP(hipMemsetAsync(P.H.state, 0, sizeof(uint32_t) * lo.cap_ht, st));
     LABS_HIP(hipMemsetAsync(P.best_seq, 0, sizeof(uint32_t) * 32, st));
-    LABS_HIP(hipMemsetAsync(P.ghist, 0, sizeof(uint32_t) * kSelBins, st));
+    LABS_HIP(hipMemsetAsync(P.ghist, 0, sizeof(uint32_t) * kHistWords, st));
     const dim3 gS(kGridBlocks), tS(kSelThreads);
     // Selection; rounds take their energy bounds from the control block instead
     // of a min/max pass.
@@ -2175,20 +2315,24 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     hipLaunchKernelGGL(k_min_live, gS, tS, 0, st, P);
     hipLaunchKernelGGL(k_live_bounds, gS, tS, 0, st, P);
     hipLaunchKernelGGL(k_best, dim3(1), dim3(1024), 0, st, P, 1);
+    set_round(0);
+    hipLaunchKernelGGL(k_take_pivots, dim3(4), dim3(256), 0, st, P);
+    P.take_pivots = 1;
     LABS_LAUNCHED("step2 seeding");
 
     labs_status s;
     unsigned eth = 64;
     const expand_kernel_t ek = pick_expand(cfg.L, &eth);
     P.direct = ek == k_expand_direct ? 1 : 0;
-    // A round: pop (also clears the direct expansion's repeat map), in-round
-    // repeats (the bit-sliced expansion finds its own), expansion, counts /
-    // statistics / best, cut selection, cut, then the end of the round together
+    // A round: in-round repeats (the bit-sliced expansion finds its own),
+    // expansion, counts / statistics / best, cut selection, the cut (which takes
+    // the next round's pivots out of Open), then the end of the round together
     // with the start of the next.
     hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, P);
     for (long long r = 0;; ++r) {
-        hipLaunchKernelGGL(k_pop, gS, tS, 0, st, P);
+        set_round(r);
         if (P.direct) {
+            hipLaunchKernelGGL(k_clear_repeats, gS, tS, 0, st, P);
             const unsigned nt = (unsigned)((cfg.batch + kRepTile - 1) / kRepTile);
             hipLaunchKernelGGL(k_repeats, dim3(nt, nt), dim3(256), 0, st, P);
         }
@@ -2217,10 +2361,10 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
             if (flags[0]) break;
             if ((uint64_t)claimed * 2 >= lo.cap_ht) {
                 Table& dst = tabs[1 - tcur];
-                LABS_HIP(hipMemsetAsync(dst.hkey, 0, sizeof(unsigned long long) * lo.cap_ht, st));
+                LABS_HIP(hipMemsetAsync(dst.rec, 0, sizeof(SlotRec) * lo.cap_ht, st));
                 LABS_HIP(hipMemsetAsync(dst.tag, 0, lo.cap_ht, st));
-                LABS_HIP(hipMemsetAsync(dst.state, 0, sizeof(uint32_t) * lo.cap_ht, st));
                 hipLaunchKernelGGL(k_rebuild, dim3(8192), dim3(256), 0, st, tabs[tcur], dst, remap, P.ctl);
+                set_round(r + 1);   // the coming round's pivot slots are remapped too
                 hipLaunchKernelGGL(k_remap, gS, tS, 0, st, P, remap);
                 hipLaunchKernelGGL(k_rebuild_fin, dim3(1), dim3(1), 0, st, P.ctl, remap);
                 LABS_LAUNCHED("step2 rebuild");
