@@ -75,14 +75,19 @@ def parse():
                     help="skip the Bloom-filter walk measurement")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the first-step rates of the L=101 and L=451/475/527 configurations")
-    ap.add_argument("--ab-seeds", type=int, default=1,
+    ap.add_argument("--ab-seeds", type=int, default=3,
                     help="comparison seeds 1001.. (median and IQR are reported for more than one)")
     ap.add_argument("--no-ab", action="store_true",
                     help="skip the learned-vs-plain comparison at equal wall budgets")
-    ap.add_argument("--ab-budget", type=float, default=8.0, help="seconds of walking per arm")
+    ap.add_argument("--ab-budget", type=float, default=6.0, help="seconds of walking per arm")
     ap.add_argument("--ab-pairs", type=int, default=10_000_000, help="logged training pairs")
     ap.add_argument("--ab-log-steps", type=int, default=4880, help="plain-walker steps logged")
     ap.add_argument("--ab-epochs", type=float, default=1.0)
+    ap.add_argument("--no-counters", action="store_true",
+                    help="skip the rocprofv3 counter pass of the walk kernel (the hardware roofline "
+                         "fraction and HBM traffic are then null)")
+    ap.add_argument("--counter-probe", default="", choices=["", "walk"],
+                    help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference "
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -100,41 +105,89 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_calibration_bytes": n, "launches": 5}), flush=True)
 
 
-WALK_SOURCES = ["walk_impl.h", "walk.hip", "walk_inst_a.hip", "walk_inst_b.hip", "walk_inst_c.hip"]
-COUNTERS = os.path.join(ROOT, "profiles", "walk_L501_hbm_counters.txt")
+# ---------------------------------------------------------------- counter pass
+# The walk kernel's hardware work per walker-step, measured by rocprofv3 on a
+# probe launch of the benchmark's walk (L = 501, p = 16, the benchmark's walker
+# count, PROBE_STEPS steps, one launch) that this script runs as a child process
+# before it touches the GPU itself.
+PROBE_STEPS = 1024
+PROBE_SQ = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_LDS_LOAD_BANDWIDTH",
+            "SQ_INSTS_LDS_STORE_BANDWIDTH", "SQ_INSTS_LDS_ATOMIC_BANDWIDTH", "SQ_ACTIVE_INST_VALU"]
+# copy-calibrated scale of the L2 counters (a plain device copy of known size
+# reads FETCH_SIZE = half the bytes it reads and WRITE_SIZE = the bytes it writes;
+# profiles/walk_L501_hbm_counters.txt)
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+# gfx950 LDS: 128 bytes per clock per CU
+PEAK_LDS_BYTES = 256 * 128 * 2.4e9
 
 
-VALU_COUNTERS = os.path.join(ROOT, "profiles", "walk_L501_valu_counters.txt")
+def counter_probe(a):
+    """The child's work under rocprofv3: one walk launch of the benchmark's shape."""
+    import torch
+    from paper_2409_07222_amd import labs
+    labs.walk_step1(L, P, PROBE_STEPS, L // 10, L // 5, 4, a.walkers)
+    torch.cuda.synchronize()
+    print(json.dumps({"walker_steps": a.walkers * PROBE_STEPS}), flush=True)
 
 
-def _profile_value(path, key):
-    """A figure from a committed counter summary, or None when the walk kernel's
-    sources have changed since the counters were taken."""
-    import hashlib
+def _rocprof_walk(counters, walkers):
+    """Counter values (summed over the dispatches of the walk kernel) of one probe
+    run, or an error string."""
+    import csv
+    import glob
+    import shutil
+    import subprocess
+    import tempfile
+    exe = shutil.which("rocprofv3")
+    if not exe:
+        return "rocprofv3 not found"
+    out = tempfile.mkdtemp(prefix="labs_pmc_", dir="/tmp")
+    cmd = [exe, "--pmc"] + counters + ["--output-format", "csv", "-d", out, "-o", "probe", "--",
+                                       sys.executable, os.path.abspath(__file__), "--counter-probe", "walk",
+                                       "--walkers", str(walkers)]
     try:
-        txt = open(path).read()
-    except OSError:
-        return None
-    vals = dict(line.strip().split(": ", 1) for line in txt.splitlines()
-                if line.strip().startswith((key + ":", "kernel_sources_sha256:")))
-    h = hashlib.sha256()
-    for f in WALK_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2409_07222_amd", "csrc", f), "rb").read())
-    if vals.get("kernel_sources_sha256") != h.hexdigest() or key not in vals:
-        return None
-    return vals[key]
+        r = subprocess.run(cmd, cwd="/tmp", env=dict(os.environ, TMPDIR="/tmp"), capture_output=True,
+                           text=True, timeout=180)
+    except subprocess.TimeoutExpired:
+        return "rocprofv3 timed out"
+    files = glob.glob(os.path.join(out, "**", "*counter_collection.csv"), recursive=True)
+    if r.returncode != 0 and not files:
+        return "rocprofv3 exited %d: %s" % (r.returncode, (r.stderr or "")[-300:])
+    vals, disp = {}, set()
+    for fn in files:
+        with open(fn) as f:
+            for row in csv.DictReader(f):
+                if "k_walk<" not in row.get("Kernel_Name", ""):
+                    continue
+                disp.add(row.get("Dispatch_Id") or row.get("Correlation_Id"))
+                vals[row["Counter_Name"]] = vals.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+    shutil.rmtree(out, ignore_errors=True)
+    if not vals:
+        return "no walk-kernel counters in the profiler output"
+    vals["dispatches"] = len(disp)
+    return vals
 
 
-def walk_traffic():
-    """HBM bytes per walk launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)."""
-    v = _profile_value(COUNTERS, "traffic_bytes_per_launch")
-    return int(v) if v is not None else None
-
-
-def walk_valu_utilisation():
-    """Fraction of the VALU peak the walk kernel issues (SQ_INSTS_VALU x 4 cycles)."""
-    v = _profile_value(VALU_COUNTERS, "valu_utilisation")
-    return float(v) if v is not None else None
+def walk_counters(a):
+    """Per walker-step VALU instructions, LDS bytes and HBM bytes of the walk
+    kernel, from three probe runs (the SQ set, FETCH_SIZE, WRITE_SIZE: the L2
+    counters each in a run of their own)."""
+    ws = a.walkers * PROBE_STEPS
+    sq = _rocprof_walk(PROBE_SQ, a.walkers)
+    if isinstance(sq, str):
+        return {"error": sq}
+    res = {"probe": "L=%d p=%d, %d walkers x %d steps, one launch" % (L, P, a.walkers, PROBE_STEPS),
+           "dispatches": sq["dispatches"], "counters": {k: v for k, v in sq.items() if k != "dispatches"},
+           "valu_insts_per_walker_step": sq["SQ_INSTS_VALU"] / ws,
+           "lds_bytes_per_walker_step": 64.0 * sum(sq.get(k, 0.0) for k in PROBE_SQ
+                                                   if k.endswith("_BANDWIDTH")) / ws}
+    fb = _rocprof_walk(["FETCH_SIZE"], a.walkers)
+    wb = _rocprof_walk(["WRITE_SIZE"], a.walkers)
+    if isinstance(fb, dict) and isinstance(wb, dict):
+        res["hbm_bytes_per_launch"] = (FETCH_SCALE * fb["FETCH_SIZE"] + WRITE_SCALE * wb["WRITE_SIZE"]) * 1024.0
+    else:
+        res["hbm_error"] = fb if isinstance(fb, str) else wb
+    return res
 
 
 def host_threads():
@@ -397,12 +450,14 @@ def learned_ab(a, labs, dev):
     p = 16, the bench's walker count): log plain-walker pairs (seed 5), train the
     network (init seed 55, Adam lr 1e-3, batch 4096), fix tau* from a plain run of
     half the budget (seed 999, best F rounded down to 0.05), then run each arm for
-    the budget from seed 1001: the plain walker, the trained network (top-8, a
-    full scan every 64 steps), the untrained network and a random top-8.  The
-    time to reach F >= tau* is the first hit step over all walkers times the arm's
-    measured time per step (walkers advance in lockstep).  A further arm runs the
-    paper's own first step, the Bloom-filter walk of T_i = 4(L+1) steps, in
-    batches of fresh walkers for the same budget."""
+    the budget from seeds 1001.. (--ab-seeds): the plain walker, the trained
+    network (top-8, a full scan every 64 steps), the untrained network and a
+    random top-8.  The time to reach F >= tau* (and each ladder level) is read
+    from the device's real-time counter: the walker kernels stamp the first step
+    at which any walker reaches the level, against the stamp of the walker-init
+    kernel that starts the arm.  A further arm runs the paper's own first step,
+    the Bloom-filter walk of T_i = 4(L+1) steps, in batches of fresh walkers for
+    the same budget (times from the first batch's start)."""
     import numpy as np
     import torch
     import labs_inputs as li
@@ -452,14 +507,26 @@ def learned_ab(a, labs, dev):
 
     ladder = [5.2, 5.3, 5.4, 6.0, 6.5, 7.0, 7.5, 8.0]
 
+    def stamps_for(e_max):
+        # first-hit stamps of the device real-time counter: tau* first, then the ladder
+        lv = ([e_max] if e_max >= 0 else []) + [int(np.floor(L * L / (2.0 * tl))) for tl in ladder]
+        return labs.Stamps(lv[:labs.MAX_LEVELS], device=dev)
+
+    def stamp_times(st, e_max):
+        sec = st.seconds()
+        off = 1 if e_max >= 0 else 0
+        return (sec[0] if e_max >= 0 else None), {str(tl): sec[off + i] for i, tl in enumerate(ladder)
+                                                  if off + i < len(sec)}
+
     def plain_run(steps, seed, e_max, tau_star=None):
-        # the pool sieves at the lowest ladder level; each level's first hit is the
-        # least step among the pooled sequences at or below its energy
+        # device stamps give the times; the pool (sieve at the lowest ladder level)
+        # gives each level's first hit step as a cross-check
         e_pool = max(e_max, int(np.floor(L * L / (2.0 * ladder[0])))) if e_max >= 0 else -1
         pool = labs.PoolBuffers.empty(L, 1 << 20, device=dev)
+        st = stamps_for(e_max)
         sync()
         t0 = time.perf_counter()
-        r = labs.walk_step1(L, P, steps, lo, hi, seed, n, e_max=e_pool, pool=pool, device=dev)
+        r = labs.walk_step1(L, P, steps, lo, hi, seed, n, e_max=e_pool, pool=pool, device=dev, stamps=st)
         sync()
         dt = time.perf_counter() - t0
         c = int(pool.count.item())
@@ -470,8 +537,10 @@ def learned_ab(a, labs, dev):
             sel = pS[pE <= em]
             return int(sel.min()) if sel.size else None
         hits = {str(tl): first(int(np.floor(L * L / (2.0 * tl)))) for tl in ladder}
+        tt, lt = stamp_times(st, e_max)
         return {"seconds": dt, "steps": steps, "best_E": int(r.best_E.min().item()),
                 "hit_step": first(e_max) if e_max >= 0 else None, "ladder_hit_steps": hits,
+                "time_to_tau_s": tt, "ladder_time_s": lt,
                 "flip_evals": int(r.flip_evals.item()), "pool_dropped": int(pool.dropped.item())}
 
     T_i = 4 * (L + 1)
@@ -481,52 +550,40 @@ def learned_ab(a, labs, dev):
         # steps, so fresh batches of walkers (new ids) are launched until the
         # budget is spent; a level's hit time is the start of the batch that first
         # reaches it plus the fraction of that batch up to its earliest hit step
-        e_pool = max(e_max, int(np.floor(L * L / (2.0 * ladder[0])))) if e_max >= 0 else -1
-        pool = labs.PoolBuffers.empty(L, 1 << 20, device=dev)
-        hits = {str(tl): None for tl in ladder}
-        hit = None
+        # one set of stamps over every batch: times from the first batch's start
+        st = stamps_for(e_max)
         t_total, b, best, flips = 0.0, 0, None, 0
         while t_total < budget_s:
-            pool.count.zero_()
-            pool.dropped.zero_()
             sync()
             t0 = time.perf_counter()
-            r = labs.walk_step1(L, P, T_i, 0, 0, seed, n, walker_begin=b * n, e_max=e_pool, pool=pool,
-                                bloom=BLOOM, device=dev)
+            r = labs.walk_step1(L, P, T_i, 0, 0, seed, n, walker_begin=b * n, bloom=BLOOM, device=dev,
+                                stamps=st)
             sync()
             dt = time.perf_counter() - t0
-            c = int(pool.count.item())
-            pE = pool.E[:c].cpu().numpy()
-            pS = pool.step[:c].cpu().numpy()
-
-            def at(em):
-                sel = pS[pE <= em]
-                return t_total + sel.min() / T_i * dt if sel.size else None
-            for tl in ladder:
-                if hits[str(tl)] is None:
-                    hits[str(tl)] = at(int(np.floor(L * L / (2.0 * tl))))
-            if hit is None and e_max >= 0:
-                hit = at(e_max)
             e = int(r.best_E.min().item())
             best = e if best is None or e < best else best
             flips += int(r.flip_evals.item())
             t_total += dt
             b += 1
+        tt, lt = stamp_times(st, e_max)
         return {"seconds": t_total, "steps": b * T_i, "batches": b, "steps_per_walk": T_i,
                 "bloom": {"log2_bits": BLOOM[0], "n_hash": BLOOM[1]}, "best_E": best,
-                "time_to_tau_s": hit, "ladder_time_s": hits, "flip_evals": flips}
+                "time_to_tau_s": tt, "ladder_time_s": lt, "flip_evals": flips}
 
     def learned_run(steps, seed, e_max, kw):
+        st = stamps_for(e_max)
         sync()
         t0 = time.perf_counter()
         r = labs.learned_walk(L, P, steps, lo, hi, seed, n, top_m=8, fallback_every=64, e_max=e_max,
-                              device=dev, **kw)
+                              device=dev, stamps=st, **kw)
         sync()
         dt = time.perf_counter() - t0
         h = r["hit_step"]
         h = h[h >= 0]
+        tt, lt = stamp_times(st, e_max)
         return {"seconds": dt, "steps": steps, "best_E": int(r["best_E"].min().item()),
                 "hit_step": int(h.min().item()) if h.numel() else None,
+                "time_to_tau_s": tt, "ladder_time_s": lt,
                 "flip_evals": int(r["flip_evals"].item())}
 
     arms = {"learned": net.proposer_args(), "untrained": untrained.proposer_args(),
@@ -539,6 +596,12 @@ def learned_ab(a, labs, dev):
         learned_run(128, 11, -1, kw)
         q = learned_run(1024, 12, -1, kw)
         rate[name] = q["steps"] / q["seconds"]
+    # measured cost of one walker-step per arm (16,384 walkers in lockstep): the plain
+    # step scans every neighbour exactly; a proposal step rescoring m candidates costs
+    # the random arm's step without a network, and the network pass adds the rest
+    res["step_cost_us"] = {name: 1e6 / r for name, r in rate.items()}
+    res["step_cost_us"]["network_per_step"] = \
+        1e6 / rate["learned"] - 1e6 / rate["random_top8"]
     # tau* from a plain run of half the budget
     cal = plain_run(max(64, int(rate["plain"] * a.ab_budget / 2)), 999, -1)
     tau = np.floor(L * L / (2.0 * cal["best_E"]) / 0.05) * 0.05
@@ -561,14 +624,11 @@ def learned_ab(a, labs, dev):
             log("seed %d %s: best E %d" % (seed, name, out[name]["best_E"]))
         for name, o in out.items():
             o["best_F"] = L * L / (2.0 * o["best_E"])
-            if "time_to_tau_s" not in o:
-                o["time_to_tau_s"] = (o["hit_step"] / o["steps"] * o["seconds"]
-                                      if o["hit_step"] is not None else None)
+            if o.get("hit_step") is not None:
+                # the older estimate (hit step x mean time per step), beside the stamps
+                o["time_to_tau_from_steps_s"] = o["hit_step"] / o["steps"] * o["seconds"]
             o["walker_steps_per_s"] = n * o["steps"] / o["seconds"]
             o["flip_evals_per_s"] = o["flip_evals"] / o["seconds"]
-        o = out["plain"]
-        o["ladder_time_s"] = {k: (v / o["steps"] * o["seconds"] if v is not None else None)
-                              for k, v in o["ladder_hit_steps"].items()}
         per_seed.append(out)
     res["arms"] = per_seed[0]
     if len(per_seed) > 1:
@@ -594,10 +654,21 @@ def main():
     if a.copy_calibration:
         copy_calibration(a.copy_calibration)
         return
+    if a.counter_probe:
+        counter_probe(a)
+        return
     if a.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(walkers would shard across GPUs by walker-id range)", file=sys.stderr)
         sys.exit(2)
+    # the counter pass runs in child processes before this one touches the GPU
+    counters = None
+    if not a.no_counters and not a.no_roofline_pass:
+        log("counter pass of the walk kernel (rocprofv3)")
+        counters = walk_counters(a)
+        log("counter pass: %s" % ({k: counters[k] for k in ("valu_insts_per_walker_step",
+                                                            "lds_bytes_per_walker_step")
+                                   if k in counters} or counters))
     import torch
     from paper_2409_07222_amd import labs
     import labs_inputs  # noqa: F401  (seeded inputs live in the library's own RNG streams)
@@ -678,19 +749,34 @@ def main():
         labs.timing_enable(False)
         ms, launches = labs.timing_read("walk")
         ms2, launches2 = labs.timing_read("expand")
-        ops = int(r.flip_evals.item()) * W_OPS
-        achieved = ops / (ms / 1e3) / 1e12
+        fe = int(r.flip_evals.item())
+        wsteps = fe / nf                       # walker-steps over the pass's walk launches
         peak = PEAK_INT_OPS / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
-                "frac": achieved / peak, "traffic": walk_traffic(),
-                "kernel": "walk", "launches": launches, "avg_launch_ms": ms / max(launches, 1),
-                "valu_utilisation_from_counters": walk_valu_utilisation(),
-                "ops_per_flip_eval": W_OPS, "kernel_share_of_pass": ms / 1e3 / t_pass}
+        nominal = fe * W_OPS / (ms / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": None, "peak": peak, "unit": "Tops/s", "frac": None,
+                "traffic": None, "kernel": "k_walk<8,4,4> (walk)", "launches": launches,
+                "avg_launch_ms": ms / max(launches, 1), "kernel_share_of_pass": ms / 1e3 / t_pass,
+                "nominal": {"ops_per_flip_eval": W_OPS, "achieved_Tops": nominal,
+                            "ratio_to_peak": nominal / peak,
+                            "note": "direct-formula op count; the bit-sliced scan does fewer"}}
+        if counters and "valu_insts_per_walker_step" in counters:
+            lane_ops = counters["valu_insts_per_walker_step"] * 64.0 * wsteps
+            achieved = lane_ops / (ms / 1e3) / 1e12
+            lds_bps = counters["lds_bytes_per_walker_step"] * wsteps / (ms / 1e3)
+            roof.update({"achieved": achieved, "frac": max(achieved / peak, lds_bps / PEAK_LDS_BYTES),
+                         "valu_frac": achieved / peak,
+                         "lds": {"achieved_TBps": lds_bps / 1e12, "peak_TBps": PEAK_LDS_BYTES / 1e12,
+                                 "frac": lds_bps / PEAK_LDS_BYTES},
+                         "per_walker_step": {"valu_insts": counters["valu_insts_per_walker_step"],
+                                             "lds_bytes": counters["lds_bytes_per_walker_step"]}})
+            if "hbm_bytes_per_launch" in counters:
+                roof["traffic"] = counters["hbm_bytes_per_launch"]
+        roof["counters"] = counters
         if launches2:
             ops2 = int(r2["expansions"]) * L * W2_OPS
             a2 = ops2 / (ms2 / 1e3) / 1e12
-            roof["step2_expand"] = {"achieved": a2, "frac": a2 / peak, "launches": launches2,
-                                    "avg_launch_ms": ms2 / launches2,
+            roof["step2_expand"] = {"nominal_Tops": a2, "nominal_ratio_to_peak": a2 / peak,
+                                    "launches": launches2, "avg_launch_ms": ms2 / launches2,
                                     "ops_per_neighbour_eval": W2_OPS,
                                     "kernel_share_of_pass": ms2 / 1e3 / t_pass}
 

@@ -159,7 +159,27 @@ typedef struct {
     int32_t* traj_E;       /* [n*steps] energy after step t at j*steps + t-1, may be NULL */
     int64_t* flip_evals;   /* device int64, incremented by (steps taken)*(k+1-p) per walker;
                               may be NULL */
+    /* First-hit stamps of the device's constant-rate real-time counter (the
+     * s_memrealtime clock; labs_realtime_hz gives its rate).  With n_levels in
+     * 1..LABS_MAX_LEVELS, first_hit_ticks[l] (device uint64, caller-initialised,
+     * e.g. to UINT64_MAX) is lowered, by atomic min, to the counter's value when a
+     * walker's energy first reaches E <= level_E[l] (the initial sequence
+     * counted); start_ticks (device uint64, caller-initialised) is lowered to the
+     * counter's value as the call's walker-init kernel starts.  A walker that
+     * stays at or below a level re-stamps it at most once per launch, later, so
+     * the minimum is its first hit.  The stamps accumulate across calls that
+     * share the buffers.  n_levels = 0: no stamps (both pointers ignored). */
+    int32_t n_levels;
+    int32_t level_E[16];
+    uint64_t* first_hit_ticks;
+    uint64_t* start_ticks;
 } labs_step1_out;
+
+#define LABS_MAX_LEVELS 16
+
+/* Rate of the real-time counter the first-hit stamps read, in ticks per second,
+ * for the current device.  Host call. */
+labs_status labs_realtime_hz(int64_t* hz);
 
 /* Workspace bytes for labs_walk_step1 with these configurations and pools of at
  * most pool_capacity entries (ignored when no cfg has e_max >= 0).  Host call. */
@@ -541,6 +561,11 @@ typedef struct {
     uint32_t* log_mask;
     int32_t* log_label;
     int64_t* flip_evals;
+    /* first-hit stamps, as in labs_step1_out */
+    int32_t n_levels;
+    int32_t level_E[16];
+    uint64_t* first_hit_ticks;
+    uint64_t* start_ticks;
 } labs_learned_out;
 
 labs_status labs_learned_walk_workspace(const labs_step1_cfg* cfg, const labs_proposer* prop, size_t* bytes);

@@ -250,6 +250,17 @@ const char* labs_last_error(void) { return last_error(); }
 
 int32_t labs_words(int32_t L) { return L <= 0 ? 0 : words_of(L); }
 
+labs_status labs_realtime_hz(int64_t* hz) {
+    clear_error();
+    if (!hz) return invalid("hz must not be NULL");
+    int dev = 0, khz = 0;
+    LABS_HIP(hipGetDevice(&dev));
+    LABS_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) return invalid("the device reports no real-time counter rate");
+    *hz = (int64_t)khz * 1000;
+    return LABS_OK;
+}
+
 labs_status labs_energy(int32_t L, int64_t n, const uint32_t* seqs, int32_t* E, int32_t* C,
                         void* stream) {
     clear_error();
@@ -353,6 +364,7 @@ labs_status walk_single(const labs_step1_cfg& c, const labs_bloom* bloom, labs_p
     A.bestSeq = (uint32_t*)(base + lo.off_bS);
     A.traj = o.traj_E;
     A.e_max = c.e_max;
+    if ((s = set_stamps(A, o)) != LABS_OK) return s;
     if (bloom) {
         A.tabu = nullptr;
         A.zh = (uint64_t*)(base + lo.off_zh);

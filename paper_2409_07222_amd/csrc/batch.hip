@@ -234,6 +234,7 @@ labs_status build_plan(const labs_step1_cfg* c, int n, const labs_step1_out* out
         A.bestSeq = (uint32_t*)(base + l.off_bS);
         A.traj = outs[i].traj_E;
         A.e_max = -1;
+        if (labs_status st_ = set_stamps(A, outs[i])) return st_;
         const Shape sh = shape_of(L, ci.p);
         byshape[{sh.NW, sh.R}].push_back(i);
     }

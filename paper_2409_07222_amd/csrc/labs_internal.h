@@ -154,7 +154,52 @@ struct WalkArgs {
     uint32_t* bloom;       // [n << (bloom_log2 - 5)] filter words per walker
     int32_t bloom_log2;    // filter bits per walker = 2^bloom_log2
     int32_t bloom_hashes;  // bits set / tested per key
+    // first-hit stamps of the real-time counter (n_levels = 0: off)
+    int32_t n_levels;
+    int32_t level_E[16];
+    unsigned long long* hit_ticks;    // [n_levels], atomic min
+    unsigned long long* start_ticks;  // [1], atomic min, stamped by the init kernel
 };
+
+// Stamp every level l that energy E reaches (E <= level_E[l]) with the real-time
+// counter (lane 0, atomic min: a level reached again later keeps its first stamp)
+// and return the largest level energy below E (-1: none), which the caller
+// compares E against before calling again.  Wave-uniform.
+__device__ __forceinline__ int stamp_levels(const WalkArgs& A, int E, int lane) {
+    const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+    int pend = -1;
+    for (int l = 0; l < A.n_levels; ++l) {
+        const int lv = A.level_E[l];
+        if (E <= lv) {
+            if (lane == 0) atomicMin(&A.hit_ticks[l], now);
+        } else {
+            pend = lv > pend ? lv : pend;
+        }
+    }
+    return __builtin_amdgcn_readfirstlane(pend);
+}
+// Copies the first-hit stamp request of an output struct into walker arguments
+// (n_levels, level_E, first_hit_ticks, start_ticks), validating it.
+template <class Out>
+inline labs_status set_stamps(WalkArgs& A, const Out& o) {
+    A.n_levels = 0;
+    A.hit_ticks = nullptr;
+    A.start_ticks = nullptr;
+    if (o.n_levels == 0) return LABS_OK;
+    if (o.n_levels < 0 || o.n_levels > LABS_MAX_LEVELS)
+        return invalid("n_levels must be in [0, %d], got %d", LABS_MAX_LEVELS, o.n_levels);
+    if (!o.first_hit_ticks) return invalid("first_hit_ticks must not be NULL when n_levels > 0");
+    A.n_levels = o.n_levels;
+    for (int l = 0; l < LABS_MAX_LEVELS; ++l) A.level_E[l] = l < o.n_levels ? o.level_E[l] : -1;
+    A.hit_ticks = (unsigned long long*)o.first_hit_ticks;
+    A.start_ticks = (unsigned long long*)o.start_ticks;
+    return LABS_OK;
+}
+__device__ __forceinline__ int pending_level(const WalkArgs& A) {
+    int pend = -1;
+    for (int l = 0; l < A.n_levels; ++l) pend = A.level_E[l] > pend ? A.level_E[l] : pend;
+    return __builtin_amdgcn_readfirstlane(pend);
+}
 bool walk_shape_supported(int L, int p);
 size_t step2_workspace_bytes(const labs_step2_cfg& c, long long n_cand);
 bool step2_fits(const labs_step2_cfg& c, long long n_cand);   // hash-set slots fit int32 indices

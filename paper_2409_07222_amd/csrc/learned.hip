@@ -40,6 +40,11 @@ struct LwArgs {
     int32_t* tstep;
     int64_t* evals;
     int32_t* hit;
+    // first-hit stamps (n_levels = 0: off); hitmask [n] holds each walker's stamped levels
+    int32_t n_levels;
+    int32_t level_E[16];
+    unsigned long long* hit_ticks;
+    uint32_t* hitmask;
     const float* logits;
     uint16_t* X;
     int32_t* traj;
@@ -253,6 +258,17 @@ __global__ __launch_bounds__(64) void k_lw_step(LwArgs A) {
         A.evals[j] += ncand;
         A.tstep[j] = t;
         if (A.e_max >= 0 && newE <= A.e_max && A.hit[j] < 0) A.hit[j] = t;
+        if (A.n_levels > 0) {
+            const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+            uint32_t hm = A.hitmask[j];
+            const uint32_t hm0 = hm;
+            for (int l = 0; l < A.n_levels; ++l)
+                if (!((hm >> l) & 1u) && newE <= A.level_E[l]) {
+                    atomicMin(&A.hit_ticks[l], now);
+                    hm |= 1u << l;
+                }
+            if (hm != hm0) A.hitmask[j] = hm;
+        }
         if (newE < bE0) {
             A.bestE[j] = newE;
             A.bestT[j] = t;
@@ -283,12 +299,13 @@ __global__ __launch_bounds__(64) void k_lw_step(LwArgs A) {
     }
 }
 
-__global__ void k_lw_init(int64_t n, int32_t* tstep, int64_t* evals, int32_t* hit) {
+__global__ void k_lw_init(int64_t n, int32_t* tstep, int64_t* evals, int32_t* hit, uint32_t* hitmask) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         tstep[i] = 0;
         evals[i] = 0;
         hit[i] = -1;
+        hitmask[i] = 0;
     }
 }
 
@@ -363,6 +380,7 @@ LwBuffers carve_lw(const labs_step1_cfg& c, const labs_proposer& pr, const labs_
     a.tstep = cv.take<int32_t>(n);
     a.evals = cv.take<int64_t>(n);
     a.hit = cv.take<int32_t>(n);
+    a.hitmask = cv.take<uint32_t>(n);
     if (lay) {
         a.X = cv.take<uint16_t>((size_t)n * lay->ld_in);
         a.logits = cv.take<float>((size_t)n * lay->ld_out);
@@ -409,6 +427,13 @@ labs_status learned_walk(const labs_step1_cfg& c, const labs_proposer& pr, const
     A.log_seqs = o.log_seqs;
     A.log_mask = o.log_mask;
     A.log_label = o.log_label;
+    {
+        labs_status ss = set_stamps(B.wa, o);
+        if (ss != LABS_OK) return ss;
+        A.n_levels = B.wa.n_levels;
+        for (int l = 0; l < LABS_MAX_LEVELS; ++l) A.level_E[l] = B.wa.level_E[l];
+        A.hit_ticks = B.wa.hit_ticks;
+    }
     if (!mlp) {
         A.X = nullptr;
         A.logits = nullptr;
@@ -416,7 +441,8 @@ labs_status learned_walk(const labs_step1_cfg& c, const labs_proposer& pr, const
     const int64_t n = A.n;
     labs_status s = launch_walker_init(B.wa, st);
     if (s) return s;
-    hipLaunchKernelGGL(k_lw_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, A.tstep, A.evals, A.hit);
+    hipLaunchKernelGGL(k_lw_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, A.tstep, A.evals, A.hit,
+                       A.hitmask);
     LABS_LAUNCHED("k_lw_init");
 
     // One launch sequence per step; steps t with (t-1) mod F == 0 need no network pass.

@@ -55,6 +55,7 @@ __device__ void walker_init_body(const WalkArgs& A, int64_t j, Lds<10>& S) {
     const int64_t w = A.walker_begin + j;
     const int L = A.L, k = A.k, p = A.p;
     const uint64_t key = walker_key(A.seed, L, w);
+    if (A.start_ticks && lane == 0) atomicMin(A.start_ticks, __builtin_amdgcn_s_memrealtime());
     // s_i for i = 1..k+1 from stream outputs i-1; s_1 = +1 when p >= 1; Eq. (2) for the rest
     for (int i = lane; i < Lds<NW>::SV; i += 64) S.sv[i] = 0;
     __syncthreads();
@@ -107,6 +108,7 @@ __device__ void walker_init_body(const WalkArgs& A, int64_t j, Lds<10>& S) {
         A.bestE[j] = e;
         A.bestT[j] = 0;
     }
+    if (A.n_levels > 0 && e <= pending_level(A)) stamp_levels(A, e, lane);
 }
 
 __global__ __launch_bounds__(64) void k_walker_init(WalkArgs A) {

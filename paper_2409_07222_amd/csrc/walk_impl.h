@@ -106,8 +106,10 @@ __device__ inline void store_tables(Lds<NW>& S, int K, int lane, const int32_t* 
     }
 }
 
+// bfull: the last backward word holds a lag (k/2 > 32(NQ-1)); when it does not
+// (k = 64(NQ-1)+1 with NW odd), that word is zero for every slot and is skipped.
 template <int NW, int R>
-__device__ __forceinline__ void build_windows(const Lds<NW>& S, int p, int k, int lane,
+__device__ __forceinline__ void build_windows(const Lds<NW>& S, int p, int k, int lane, bool bfull,
                                               uint32_t (&F)[R][NW],
                                               uint32_t (&B)[R][(NW + 1) / 2]) {
     constexpr int NQ = (NW + 1) / 2;
@@ -127,8 +129,9 @@ __device__ __forceinline__ void build_windows(const Lds<NW>& S, int p, int k, in
         for (int w = 0; w < NW; ++w)
             F[r][w] = __builtin_amdgcn_alignbit(Vp[qf + w + 1], Vp[qf + w], hf);
 #pragma unroll
-        for (int w = 0; w < NQ; ++w)
+        for (int w = 0; w < NQ - 1; ++w)
             B[r][w] = __builtin_amdgcn_alignbit(VRp[qb + w + 1], VRp[qb + w], hb);
+        B[r][NQ - 1] = bfull ? __builtin_amdgcn_alignbit(VRp[qb + NQ], VRp[qb + NQ - 1], hb) : 0u;
     }
 }
 
@@ -197,6 +200,8 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
     const bool sieve = A.e_max >= 0;
     const int thr = A.e_max;
     const int64_t wid = A.walker_begin + j;
+    const bool bfull = (NW & 1) == 0 || (k >> 1) > 32 * (NQ - 1);   // always, for even NW
+    int pend = pending_level(A);          // first-hit stamps: largest level energy above E
     __syncthreads();
 
     // masks of lags m <= Mb for the backward-overlap count
@@ -230,7 +235,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi) {
             uint32_t F[RB][NW], B[RB][NQ];
-            build_windows<NW, RB>(S, p + 64 * RB * gi, k, lane, F, B);
+            build_windows<NW, RB>(S, p + 64 * RB * gi, k, lane, bfull, F, B);
             int32_t H[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) H[r] = 0;
@@ -246,8 +251,13 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
                     for (int r = 0; r < RB; ++r) {
                         acc[r] += __popc(lo & F[r][2 * q]);
                         if (2 * q + 1 < NW) acc[r] += __popc(hi & F[r][2 * q + 1]);
-                        if (2 * q < NQ) acc[r] += __popc(lo & B[r][2 * q]);
-                        if (2 * q + 1 < NQ) acc[r] += __popc(hi & B[r][2 * q + 1]);
+                        if (2 * q < NQ - 1) acc[r] += __popc(lo & B[r][2 * q]);
+                        if (2 * q + 1 < NQ - 1) acc[r] += __popc(hi & B[r][2 * q + 1]);
+                    }
+                    if ((2 * q == NQ - 1 || 2 * q + 1 == NQ - 1) && bfull) {
+                        const uint32_t hl = (2 * q == NQ - 1) ? lo : hi;
+#pragma unroll
+                        for (int r = 0; r < RB; ++r) acc[r] += __popc(hl & B[r][NQ - 1]);
                     }
                 }
                 const int wgt = (jp == nb - 1) ? -(1 << jp) : (1 << jp);
@@ -260,7 +270,8 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
 #pragma unroll
                 for (int w = 0; w < NW; ++w) pf += __popc(F[r][w]);
 #pragma unroll
-                for (int w = 0; w < NQ; ++w) pf += __popc(B[r][w]);
+                for (int w = 0; w < NQ - 1; ++w) pf += __popc(B[r][w]);
+                if (bfull) pf += __popc(B[r][NQ - 1]);
                 H[r] = 2 * H[r] + pf;
             }
 #pragma unroll
@@ -280,7 +291,8 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
                     const int sbv = S.sv[PADL + L + 1 - a];
                     int X = 0;
 #pragma unroll
-                    for (int w = 0; w < NQ; ++w) X += __popc((F[rr][w] ^ B[rr][w]) & QM[r][w]);
+                    for (int w = 0; w < NQ - 1; ++w) X += __popc((F[rr][w] ^ B[rr][w]) & QM[r][w]);
+                    if (bfull) X += __popc((F[rr][NQ - 1] ^ B[rr][NQ - 1]) & QM[r][NQ - 1]);
                     const int G = 2 * H[rr] - S.PC[Mf] - S.PC[Mb] - S.Cev[mp] * sbv;
                     const int corr = (mp <= Mb) ? 2 * sbv * S.sv[PADL + a - 2 * mp] : 0;
                     const int Q = Mf - 1 + 3 * Mb - 4 * X - corr;
@@ -397,6 +409,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
             if (lane < W) S.pkbest[lane] = S.pk[lane];
         }
         if (A.traj && lane == 0) A.traj[j * A.steps_total + (t - 1)] = E;
+        if (E <= pend) pend = stamp_levels(A, E, lane);
         if (sieve && E <= thr) {
             uint32_t slot = 0;
             if (lane == 0) slot = atomicAdd(A.st_count, 1u);

@@ -50,11 +50,16 @@ class Pool(ctypes.Structure):
                 ("count", ctypes.c_void_p), ("dropped", ctypes.c_void_p)]
 
 
+MAX_LEVELS = 16
+_STAMP_FIELDS = [("n_levels", ctypes.c_int32), ("level_E", ctypes.c_int32 * MAX_LEVELS),
+                 ("first_hit_ticks", ctypes.c_void_p), ("start_ticks", ctypes.c_void_p)]
+
+
 class Step1Out(ctypes.Structure):
     _fields_ = [("final_seqs", ctypes.c_void_p), ("final_E", ctypes.c_void_p),
                 ("best_seqs", ctypes.c_void_p), ("best_E", ctypes.c_void_p),
                 ("best_step", ctypes.c_void_p), ("traj_E", ctypes.c_void_p),
-                ("flip_evals", ctypes.c_void_p)]
+                ("flip_evals", ctypes.c_void_p)] + _STAMP_FIELDS
 
 
 class Step2Cfg(ctypes.Structure):
@@ -96,7 +101,43 @@ class Proposer(ctypes.Structure):
 class LearnedOut(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in (
         "final_seqs", "final_E", "best_seqs", "best_E", "best_step", "hit_step", "traj_E", "moves",
-        "cands", "log_seqs", "log_mask", "log_label", "flip_evals")]
+        "cands", "log_seqs", "log_mask", "log_label", "flip_evals")] + _STAMP_FIELDS
+
+
+class Stamps:
+    """First-hit stamps of the device real-time counter: pass one object to
+    several calls to accumulate over them.  ticks[l] is the counter's value when
+    a walker first reached E <= level_E[l] (2^64 - 1: never), start the earliest
+    walker-init start; seconds() converts to seconds since start."""
+
+    def __init__(self, level_E, device="cuda"):
+        torch = _torch()
+        if not 1 <= len(level_E) <= MAX_LEVELS:
+            raise LabsError("1..%d levels" % MAX_LEVELS)
+        self.level_E = [int(e) for e in level_E]
+        self.ticks = torch.full((len(level_E),), -1, dtype=torch.int64, device=device)
+        self.start = torch.full((1,), -1, dtype=torch.int64, device=device)
+
+    def fill(self, out):
+        out.n_levels = len(self.level_E)
+        for i, e in enumerate(self.level_E):
+            out.level_E[i] = e
+        out.first_hit_ticks = self.ticks.data_ptr()
+        out.start_ticks = self.start.data_ptr()
+
+    def seconds(self):
+        """Per level, seconds from the earliest start to the first hit (None: no hit)."""
+        hz = realtime_hz()
+        t = [x & 0xFFFFFFFFFFFFFFFF for x in self.ticks.cpu().tolist()]
+        s0 = self.start.cpu().tolist()[0] & 0xFFFFFFFFFFFFFFFF
+        return [None if x == 0xFFFFFFFFFFFFFFFF else (x - s0) / hz for x in t]
+
+
+def realtime_hz() -> int:
+    """labs_realtime_hz: ticks per second of the stamps' counter on the current device."""
+    v = ctypes.c_int64(0)
+    _check(lib().labs_realtime_hz(ctypes.byref(v)))
+    return int(v.value)
 
 
 PROPOSE_MLP = 0
@@ -118,6 +159,8 @@ def lib():
             L.labs_last_error.restype = ctypes.c_char_p
             L.labs_words.restype = i32
             L.labs_words.argtypes = [i32]
+            L.labs_realtime_hz.restype = i32
+            L.labs_realtime_hz.argtypes = [ctypes.POINTER(i64)]
             L.labs_energy.restype = i32
             L.labs_energy.argtypes = [i32, i64, vp, vp, vp, vp]
             L.labs_flip_deltas.restype = i32
@@ -359,9 +402,10 @@ def walk_step1(L: int, p: int, steps: int, tenure_lo: int, tenure_hi: int, seed:
                n_walkers: int, walker_begin: int = 0, e_max: int = -1,
                pool: PoolBuffers | None = None, want_traj: bool = False,
                pool_walker_best: bool = False, device="cuda", workspace=None,
-               bloom: tuple | None = None) -> Step1Result:
+               bloom: tuple | None = None, stamps: Stamps | None = None) -> Step1Result:
     """labs_walk_step1 for one configuration; with bloom = (log2_bits, n_hash),
-    labs_walk_step1_bloom (tenure_lo = tenure_hi = 0)."""
+    labs_walk_step1_bloom (tenure_lo = tenure_hi = 0).  `stamps` (a Stamps)
+    receives the first-hit stamps of its levels."""
     torch = _torch()
     cfg = Step1Cfg(L, p, steps, tenure_lo, tenure_hi, e_max, walker_begin, n_walkers, seed,
                    LABS_POOL_WALKER_BEST if pool_walker_best else 0, 0)
@@ -389,6 +433,8 @@ def walk_step1(L: int, p: int, steps: int, tenure_lo: int, tenure_hi: int, seed:
     out = Step1Out(r.final_seqs.data_ptr(), r.final_E.data_ptr(), r.best_seqs.data_ptr(),
                    r.best_E.data_ptr(), r.best_step.data_ptr(),
                    r.traj_E.data_ptr() if want_traj else None, r.flip_evals.data_ptr())
+    if stamps is not None:
+        stamps.fill(out)
     ps = pool.struct() if pool is not None else None
     if bc is not None:
         _check(lib().labs_walk_step1_bloom(ctypes.byref(cfg), ctypes.byref(bc),
@@ -674,8 +720,9 @@ def learned_walk(L: int, p: int, steps: int, tenure_lo: int, tenure_hi: int, see
                  n_walkers: int, mode: int = PROPOSE_MLP, top_m: int = 8, fallback_every: int = 64,
                  hidden: int = 256, params=None, params_bf16=None, prop_seed: int = 0,
                  log_every: int = 0, e_max: int = -1, walker_begin: int = 0, want_traj: bool = False,
-                 want_cands: bool = False, device="cuda", workspace=None):
-    """labs_learned_walk; returns a dict of device tensors (and the workspace)."""
+                 want_cands: bool = False, device="cuda", workspace=None, stamps: Stamps | None = None):
+    """labs_learned_walk; returns a dict of device tensors (and the workspace).
+    `stamps` (a Stamps) receives the first-hit stamps of its levels."""
     torch = _torch()
     dev = torch.device(device)
     W = words(L)
@@ -707,7 +754,9 @@ def learned_walk(L: int, p: int, steps: int, tenure_lo: int, tenure_hi: int, see
         r["log_seqs"] = torch.empty((n_walkers * n_log, W), dtype=i32, device=dev)
         r["log_mask"] = torch.empty((n_walkers * n_log, mw), dtype=i32, device=dev)
         r["log_label"] = torch.empty(n_walkers * n_log, dtype=i32, device=dev)
-    out = LearnedOut(*[_ptr(r.get(name)).value for name, _ in LearnedOut._fields_])
+    out = LearnedOut(*[_ptr(r.get(name)).value for name, _ in LearnedOut._fields_[:-len(_STAMP_FIELDS)]])
+    if stamps is not None:
+        stamps.fill(out)
     _check(lib().labs_learned_walk(ctypes.byref(cfg), ctypes.byref(pr), ctypes.byref(out),
                                    _ptr(workspace), workspace.numel(), _stream(dev)))
     r["workspace"] = workspace
