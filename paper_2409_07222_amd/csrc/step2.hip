@@ -75,12 +75,19 @@ constexpr int kSubBits = 13;
 static_assert(kSelBits + kSubBits >= 27, "the sub-bins must cover (E - emin)/4 for L <= 1023");
 constexpr int kSelBins = 1 << kSelBits;
 // After the energy histogram, two 256-bin histograms of the top Zobrist-key byte of
-// the entries tied at the cut's energy (first) and at the pivots' energy (second).
+// the entries tied at the cut's energy (first) and at the pivots' energy (second),
+// in kZCopies copies (workgroup b adds into copy b mod kZCopies, so that few
+// workgroups add into one counter; the tie select sums the copies).
 constexpr int kZBins = 256;
-constexpr int kHistWords = kSelBins + 2 * kZBins;
+constexpr int kZCopies = 16;
+constexpr int kHistWords = kSelBins + kZCopies * 2 * kZBins;
 constexpr int kSelBlocks = 256;
 constexpr int kSelThreads = 512;
 constexpr int kGridBlocks = 1024;                    // grid-stride kernels over the Open list
+// The classify pass and the cut with as many workgroups as stay resident together
+// (two, three per CU at their register use), so that no workgroup waits for a slot.
+constexpr int kClassifyBlocks = 512;
+constexpr int kKeepBlocks = 768;
 constexpr int kMaxL = 1023;
 constexpr int kPad = 1024;
 constexpr int kSv = kMaxL + 2 * kPad + 2;
@@ -143,6 +150,9 @@ struct Ctl {
     // below the threshold byte are taken by the cut itself (flag bits 2 / 3 mark
     // the tied entries); 0 when unused.
     uint32_t zv, zv2;
+    // n_live and expansions as the round began (read by every workgroup of the
+    // histogram pass, whose workgroup 0 updates the live fields)
+    long long n_live0, expansions0;
 };
 
 // A pending insertion: the slot whose key matched, the source of the sequence
@@ -185,6 +195,7 @@ struct Params {
     uint32_t* pseq;        // [B*W] packed sequences of the round's pivots
     uint32_t* pseqn;       // [B*W] the next round's (written by the cut)
     int32_t* pivpos;       // [B] the next round's pivots' Open positions (the cut)
+    int32_t best_in_classify;   // rounds: the classify launch's extra workgroup finds an improving round's best
     int32_t take_pivots;   // the cut takes its pivots out of Open (rounds; not the seeding cut,
                            // whose pivots leave after the initial best is found)
     // MAKE_ROTATIONS: rotation q of pivot b sits at Open position batch_begin +
@@ -197,6 +208,8 @@ struct Params {
 };
 
 __device__ __forceinline__ uint64_t zob(int i) { return zobrist_at(i); }
+
+__device__ void best_scan(const Params& P, int initial);
 
 // Block-aggregated append: every thread of the block must call it (uniformly).
 __device__ long long block_append(long long* counter, bool take) {
@@ -252,6 +265,44 @@ __device__ long long block_append_n(long long* counter, int n) {
     return r;
 }
 
+// Two block-aggregated appends in one pass (every thread calls it uniformly):
+// *oa, *ob receive this thread's first positions in the two lists.
+__device__ void block_append2(long long* ca, int na, long long* cb, int nb, long long* oa, long long* ob) {
+    __shared__ int wa[16], wb[16];
+    __shared__ long long ba, bbq;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    int x = na, y = nb;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(x, o, 64), v = __shfl_up(y, o, 64);
+        if (lane >= o) {
+            x += u;
+            y += v;
+        }
+    }
+    if (lane == 63) {
+        wa[wv] = x;
+        wb[wv] = y;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ra = 0, rb = 0;
+        for (int k = 0; k < nw; ++k) {
+            const int ta = wa[k], tb = wb[k];
+            wa[k] = ra;
+            wb[k] = rb;
+            ra += ta;
+            rb += tb;
+        }
+        ba = ra ? (long long)atomicAdd((unsigned long long*)ca, (unsigned long long)ra) : 0;
+        bbq = rb ? (long long)atomicAdd((unsigned long long*)cb, (unsigned long long)rb) : 0;
+    }
+    __syncthreads();
+    *oa = ba + wa[wv] + (x - na);
+    *ob = bbq + wb[wv] + (y - nb);
+    __syncthreads();
+}
+
 __device__ __forceinline__ void atomic_min_batch(Ctl* c, bool take, int32_t E) {
     const int mn = __ockl_wfred_min_i32(take ? E : INT32_MAX);
     if ((threadIdx.x & 63) == 0 && mn != INT32_MAX) atomicMin(&c->batch_minE, mn);
@@ -302,10 +353,16 @@ __device__ __forceinline__ int rot_shift(const Params& P, int q) { return q < P.
 // Word w of this round's new entry at offset j from batch_begin: a single flip
 // of a pivot, or (past every flip) a rotation of one.
 __device__ __forceinline__ uint32_t new_word(const Params& P, long long j, int w) {
+    // from the round's compact copy of its pivots' words
     const long long nf = P.ctl->n_piv * P.L;
-    if (j < nf) return src_word(P, P.piv[j / P.L], (int)(j % P.L) + 1, w);
+    if (j < nf) {
+        const int flip = (int)(j % P.L) + 1;
+        uint32_t x = P.pseq[(size_t)(j / P.L) * P.W + w];
+        if (w == ((flip - 1) >> 5)) x ^= 1u << (31 - ((flip - 1) & 31));
+        return x;
+    }
     const long long jr = j - nf;
-    return rot_word(P.H.seq + (size_t)P.piv[jr / P.R2] * P.W, P.L, P.W, rot_shift(P, (int)(jr % P.R2)), w);
+    return rot_word(P.pseq + (size_t)(jr / P.R2) * P.W, P.L, P.W, rot_shift(P, (int)(jr % P.R2)), w);
 }
 
 // Word w of the sequence of Open entry o (table slot `slot`, or a new entry of
@@ -663,6 +720,8 @@ __device__ void round_begin(const Params& P, const int32_t* next_piv) {
     // in the list) and copied their slots and words
     if (c->n_pivpos > P.B) atomicExch(&c->error, 3);
     c->n_piv = c->n_pivpos < P.B ? c->n_pivpos : P.B;
+    c->n_live0 = c->n_live;
+    c->expansions0 = c->expansions;
     c->n_pend = 0;
     c->n_slow = 0;
     c->batch_begin = c->n_tot;
@@ -744,6 +803,107 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_hist(Params P) {
         if (h[b]) atomicAdd(&P.ghist[b], h[b]);
 }
 
+// The round's counts and the histogram in one launch.  Every workgroup reduces
+// the expansion's per-pivot counts and energy bounds and derives the round's
+// values (as k_round_mid and cut_setup do) from fields no workgroup writes here;
+// workgroup 0 stores them in the control block; then the energy histogram of the
+// live entries, as k_sel_hist.  (The best sequence of an improving round is found
+// by the classify pass.)
+struct MidVals {
+    long long n_tot, n_live, expansions, cnt, T2;
+    int32_t mn, mx, sel_all, dual, dual_all, sel_enabled;
+    uint32_t emin, emax;
+};
+
+__global__ __launch_bounds__(kSelThreads) void k_mid_hist(Params P) {
+    Ctl* c = P.ctl;
+    if (c->stop) return;
+    __shared__ long long s_cnt[kSelThreads / 64];
+    __shared__ int32_t s_min[kSelThreads / 64], s_max[kSelThreads / 64];
+    __shared__ MidVals m;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const long long np = c->n_piv;
+    long long cnt = 0;
+    int32_t mn = INT32_MAX, mx = 0;
+    for (long long b = t; b < np; b += blockDim.x) {
+        cnt += P.bcnt[b];
+        mn = P.bmin[b] < mn ? P.bmin[b] : mn;
+        mx = P.bmax[b] > mx ? P.bmax[b] : mx;
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    mn = __ockl_wfred_min_i32(mn);
+    mx = (int32_t)__ockl_wfred_max_u32((uint32_t)mx);
+    if (lane == 0) {
+        s_cnt[wv] = cnt;
+        s_min[wv] = mn;
+        s_max[wv] = mx;
+    }
+    __syncthreads();
+    if (t == 0) {
+        cnt = s_cnt[0];
+        mn = s_min[0];
+        mx = s_max[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            cnt += s_cnt[k];
+            mn = s_min[k] < mn ? s_min[k] : mn;
+            mx = s_max[k] > mx ? s_max[k] : mx;
+        }
+        m.cnt = cnt;
+        m.mn = mn;
+        m.mx = mx;
+        m.n_tot = c->batch_begin + np * (P.L + P.R2);
+        m.n_live = c->n_live0 - np + cnt;
+        m.expansions = c->expansions0 + np;
+        // cut_setup's decisions on the round's values
+        m.sel_all = m.n_live > P.Q ? 0 : 1;
+        long long T2 = P.X - m.expansions;
+        if (T2 > P.B) T2 = P.B;
+        const long long surv = m.sel_all ? m.n_live : P.Q;
+        m.T2 = T2;
+        m.dual = T2 > 0 ? 1 : 0;
+        m.dual_all = T2 >= surv ? 1 : 0;
+        m.sel_enabled = (!m.sel_all || (m.dual && !m.dual_all)) ? 1 : 0;
+        m.emin = (uint32_t)mn < c->blo ? (uint32_t)mn : c->blo;
+        m.emax = (uint32_t)mx > c->bhi ? (uint32_t)mx : c->bhi;
+        if (blockIdx.x == 0) {
+            c->n_tot = m.n_tot;
+            c->batch_minE = mn;
+            c->expansions = m.expansions;
+            c->n_live = m.n_live;
+            c->pushes += cnt;
+            c->dups += np * (P.L + P.R2) - cnt;
+            if (mn < c->best_E) c->improved = 1;
+            else c->u += np;
+            cut_setup(P);
+            c->emin = m.emin;
+            c->emax = m.emax;
+        }
+    }
+    __syncthreads();
+    if (!m.sel_enabled || m.emax == m.emin) return;
+    __shared__ uint32_t h[kSelBins];
+    const uint32_t R = (m.emax - m.emin) >> 2;
+    const int hs = R ? 32 - __clz((int)R) : 0;
+    const int ls = hs > kSelBits ? hs - kSelBits : 0;
+    const int nbins = 1 << (hs - ls);   // bins in use
+    for (int b = t; b < nbins; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    const int cur = c->which;
+    const uint32_t emin = m.emin;
+    const uint32_t dmask = (1u << (hs - ls)) - 1u;
+    for (long long i = (long long)blockIdx.x * blockDim.x + t; i < m.n_tot;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int32_t e = P.oE[cur][i];
+        if (e == DEAD) continue;
+        const uint32_t D = ((uint32_t)e - emin) >> 2;
+        if (hs < 32 && (D >> hs) != 0u) continue;
+        atomicAdd(&h[(D >> ls) & dmask], 1u);
+    }
+    __syncthreads();
+    for (int b = t; b < nbins; b += blockDim.x)
+        if (h[b]) atomicAdd(&P.ghist[b], h[b]);
+}
+
 // The cut from the histogram: the bin holding the T-th smallest entry (and, for a
 // dual cut, the T2-th).  A bin is resolved when bins are single values of D
 // (ls = 0); otherwise the bin [prefix << ls, (prefix + 1) << ls) is left to the tie
@@ -818,7 +978,15 @@ __device__ void find_cut(const Params& P, const Ctl* c, SelCut* out) {
 
 __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
     Ctl* c = P.ctl;
-    if (c->stop || !c->sel_enabled) return;
+    if (c->stop) return;
+    // rounds launch one workgroup more: when the round improved on the best, it
+    // finds the round's best sequence among the new entries
+    const int nblk = P.best_in_classify ? (int)gridDim.x - 1 : (int)gridDim.x;
+    if ((int)blockIdx.x == nblk) {
+        if (c->improved) best_scan(P, 0);
+        return;
+    }
+    if (!c->sel_enabled) return;
     __shared__ SelCut cut;
     find_cut(P, c, &cut);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -852,7 +1020,7 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
     __shared__ uint32_t zh[2 * kZBins];
     for (int b = threadIdx.x; b < 2 * kZBins; b += blockDim.x) zh[b] = 0;
     __syncthreads();
-    const long long stride = (long long)gridDim.x * blockDim.x * kItems;
+    const long long stride = (long long)nblk * blockDim.x * kItems;
     for (long long base = (long long)blockIdx.x * blockDim.x * kItems; base < n_tot; base += stride) {
         bool tie[kItems], tie2[kItems];
         int cnt = 0, cnt2 = 0;
@@ -898,7 +1066,9 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
             cnt += tie[k] ? 1 : 0;
             cnt2 += tie2[k] ? 1 : 0;
         }
-        long long o = block_append_n(&c->out_count, cnt);
+        long long o, o2;
+        if (dual && !dual_all) block_append2(&c->out_count, cnt, &c->out_count2, cnt2, &o, &o2);   // uniform
+        else o = block_append_n(&c->out_count, cnt);
 #pragma unroll
         for (int k = 0; k < kItems; ++k)
             if (tie[k]) {
@@ -910,7 +1080,6 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
                 ++o;
             }
         if (dual && !dual_all) {   // uniform
-            long long o2 = block_append_n(&c->out_count2, cnt2);
 #pragma unroll
             for (int k = 0; k < kItems; ++k)
                 if (tie2[k]) {
@@ -924,8 +1093,9 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
         }
     }
     __syncthreads();
+    uint32_t* zcopy = P.ghist + kSelBins + (blockIdx.x % kZCopies) * 2 * kZBins;
     for (int b = threadIdx.x; b < 2 * kZBins; b += blockDim.x)
-        if (zh[b]) atomicAdd(&P.ghist[kSelBins + b], zh[b]);
+        if (zh[b]) atomicAdd(&zcopy[b], zh[b]);
 }
 
 // Tie digits of Open entry o: bytes 0..7 are its Zobrist key (most significant
@@ -1071,8 +1241,11 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         // byte v comes from that histogram, the tied entries below it are taken by
         // the cut itself (zv / zv2, flag bits 2 / 3), and one pass over the tied
         // entries keeps those of byte v.
-        const uint32_t* zhg = P.ghist + kSelBins + kZBins * which;
-        if (t < 256) h[t] = zhg[t];
+        if (t < kZBins) {
+            uint32_t v = 0;
+            for (int cp = 0; cp < kZCopies; ++cp) v += P.ghist[kSelBins + cp * 2 * kZBins + kZBins * which + t];
+            h[t] = v;
+        }
         if (t == 0) s_m2 = 0;
         __syncthreads();
         if (t < 64) {
@@ -1392,12 +1565,14 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
     constexpr int NVW = 2 * NW2 + 8;
     __shared__ uint32_t V[NVW], VR[NVW], pk[32];
     __shared__ int32_t Cl[32 * NW2 + 1], PC[32 * NW2 + 1];
-    __shared__ unsigned long long hpart[kExThreads / 64];
     __shared__ uint8_t srep[32 * NW2 + 4];   // flip i repeats a lower-numbered pivot's neighbour
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int L = P.L, W = P.W;
     const int ps = P.piv[blockIdx.x];
     const int32_t Ep = P.H.rec[ps].E;
+    // the pivot's Zobrist key as stored with its slot (lowest bit forced to 1, which
+    // the neighbours' keys force as well)
+    const unsigned long long hp = P.H.rec[ps].key;
     const uint32_t* pw = P.pseq + (size_t)blockIdx.x * W;
     // V bit j = digit of s_{j+1} (LSB first): word w is the bit-reversed packed word;
     // VR (reversal over N = 32W bits): word W-1-w is the packed word itself.
@@ -1418,18 +1593,31 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
     // positions where they differ (p_b (+) e_i = p_q (+) e_i' with i' the other).
     // Of every repeated sequence the copy of the lowest-numbered pivot is kept, so
     // pivot b compares itself with every q < b.
-    for (int q = tid; q < (int)blockIdx.x; q += kExThreads) {
-        const uint32_t* row = P.pseq + (size_t)q * W;
-        int d = 0;
-        for (int w = 0; w < W; ++w) d += __popc(row[w] ^ pk[w]);
-        if (d != 2) continue;
-        for (int w = 0; w < W; ++w) {
-            uint32_t x = row[w] ^ pk[w];
-            while (x) {
-                const int k = __clz((int)x);
-                const int pos = 32 * w + k + 1;   // 1-based position, MSB first
-                if (pos <= L) srep[pos - 1] = 1;
-                x &= ~(0x80000000u >> k);
+    // The first words of four rows are loaded together; a pair whose first words
+    // alone differ in more than 2 places is not at distance 2.
+    constexpr int kRepU = 4;
+    for (int q0 = tid; q0 < (int)blockIdx.x; q0 += kRepU * kExThreads) {
+        uint32_t f0[kRepU];
+#pragma unroll
+        for (int u = 0; u < kRepU; ++u) {
+            const int q = q0 + u * kExThreads;
+            f0[u] = q < (int)blockIdx.x ? P.pseq[(size_t)q * W] : ~pk[0];
+        }
+#pragma unroll
+        for (int u = 0; u < kRepU; ++u) {
+            if (__popc(f0[u] ^ pk[0]) > 2) continue;
+            const uint32_t* row = P.pseq + (size_t)(q0 + u * kExThreads) * W;
+            int d = 0;
+            for (int w = 0; w < W; ++w) d += __popc(row[w] ^ pk[w]);
+            if (d != 2) continue;
+            for (int w = 0; w < W; ++w) {
+                uint32_t x = row[w] ^ pk[w];
+                while (x) {
+                    const int k = __clz((int)x);
+                    const int pos = 32 * w + k + 1;   // 1-based position, MSB first
+                    if (pos <= L) srep[pos - 1] = 1;
+                    x &= ~(0x80000000u >> k);
+                }
             }
         }
     }
@@ -1462,14 +1650,7 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
             carry += __shfl(v, 63, 64);
         }
     }
-    unsigned long long hz = 0;
-    for (int x = 1 + tid; x <= L; x += kExThreads)
-        if ((pk[(x - 1) >> 5] >> (31 - ((x - 1) & 31))) & 1u) hz ^= zob(x - 1);
-    for (int o = 32; o > 0; o >>= 1) hz ^= __shfl_xor(hz, o, 64);
-    if (lane == 0) hpart[wv] = hz;
     __syncthreads();
-    unsigned long long hp = 0;
-    for (int k = 0; k < kExThreads / 64; ++k) hp ^= hpart[k];
     // the neighbours' keys, and their home slots' tags loaded now: the loads land
     // while the energies are computed
     unsigned long long nkey[R2];
@@ -1839,8 +2020,8 @@ __device__ void best_scan(const Params& P, int initial) {
     }
     best[threadIdx.x] = mine;
     __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
+    for (int o = (int)blockDim.x >> 1; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) {
             const long long x = best[threadIdx.x], y = best[threadIdx.x + o];
             if (x < 0 || (y >= 0 && entry_less(P, cur, y, x))) best[threadIdx.x] = y;
         }
@@ -1890,75 +2071,88 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
     for (long long base = (long long)blockIdx.x * blockDim.x * kKeepItems; base < n_tot; base += stride) {
         int slot[kKeepItems];
         bool keep[kKeepItems];
+        int32_t ev[kKeepItems];
+        uint32_t fv[kKeepItems];
+        unsigned long long zk[kKeepItems];
         int cnt = 0;
+        // every load of the pass first
 #pragma unroll
         for (int k = 0; k < kKeepItems; ++k) {
             const long long i = base + threadIdx.x + (long long)k * blockDim.x;
-            keep[k] = false;
-            slot[k] = -1;
-            if (i < n_tot && P.oE[cur][i] != DEAD) {
-                const uint32_t f = P.flag[i];
-                // tied at the cut's energy below the threshold key byte: taken
-                keep[k] = !cut || (f & 1u) || ((f & 4u) && (uint32_t)(P.oZ[cur][i] >> 56) < zv);
-                slot[k] = P.oS[cur][i];
-                if (slot[k] >= 0) {
-                    if (!keep[k]) H.rec[slot[k]].state = ST_EVICTED;
-                } else if (keep[k]) {
-                    // A surviving new entry enters H: its tombstone is re-opened, or
-                    // an empty slot is claimed.  A slot already holding its key holds
-                    // another sequence (an equal sequence would have been found by
-                    // the expansion's probe, and surviving new entries are distinct).
-                    const long long j = i - bb;
-                    const unsigned long long key = P.oZ[cur][i];
-                    if (P.ntomb[j] >= 0) {
-                        slot[k] = P.ntomb[j];
-                        H.rec[slot[k]].state = ST_OPEN;
-                    } else {
-                        uint64_t s2 = key & H.mask;
-                        for (uint64_t probe = 0; probe <= H.mask; ++probe, s2 = (s2 + 1) & H.mask)
-                            if (atomicCAS(&H.rec[s2].key, 0ull, key) == 0ull) {
-                                slot[k] = (int)s2;
-                                H.tag[s2] = tag_of(key);
-                                break;
-                            }
-                        if (slot[k] < 0) {
-                            atomicExch(&c->error, 2);
-                            keep[k] = false;
-                        } else {
-                            for (int w = 0; w < H.W; ++w)
-                                H.seq[(size_t)slot[k] * H.W + w] = new_word(P, j, w);
-                            H.rec[slot[k]].E = P.oE[cur][i];
-                            H.rec[slot[k]].state = ST_OPEN;
-                            ++claims;
+            const bool in = i < n_tot;
+            ev[k] = in ? P.oE[cur][i] : DEAD;
+            fv[k] = in ? P.flag[i] : 0u;
+            slot[k] = in ? P.oS[cur][i] : -1;
+            zk[k] = in ? P.oZ[cur][i] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < kKeepItems; ++k) {
+            const long long i = base + threadIdx.x + (long long)k * blockDim.x;
+            const uint32_t f = fv[k];
+            keep[k] = ev[k] != DEAD && (!cut || (f & 1u) || ((f & 4u) && (uint32_t)(zk[k] >> 56) < zv));
+            if (ev[k] == DEAD) {
+                slot[k] = -1;
+            } else if (slot[k] >= 0) {
+                if (!keep[k]) H.rec[slot[k]].state = ST_EVICTED;
+            } else if (keep[k]) {
+                const long long j = i - bb;
+                const unsigned long long key = zk[k];
+                const int tomb = P.ntomb[j];
+                if (tomb >= 0) {
+                    slot[k] = tomb;
+                    H.rec[slot[k]].state = ST_OPEN;
+                } else {
+                    uint64_t s2 = key & H.mask;
+                    for (uint64_t probe = 0; probe <= H.mask; ++probe, s2 = (s2 + 1) & H.mask)
+                        if (atomicCAS(&H.rec[s2].key, 0ull, key) == 0ull) {
+                            slot[k] = (int)s2;
+                            H.tag[s2] = tag_of(key);
+                            break;
                         }
+                    if (slot[k] < 0) {
+                        atomicExch(&c->error, 2);
+                        keep[k] = false;
+                    } else {
+                        for (int w = 0; w < H.W; ++w)
+                            H.seq[(size_t)slot[k] * H.W + w] = new_word(P, j, w);
+                        H.rec[slot[k]].E = ev[k];
+                        H.rec[slot[k]].state = ST_OPEN;
+                        ++claims;
                     }
                 }
             }
             cnt += keep[k] ? 1 : 0;
         }
-        // the next round's pivots: every survivor (dual_all) or those of flag bit 1
+        // the next round's pivots: every survivor (dual_all) or those of flag bit 1.
+        // At most B per round, so they take their list places per wavefront (one
+        // atomic for each wavefront that holds some), not per workgroup.
         bool pv[kKeepItems];
-        int npv = 0;
+        long long opk[kKeepItems];
+        const int lane = threadIdx.x & 63;
+        const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
 #pragma unroll
         for (int k = 0; k < kKeepItems; ++k) {
-            const long long i = base + threadIdx.x + (long long)k * blockDim.x;
             if (dual && keep[k] && !dual_all) {
-                const uint32_t f = P.flag[i];
-                pv[k] = (f & 2u) || ((f & 8u) && (uint32_t)(P.oZ[cur][i] >> 56) < zv2);
+                const uint32_t f = fv[k];
+                pv[k] = (f & 2u) || ((f & 8u) && (uint32_t)(zk[k] >> 56) < zv2);
             } else {
                 pv[k] = dual && keep[k];
             }
-            npv += pv[k] ? 1 : 0;
+            const uint64_t pm = __ballot(pv[k]);
+            unsigned long long pb = 0;
+            if (pm && lane == __ffsll((unsigned long long)pm) - 1)
+                pb = atomicAdd((unsigned long long*)&c->n_pivpos, (unsigned long long)__popcll(pm));
+            pb = __shfl(pb, __ffsll((unsigned long long)pm) - 1, 64);
+            opk[k] = (long long)pb + __popcll(pm & lt);
         }
         long long o = block_append_n(&c->survivors, cnt);
-        long long op = dual ? block_append_n(&c->n_pivpos, npv) : 0;   // dual is uniform
 #pragma unroll
         for (int k = 0; k < kKeepItems; ++k) {
             if (!keep[k]) continue;
-            const long long i = base + threadIdx.x + (long long)k * blockDim.x;
-            P.oE[1 - cur][o] = P.oE[cur][i];
+            const long long op = opk[k];
+            P.oE[1 - cur][o] = ev[k];
             P.oS[1 - cur][o] = slot[k];
-            P.oZ[1 - cur][o] = P.oZ[cur][i];
+            P.oZ[1 - cur][o] = zk[k];
             if (pv[k]) {
                 // a pivot of the next round: out of Open (CLOSED, DEAD in the list),
                 // its slot and words copied for the expansion
@@ -1970,9 +2164,17 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
                         P.oE[1 - cur][o] = DEAD;
                         H.rec[sl].state = ST_CLOSED;
                     }
-                    for (int w = 0; w < H.W; ++w) P.pseqn[(size_t)op * H.W + w] = H.seq[(size_t)sl * H.W + w];
+                    // the words loaded together (W <= 32), then stored
+                    for (int w0 = 0; w0 < H.W; w0 += 16) {
+                        uint32_t wv[16];
+#pragma unroll
+                        for (int w = 0; w < 16; ++w)
+                            wv[w] = w0 + w < H.W ? H.seq[(size_t)sl * H.W + w0 + w] : 0u;
+#pragma unroll
+                        for (int w = 0; w < 16; ++w)
+                            if (w0 + w < H.W) P.pseqn[(size_t)op * H.W + w0 + w] = wv[w];
+                    }
                 }
-                ++op;
             }
             ++o;
         }
@@ -2295,11 +2497,18 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     // Selection; rounds take their energy bounds from the control block instead
     // of a min/max pass.
     // dual: the round's cut, which may also select the next round's pivots
-    auto select = [&](bool minmax, bool dual) {
-        if (minmax) hipLaunchKernelGGL(k_sel_minmax, dim3(kSelBlocks), tS, 0, st, P);
-        hipLaunchKernelGGL(k_sel_hist, dim3(kSelBlocks), tS, 0, st, P);
-        hipLaunchKernelGGL(k_sel_classify, gS, tS, 0, st, P);
-        hipLaunchKernelGGL(k_sel_keys, dim3(dual ? 2 : 1), dim3(1024), 0, st, P);
+    // round: the round's counts come with the histogram pass, and the classify
+    // launch's extra workgroup finds an improving round's best
+    auto select = [&](bool minmax, bool round) {
+        P.best_in_classify = round ? 1 : 0;
+        if (round) {
+            hipLaunchKernelGGL(k_mid_hist, dim3(kSelBlocks), tS, 0, st, P);
+        } else {
+            if (minmax) hipLaunchKernelGGL(k_sel_minmax, dim3(kSelBlocks), tS, 0, st, P);
+            hipLaunchKernelGGL(k_sel_hist, dim3(kSelBlocks), tS, 0, st, P);
+        }
+        hipLaunchKernelGGL(k_sel_classify, dim3(kClassifyBlocks + (round ? 1 : 0)), tS, 0, st, P);
+        hipLaunchKernelGGL(k_sel_keys, dim3(2), dim3(1024), 0, st, P);
     };
 
     // seeding: insert the candidates (exact dedupe), cut to Q, best = minimum
@@ -2308,8 +2517,8 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     hipLaunchKernelGGL(k_resolve, gS, tS, 0, st, P);
     hipLaunchKernelGGL(k_slow, dim3(1), dim3(1), 0, st, P);
     hipLaunchKernelGGL(k_seed_fin, dim3(1), dim3(1), 0, st, P);
-    select(true, true);
-    hipLaunchKernelGGL(k_keep, gS, tS, 0, st, P);
+    select(true, false);
+    hipLaunchKernelGGL(k_keep, dim3(kKeepBlocks), tS, 0, st, P);
     hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, st, P, 0);
     hipLaunchKernelGGL(k_seed_best_setup, dim3(1), dim3(1), 0, st, P.ctl);
     hipLaunchKernelGGL(k_min_live, gS, tS, 0, st, P);
@@ -2343,9 +2552,8 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
             hipLaunchKernelGGL(k_rot_build, dim3((unsigned)cfg.batch), dim3(kRotThreads), 0, st, P);
             hipLaunchKernelGGL(k_rot_stage, dim3((unsigned)cfg.batch), dim3(kRotThreads), 0, st, P);
         }
-        hipLaunchKernelGGL(k_round_mid, dim3(1), dim3(1024), 0, st, P);
         select(false, true);
-        hipLaunchKernelGGL(k_keep, gS, tS, 0, st, P);
+        hipLaunchKernelGGL(k_keep, dim3(kKeepBlocks), tS, 0, st, P);
         hipLaunchKernelGGL(k_round_next, dim3(1), dim3(1), 0, st, P);
         LABS_LAUNCHED("step2 round");
         if ((r + 1) % kCheck == 0) {
