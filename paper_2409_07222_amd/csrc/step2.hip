@@ -40,12 +40,13 @@
 //
 // A round's launches: k_expand (repeats, then the single flips; the direct
 // expansion for long sequences adds k_clear_repeats and k_repeats), the rotation
-// kernels when T_r > 0, k_round_mid (counts, best, cut setup), k_sel_hist (radix
-// level), k_sel_classify (threshold bins, flags, tie lists, the tied entries' top
-// key bytes), k_sel_keys (the two tie selects), k_keep (the cut; it also takes the
-// next round's pivots out of Open: CLOSED in the table, their slots and words
-// copied to the next round's pivot arrays), k_round_next (end of this round,
-// start of the next).
+// kernels when T_r > 0, k_mid_hist (the round's counts and statistics, the cut
+// setup, the radix level), k_sel_classify (threshold bins, flags, tie lists, the
+// tied entries' top key bytes; in an improving round each workgroup's best
+// candidate), k_sel_keys (the two tie selects; a third workgroup takes an
+// improving round's best), k_keep (the cut; it also takes the next round's pivots
+// out of Open: CLOSED in the table, their slots and words copied to the next
+// round's pivot arrays), k_round_next (end of this round, start of the next).
 // The seeding insertions are exact and use no fences: a candidate walks its
 // probe sequence with 64-bit CAS on the key word; an empty slot is claimed, a
 // slot already holding its key makes the candidate "pending".  After the kernel
@@ -153,6 +154,7 @@ struct Ctl {
     // n_live and expansions as the round began (read by every workgroup of the
     // histogram pass, whose workgroup 0 updates the live fields)
     long long n_live0, expansions0;
+    long long n_bestc;   // workgroups' candidates for an improving round's best (bestc)
 };
 
 // A pending insertion: the slot whose key matched, the source of the sequence
@@ -195,7 +197,8 @@ struct Params {
     uint32_t* pseq;        // [B*W] packed sequences of the round's pivots
     uint32_t* pseqn;       // [B*W] the next round's (written by the cut)
     int32_t* pivpos;       // [B] the next round's pivots' Open positions (the cut)
-    int32_t best_in_classify;   // rounds: the classify launch's extra workgroup finds an improving round's best
+    int32_t best_in_classify;   // rounds: an improving round's best is found by the classify pass and the tie select
+    int32_t* bestc;             // [kClassifyBlocks] each classify workgroup's least entry at the round's least energy
     int32_t take_pivots;   // the cut takes its pivots out of Open (rounds; not the seeding cut,
                            // whose pivots leave after the initial best is found)
     // MAKE_ROTATIONS: rotation q of pivot b sits at Open position batch_begin +
@@ -682,6 +685,7 @@ __device__ void cut_setup(const Params& P) {
     c->out_count = 0;
     c->zv = 0;
     c->zv2 = 0;
+    c->n_bestc = 0;
 }
 
 // next_piv: the table slots of the pivots the last cut took out of Open for the
@@ -805,10 +809,10 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_hist(Params P) {
 
 // The round's counts and the histogram in one launch.  Every workgroup reduces
 // the expansion's per-pivot counts and energy bounds and derives the round's
-// values (as k_round_mid and cut_setup do) from fields no workgroup writes here;
-// workgroup 0 stores them in the control block; then the energy histogram of the
-// live entries, as k_sel_hist.  (The best sequence of an improving round is found
-// by the classify pass.)
+// values (the statistics and cut_setup's decisions) from fields no workgroup
+// writes here; workgroup 0 stores them in the control block; then the energy
+// histogram of the live entries, as k_sel_hist.  (The best sequence of an
+// improving round is found by the classify pass and the tie select.)
 struct MidVals {
     long long n_tot, n_live, expansions, cnt, T2;
     int32_t mn, mx, sel_all, dual, dual_all, sel_enabled;
@@ -976,16 +980,77 @@ __device__ void find_cut(const Params& P, const Ctl* c, SelCut* out) {
     __syncthreads();
 }
 
+__device__ __forceinline__ bool entry_less(const Params& P, int cur, long long a, long long b);
+
+// This workgroup's least entry (by key, then sequence) among the round's new
+// entries of the round's least energy, in the classify pass's entry layout.
+__device__ void best_offer(const Params& P) {
+    Ctl* c = P.ctl;
+    __shared__ long long best[kSelThreads];
+    const int cur = c->which;
+    const int32_t target = c->batch_minE;
+    const long long lo = c->batch_begin, n_tot = c->n_tot;
+    long long mine = -1;
+    const long long stride = (long long)gridDim.x * blockDim.x * kItems;
+    for (long long base = (long long)blockIdx.x * blockDim.x * kItems; base < n_tot; base += stride)
+        for (int k = 0; k < kItems; ++k) {
+            const long long i = base + threadIdx.x + (long long)k * blockDim.x;
+            if (i < lo || i >= n_tot || P.oE[cur][i] != target) continue;
+            if (mine < 0 || entry_less(P, cur, i, mine)) mine = i;
+        }
+    best[threadIdx.x] = mine;
+    __syncthreads();
+    for (int o = (int)blockDim.x >> 1; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) {
+            const long long x = best[threadIdx.x], y = best[threadIdx.x + o];
+            if (x < 0 || (y >= 0 && entry_less(P, cur, y, x))) best[threadIdx.x] = y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && best[0] >= 0)
+        P.bestc[atomicAdd((unsigned long long*)&c->n_bestc, 1ull)] = (int32_t)best[0];
+    __syncthreads();
+}
+
+// The tie select's third workgroup: the least offer becomes the best.
+__device__ void best_take(const Params& P) {
+    Ctl* c = P.ctl;
+    __shared__ long long best[1024];
+    const int cur = c->which;
+    const long long n = c->n_bestc;
+    long long mine = -1;
+    for (long long q = threadIdx.x; q < n; q += blockDim.x) {
+        const long long i = P.bestc[q];
+        if (mine < 0 || entry_less(P, cur, i, mine)) mine = i;
+    }
+    best[threadIdx.x] = mine;
+    __syncthreads();
+    for (int o = (int)blockDim.x >> 1; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) {
+            const long long x = best[threadIdx.x], y = best[threadIdx.x + o];
+            if (x < 0 || (y >= 0 && entry_less(P, cur, y, x))) best[threadIdx.x] = y;
+        }
+        __syncthreads();
+    }
+    const long long b = best[0];
+    if (b >= 0 && threadIdx.x < (unsigned)P.W)
+        P.best_seq[threadIdx.x] = entry_word(P, P.oS[cur][b], b, threadIdx.x);
+    if (threadIdx.x == 0 && b >= 0) {
+        c->best_slot = 1;
+        c->best_E = c->batch_minE;
+        c->best_round = (int32_t)c->rounds;
+        c->u = 0;
+    }
+}
+
 __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
     Ctl* c = P.ctl;
     if (c->stop) return;
-    // rounds launch one workgroup more: when the round improved on the best, it
-    // finds the round's best sequence among the new entries
-    const int nblk = P.best_in_classify ? (int)gridDim.x - 1 : (int)gridDim.x;
-    if ((int)blockIdx.x == nblk) {
-        if (c->improved) best_scan(P, 0);
-        return;
-    }
+    const int nblk = (int)gridDim.x;
+    // a round that improved on the best: every workgroup offers its least (key,
+    // sequence) among its new entries at the round's least energy; the tie select
+    // takes the least of the offers
+    if (P.best_in_classify && c->improved) best_offer(P);
     if (!c->sel_enabled) return;
     __shared__ SelCut cut;
     find_cut(P, c, &cut);
@@ -1137,6 +1202,10 @@ constexpr int kTieU = 8;        // candidates loaded ahead per thread in the glo
 __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
     const int which = blockIdx.x;
     Ctl* c = P.ctl;
+    if (which == 2) {
+        if (!c->stop && P.best_in_classify && c->improved) best_take(P);
+        return;
+    }
     if (c->stop || !c->sel_enabled) return;
     if (which ? (!c->dual || c->dual_all) : c->sel_all) return;
     int32_t* const* CA = which ? P.cand2 : P.cand;
@@ -1938,61 +2007,6 @@ __global__ __launch_bounds__(kRotThreads) void k_rot_stage(Params P) {
 
 __device__ void best_scan(const Params& P, int initial);
 
-// After the expansion: the pushed count and least and greatest energy over the
-// pivots' blocks, the statistics, the capacity-cut setup, and the new best when
-// the round improved it.
-__global__ __launch_bounds__(1024) void k_round_mid(Params P) {
-    Ctl* c = P.ctl;
-    if (c->stop) return;
-    __shared__ long long s_cnt[16];
-    __shared__ int32_t s_min[16], s_max[16];
-    __shared__ int s_improved;
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    long long cnt = 0;
-    int32_t mn = INT32_MAX, mx = 0;
-    for (long long b = t; b < c->n_piv; b += blockDim.x) {
-        cnt += P.bcnt[b];
-        mn = P.bmin[b] < mn ? P.bmin[b] : mn;
-        mx = P.bmax[b] > mx ? P.bmax[b] : mx;
-    }
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-    mn = __ockl_wfred_min_i32(mn);
-    mx = (int32_t)__ockl_wfred_max_u32((uint32_t)mx);
-    if (lane == 0) {
-        s_cnt[wv] = cnt;
-        s_min[wv] = mn;
-        s_max[wv] = mx;
-    }
-    __syncthreads();
-    if (t == 0) {
-        cnt = s_cnt[0];
-        mn = s_min[0];
-        mx = s_max[0];
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
-            cnt += s_cnt[k];
-            mn = s_min[k] < mn ? s_min[k] : mn;
-            mx = s_max[k] > mx ? s_max[k] : mx;
-        }
-        c->n_tot = c->batch_begin + c->n_piv * (P.L + P.R2);
-        c->batch_minE = mn;
-        c->expansions += c->n_piv;
-        c->n_live -= c->n_piv;
-        const long long n_new = cnt;
-        c->pushes += n_new;
-        c->dups += c->n_piv * (P.L + P.R2) - n_new;
-        c->n_live += n_new;
-        if (c->batch_minE < c->best_E) c->improved = 1;
-        else c->u += c->n_piv;
-        // capacity cut setup; energy bounds: the live entries before the round
-        // and this round's pushes
-        cut_setup(P);
-        c->emin = (uint32_t)mn < c->blo ? (uint32_t)mn : c->blo;
-        c->emax = (uint32_t)mx > c->bhi ? (uint32_t)mx : c->bhi;
-        s_improved = c->improved;
-    }
-    __syncthreads();
-    if (s_improved) best_scan(P, 0);
-}
 
 // best = smallest (z, sequence) among live entries in [batch_begin, n_tot) with
 // E == batch_minE.
@@ -2401,6 +2415,7 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     t += 2 * align_up(sizeof(unsigned long long) * lo.cap_o, 256);     // candz2
     t += 2 * align_up(sizeof(int32_t) * c.batch, 256);                 // piv, this round's and the next's
     t += align_up(sizeof(int32_t) * c.batch, 256);                     // pivpos
+    t += align_up(sizeof(int32_t) * kClassifyBlocks, 256);             // best candidates
     t += align_up(sizeof(uint32_t) * kHistWords, 256);                 // select histograms
     t += align_up(sizeof(uint32_t) * 32, 256);                         // best sequence
     t += 2 * align_up(sizeof(Pend) * lo.cap_pend, 256);                // pending, collisions
@@ -2471,6 +2486,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     for (int b = 0; b < 2; ++b) P.cand2[b] = cv.take<int32_t>(lo.cap_o);
     for (int b = 0; b < 2; ++b) P.candz2[b] = cv.take<unsigned long long>(lo.cap_o);
     P.pivpos = cv.take<int32_t>(cfg.batch);
+    P.bestc = cv.take<int32_t>(kClassifyBlocks);
     int32_t* pivb[2];
     for (int b = 0; b < 2; ++b) pivb[b] = cv.take<int32_t>(cfg.batch);
     // round r expands the pivots of buffer r & 1; its cut writes those of round r + 1
@@ -2507,8 +2523,8 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
             if (minmax) hipLaunchKernelGGL(k_sel_minmax, dim3(kSelBlocks), tS, 0, st, P);
             hipLaunchKernelGGL(k_sel_hist, dim3(kSelBlocks), tS, 0, st, P);
         }
-        hipLaunchKernelGGL(k_sel_classify, dim3(kClassifyBlocks + (round ? 1 : 0)), tS, 0, st, P);
-        hipLaunchKernelGGL(k_sel_keys, dim3(2), dim3(1024), 0, st, P);
+        hipLaunchKernelGGL(k_sel_classify, dim3(kClassifyBlocks), tS, 0, st, P);
+        hipLaunchKernelGGL(k_sel_keys, dim3(round ? 3 : 2), dim3(1024), 0, st, P);
     };
 
     // seeding: insert the candidates (exact dedupe), cut to Q, best = minimum
