@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--no-counters", action="store_true",
                     help="skip the rocprofv3 counter pass of the walk kernel (the hardware roofline "
                          "fraction and HBM traffic are then null)")
-    ap.add_argument("--counter-probe", default="", choices=["", "walk"],
+    ap.add_argument("--counter-probe", default="", choices=["", "walk", "step2"],
                     help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference "
@@ -111,11 +111,12 @@ def copy_calibration(mib: int):
 # count, PROBE_STEPS steps, one launch) that this script runs as a child process
 # before it touches the GPU itself.
 PROBE_STEPS = 1024
+PROBE_S2_EXPANSIONS = 500_000
 PROBE_SQ = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_LDS_LOAD_BANDWIDTH",
             "SQ_INSTS_LDS_STORE_BANDWIDTH", "SQ_INSTS_LDS_ATOMIC_BANDWIDTH", "SQ_ACTIVE_INST_VALU"]
 # copy-calibrated scale of the L2 counters (a plain device copy of known size
 # reads FETCH_SIZE = half the bytes it reads and WRITE_SIZE = the bytes it writes;
-# profiles/walk_L501_hbm_counters.txt)
+# profiles/walk_L501_counters.txt)
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 # gfx950 LDS: 128 bytes per clock per CU
 PEAK_LDS_BYTES = 256 * 128 * 2.4e9
@@ -128,6 +129,25 @@ def counter_probe(a):
     labs.walk_step1(L, P, PROBE_STEPS, L // 10, L // 5, 4, a.walkers)
     torch.cuda.synchronize()
     print(json.dumps({"walker_steps": a.walkers * PROBE_STEPS}), flush=True)
+
+
+def counter_probe_step2(a):
+    """The second step of the benchmark's shape (batch, queue capacity, seeds: the
+    top-1024 of a shorter pooled walk at L = 501) for PROBE_S2_EXPANSIONS pops,
+    for rocprofv3 counter and trace runs of the second step's kernels alone."""
+    import torch
+    from paper_2409_07222_amd import labs
+    pool = labs.PoolBuffers.empty(L, 1 << 20)
+    labs.walk_step1(L, P, 6000, L // 10, L // 5, 4, a.walkers, e_max=(L * L) // 16,
+                    pool=pool, pool_walker_best=True)
+    s, _ = labs.pool_topk(pool, 1024)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = labs.refine_step2(L, s.contiguous(), a.s2_batch, a.s2_capacity, PROBE_S2_EXPANSIONS, 1 << 62)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"rounds": g["rounds"], "us_per_round": dt / g["rounds"] * 1e6,
+                      "pushes": g["pushes"], "best_E": g["best_E"]}), flush=True)
 
 
 def _rocprof_walk(counters, walkers):
@@ -653,6 +673,9 @@ def main():
     a = parse()
     if a.copy_calibration:
         copy_calibration(a.copy_calibration)
+        return
+    if a.counter_probe == "step2":
+        counter_probe_step2(a)
         return
     if a.counter_probe:
         counter_probe(a)
