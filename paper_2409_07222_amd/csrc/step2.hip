@@ -2554,6 +2554,31 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     // the next round's pivots out of Open), then the end of the round together
     // with the start of the next.
     hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, P);
+    // the control block's flags as copied after every kCheck rounds (pinned, two
+    // batches in turn), and the claims last read
+    struct ChkFlags {
+        int32_t stop, error;
+        long long claimed;
+    };
+    struct ChkRes {
+        hipStream_t st = nullptr;
+        ChkFlags* h = nullptr;
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        ~ChkRes() {
+            // copies into h may still be queued when the search ends early
+            if (h && hipStreamSynchronize(st) == hipSuccess) (void)hipHostFree(h);
+            for (hipEvent_t e : ev)
+                if (e) (void)hipEventDestroy(e);
+        }
+    } chk_res;
+    chk_res.st = st;
+    LABS_HIP(hipHostMalloc((void**)&chk_res.h, 2 * sizeof(ChkFlags), hipHostMallocDefault));
+    for (int b = 0; b < 2; ++b) LABS_HIP(hipEventCreateWithFlags(&chk_res.ev[b], hipEventDisableTiming));
+    ChkFlags* hflags = chk_res.h;
+    hipEvent_t* chk = chk_res.ev;
+    const long long BLr = (long long)cfg.batch * (cfg.L + 2 * cfg.T_r);   // claims of one round at most
+    long long claimed_seen = n_cand;
+    int inflight = -1;
     for (long long r = 0;; ++r) {
         set_round(r);
         if (P.direct) {
@@ -2573,17 +2598,41 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
         hipLaunchKernelGGL(k_round_next, dim3(1), dim3(1), 0, st, P);
         LABS_LAUNCHED("step2 round");
         if ((r + 1) % kCheck == 0) {
-            int32_t flags[2];
-            long long claimed = 0;
-            LABS_HIP(hipMemcpyAsync(flags, &P.ctl->stop, sizeof(flags), hipMemcpyDeviceToHost, st));
-            LABS_HIP(hipMemcpyAsync(&claimed, &P.ctl->claimed, sizeof(claimed), hipMemcpyDeviceToHost, st));
-            LABS_HIP(hipStreamSynchronize(st));
-            if (flags[1]) {
-                set_error("second-step hash set failure (code %d)", flags[1]);
+            // This batch's flags are copied; the host reads the previous batch's,
+            // so the stream always holds a batch of rounds ahead of the host.
+            // Rounds enqueued after the stop return at once.  A rebuild decided on
+            // flags a batch old would come later than one decided now, so when
+            // the claims could reach half the table within the unread batches the
+            // host reads this batch's flags at once instead.
+            const int slot = (int)(((r + 1) / kCheck) & 1);
+            LABS_HIP(hipMemcpyAsync(&hflags[slot].stop, &P.ctl->stop, 2 * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, st));
+            LABS_HIP(hipMemcpyAsync(&hflags[slot].claimed, &P.ctl->claimed, sizeof(long long),
+                                    hipMemcpyDeviceToHost, st));
+            LABS_HIP(hipEventRecord(chk[slot], st));
+            const bool now = (uint64_t)(claimed_seen + 3LL * kCheck * BLr) * 2 >= lo.cap_ht;
+            int look;
+            if (now) {
+                look = slot;
+                inflight = -1;
+            } else if (inflight >= 0) {
+                look = inflight;
+                inflight = slot;
+            } else {
+                inflight = slot;
+                continue;
+            }
+            LABS_HIP(hipEventSynchronize(chk[look]));
+            const ChkFlags f = hflags[look];
+            if (f.error) {
+                set_error("second-step hash set failure (code %d)", f.error);
                 return LABS_E_DEVICE;
             }
-            if (flags[0]) break;
+            if (f.stop) break;
+            claimed_seen = f.claimed;
+            const long long claimed = f.claimed;
             if ((uint64_t)claimed * 2 >= lo.cap_ht) {
+                inflight = -1;   // its claims were counted before the rebuild
                 Table& dst = tabs[1 - tcur];
                 LABS_HIP(hipMemsetAsync(dst.rec, 0, sizeof(SlotRec) * lo.cap_ht, st));
                 LABS_HIP(hipMemsetAsync(dst.tag, 0, lo.cap_ht, st));

@@ -108,6 +108,11 @@ def test_walk_cfg1_trajectories(lb, orc):
     (301, 120, 40, 3, 6, 2),      # long prefix: 31 free positions in the smallest slot group
     (385, 12, 30, 38, 77, 2),     # k = 192: six even-lag words, three slot groups
     (387, 12, 30, 38, 77, 2),     # k = 193: one lag into a seventh word, still three groups
+    (389, 12, 30, 38, 77, 2),     # k = 194: two lags in the seventh word, backward word in use
+    (133, 4, 200, 13, 26, 4),     # k = 66: three words, two lags in the last, backward word in use
+    (141, 2, 200, 14, 28, 4),     # k = 70: six lags in the last word
+    (143, 2, 200, 14, 28, 4),     # k = 71: seven lags in the last word
+    (259, 8, 100, 25, 50, 2),     # k = 129: five words, one lag in the last
     (527, 16, 20, 52, 105, 2),    # k = 263: nine words, four slot groups
 ])
 def test_walk_shapes(lb, orc, L, p, steps, lo, hi, n):
