@@ -179,6 +179,10 @@ struct Params {
     unsigned long long* candz2[2];
     int32_t* piv;          // [B] table slots of this round's pivots
     int32_t* pivn;         // [B] the next round's (written by the cut; the host alternates the two)
+    int32_t* pivE;         // [B] energies of this round's pivots, and of the next round's
+    int32_t* pivEn;
+    unsigned long long* pivK;   // [B] their Zobrist keys (as stored with their slots)
+    unsigned long long* pivKn;
     uint32_t* ghist;       // [kHistWords]: energy bins, then the two key-byte histograms; zero between selections
     uint32_t* best_seq;    // [W] copy of the best sequence
     Pend* pend;            // [cap_pend]
@@ -433,11 +437,10 @@ __device__ __forceinline__ void push_pending(const Params& P, bool take, const P
 // DEAD when a lower-numbered pivot of the round produces the same sequence
 // (`repeated`) or when H holds its sequence as OPEN or CLOSED; otherwise it is a
 // new entry.  `taken`, `mn` and `mx` accumulate per thread.
-__device__ void stage_neighbour(const Params& P, bool valid, bool repeated, unsigned long long key, int ps,
-                                int flip, int32_t En, int& taken, int32_t& mn, int32_t& mx,
-                                int home_tag = -1) {
+__device__ void stage_neighbour(const Params& P, int cur, long long batch_begin, bool valid, bool repeated,
+                                unsigned long long key, int ps, int flip, int32_t En, int& taken,
+                                int32_t& mn, int32_t& mx, int home_tag = -1) {
     if (!valid) return;
-    Ctl* c = P.ctl;
     const long long j = (long long)blockIdx.x * P.L + (flip - 1);
     int tomb = -1;
     bool take = !repeated;
@@ -462,8 +465,7 @@ __device__ void stage_neighbour(const Params& P, bool valid, bool repeated, unsi
             break;
         }
     }
-    const int cur = c->which;
-    const long long o = c->batch_begin + j;
+    const long long o = batch_begin + j;
     if (!take) {
         P.oE[cur][o] = DEAD;
         return;
@@ -1572,6 +1574,8 @@ __global__ __launch_bounds__(kSelThreads) void k_clear_repeats(Params P) {
 __global__ __launch_bounds__(64) void k_expand_direct(Params P) {
     Ctl* c = P.ctl;
     if (c->stop || (long long)blockIdx.x >= c->n_piv) return;
+    const int cur = c->which;
+    const long long bb = c->batch_begin;
     __shared__ int8_t sv[kSv];
     __shared__ int32_t Cl[kMaxL + 1];
     __shared__ uint32_t pk[32];
@@ -1612,8 +1616,8 @@ __global__ __launch_bounds__(64) void k_expand_direct(Params P) {
             En = Ep - 4 * si * g + 4 * q;
             key = (hp ^ zob(i - 1)) | 1ull;
         }
-        stage_neighbour(P, valid, valid && P.repeat[(long long)blockIdx.x * L + (i - 1)], key, ps, i, En,
-                        taken, mn, mx);
+        stage_neighbour(P, cur, bb, valid, valid && P.repeat[(long long)blockIdx.x * L + (i - 1)], key, ps,
+                        i, En, taken, mn, mx);
     }
     stage_finish(P, taken, mn, mx);
 }
@@ -1628,8 +1632,14 @@ __global__ __launch_bounds__(64) void k_expand_direct(Params P) {
 // PC being the prefix sums of C_d.  C_d itself is (L-d) - 2 popc((V ^ V>>d) & [j < L-d]).
 template <int NW2, int R2>
 __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
-    Ctl* c = P.ctl;
-    if (c->stop || (long long)blockIdx.x >= c->n_piv) return;
+    // The pivot's slot, energy and key (as stored with its slot: lowest bit 1, as
+    // the neighbours' keys), its words and the lower-numbered pivots' first words
+    // come from the round's compact copies, in bounds for every workgroup of the
+    // launch: they are loaded before the control block says whether this
+    // workgroup has a pivot.
+    const int ps = P.piv[blockIdx.x];
+    const int32_t Ep = P.pivE[blockIdx.x];
+    const unsigned long long hp = P.pivK[blockIdx.x];
     constexpr int NQ2 = (NW2 + 1) / 2;      // chunks of 64 lags
     constexpr int NVW = 2 * NW2 + 8;
     __shared__ uint32_t V[NVW], VR[NVW], pk[32];
@@ -1637,23 +1647,26 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
     __shared__ uint8_t srep[32 * NW2 + 4];   // flip i repeats a lower-numbered pivot's neighbour
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int L = P.L, W = P.W;
-    const int ps = P.piv[blockIdx.x];
-    const int32_t Ep = P.H.rec[ps].E;
-    // the pivot's Zobrist key as stored with its slot (lowest bit forced to 1, which
-    // the neighbours' keys force as well)
-    const unsigned long long hp = P.H.rec[ps].key;
     const uint32_t* pw = P.pseq + (size_t)blockIdx.x * W;
+    static_assert(2 * NW2 + 8 <= kExThreads, "one word of V and VR per thread");
+    const uint32_t wx = tid < W ? pw[tid] : 0u, wy = tid < W ? pw[W - 1 - tid] : 0u;
+    constexpr int kRepU = 4;
+    uint32_t f0[kRepU];
+#pragma unroll
+    for (int u = 0; u < kRepU; ++u) {
+        const int q = tid + u * kExThreads;
+        f0[u] = q < (int)blockIdx.x ? P.pseq[(size_t)q * W] : 0u;
+    }
+    Ctl* c = P.ctl;
+    if (c->stop || (long long)blockIdx.x >= c->n_piv) return;
+    const int cur = c->which;
+    const long long bb = c->batch_begin;
     // V bit j = digit of s_{j+1} (LSB first): word w is the bit-reversed packed word;
     // VR (reversal over N = 32W bits): word W-1-w is the packed word itself.
-    for (int w = tid; w < NVW; w += kExThreads) {
-        uint32_t x = 0, y = 0;
-        if (w < W) {
-            x = pw[w];
-            pk[w] = x;
-            y = pw[W - 1 - w];
-        }
-        V[w] = __builtin_bitreverse32(x);
-        VR[w] = y;
+    if (tid < NVW) {
+        if (tid < W) pk[tid] = wx;
+        V[tid] = __builtin_bitreverse32(wx);
+        VR[tid] = wy;
     }
     for (int x = tid; x < 32 * NW2 + 4; x += kExThreads) srep[x] = 0;
     __syncthreads();
@@ -1662,19 +1675,20 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
     // positions where they differ (p_b (+) e_i = p_q (+) e_i' with i' the other).
     // Of every repeated sequence the copy of the lowest-numbered pivot is kept, so
     // pivot b compares itself with every q < b.
-    // The first words of four rows are loaded together; a pair whose first words
-    // alone differ in more than 2 places is not at distance 2.
-    constexpr int kRepU = 4;
+    // The first words of four rows are loaded together (those of the first pass at
+    // the start); a pair whose first words alone differ in more than 2 places is
+    // not at distance 2.
     for (int q0 = tid; q0 < (int)blockIdx.x; q0 += kRepU * kExThreads) {
-        uint32_t f0[kRepU];
+        if (q0 != tid) {
 #pragma unroll
-        for (int u = 0; u < kRepU; ++u) {
-            const int q = q0 + u * kExThreads;
-            f0[u] = q < (int)blockIdx.x ? P.pseq[(size_t)q * W] : ~pk[0];
+            for (int u = 0; u < kRepU; ++u) {
+                const int q = q0 + u * kExThreads;
+                f0[u] = q < (int)blockIdx.x ? P.pseq[(size_t)q * W] : 0u;
+            }
         }
 #pragma unroll
         for (int u = 0; u < kRepU; ++u) {
-            if (__popc(f0[u] ^ pk[0]) > 2) continue;
+            if (q0 + u * kExThreads >= (int)blockIdx.x || __popc(f0[u] ^ pk[0]) > 2) continue;
             const uint32_t* row = P.pseq + (size_t)(q0 + u * kExThreads) * W;
             int d = 0;
             for (int w = 0; w < W; ++w) d += __popc(row[w] ^ pk[w]);
@@ -1794,7 +1808,7 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
         const int G = 2 * H[r] - PC[Mf] - PC[Mb];
         const int Q = (L - 1) + 2 * (M - 2 * dis);
         const int32_t En = Ep - 4 * si * G + 4 * Q;
-        stage_neighbour(P, valid, srep[i - 1] != 0, nkey[r], ps, i, En, taken, mn, mx, htag[r]);
+        stage_neighbour(P, cur, bb, valid, srep[i - 1] != 0, nkey[r], ps, i, En, taken, mn, mx, htag[r]);
     }
     stage_finish(P, taken, mn, mx);
 }
@@ -2173,6 +2187,8 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
                 if (op < P.B) {
                     const int sl = slot[k];
                     P.pivn[op] = sl;
+                    P.pivEn[op] = ev[k];
+                    P.pivKn[op] = zk[k];
                     P.pivpos[op] = (int32_t)o;
                     if (P.take_pivots) {
                         P.oE[1 - cur][o] = DEAD;
@@ -2414,6 +2430,8 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     t += 2 * align_up(sizeof(int32_t) * lo.cap_o, 256);                // cand2
     t += 2 * align_up(sizeof(unsigned long long) * lo.cap_o, 256);     // candz2
     t += 2 * align_up(sizeof(int32_t) * c.batch, 256);                 // piv, this round's and the next's
+    t += 2 * align_up(sizeof(int32_t) * c.batch, 256);                 // their energies
+    t += 2 * align_up(sizeof(unsigned long long) * c.batch, 256);      // their keys
     t += align_up(sizeof(int32_t) * c.batch, 256);                     // pivpos
     t += align_up(sizeof(int32_t) * kClassifyBlocks, 256);             // best candidates
     t += align_up(sizeof(uint32_t) * kHistWords, 256);                 // select histograms
@@ -2489,11 +2507,19 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.bestc = cv.take<int32_t>(kClassifyBlocks);
     int32_t* pivb[2];
     for (int b = 0; b < 2; ++b) pivb[b] = cv.take<int32_t>(cfg.batch);
+    int32_t* pivEb[2];
+    for (int b = 0; b < 2; ++b) pivEb[b] = cv.take<int32_t>(cfg.batch);
+    unsigned long long* pivKb[2];
+    for (int b = 0; b < 2; ++b) pivKb[b] = cv.take<unsigned long long>(cfg.batch);
     // round r expands the pivots of buffer r & 1; its cut writes those of round r + 1
     auto set_round = [&](long long r) {
         P.piv = pivb[r & 1];
+        P.pivE = pivEb[r & 1];
+        P.pivK = pivKb[r & 1];
         P.pseq = pseqb[r & 1];
         P.pivn = pivb[(r + 1) & 1];
+        P.pivEn = pivEb[(r + 1) & 1];
+        P.pivKn = pivKb[(r + 1) & 1];
         P.pseqn = pseqb[(r + 1) & 1];
     };
     set_round(-1);   // the seeding cut writes round 0's pivots
