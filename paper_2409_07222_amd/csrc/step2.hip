@@ -95,7 +95,8 @@ constexpr int kSv = kMaxL + 2 * kPad + 2;
 constexpr int kExThreads = 256;
 constexpr int kExWaves = kExThreads / 64;
 constexpr int kItems = 8;                            // list entries per thread per pass (filters)
-constexpr int kKeepItems = 2;                        // the cut: fewer, so inserts overlap across threads
+constexpr int kKeepItems = 2;
+constexpr int kHistItems = 12;                       // the radix histogram: 256 x 512 x 12 entries a pass                        // the cut: fewer, so inserts overlap across threads
 
 // A slot's key, energy and state in one 16-byte record, so that a claim (CAS on
 // the key) and the writes of E and state touch one cache line, as do a probe's
@@ -156,6 +157,20 @@ struct Ctl {
     long long n_live0, expansions0;
     long long n_bestc;   // workgroups' candidates for an improving round's best (bestc)
 };
+
+// The control block as a kernel found it at its start, copied to LDS by the first
+// threads of each workgroup: one round trip instead of a chain of dependent scalar
+// loads.  The round kernels read their inputs from the copy and write through
+// P.ctl; a field a kernel writes is not read back through the copy.
+__device__ __forceinline__ void snap_ctl(Ctl& cs, const Ctl* c) {
+    static_assert(sizeof(Ctl) % 8 == 0, "the control block is copied in 8-byte words");
+    constexpr int n = (int)(sizeof(Ctl) / 8);
+    static_assert(n <= 64, "one wavefront copies the control block");
+    if (threadIdx.x < (unsigned)n)
+        reinterpret_cast<unsigned long long*>(&cs)[threadIdx.x] =
+            reinterpret_cast<const unsigned long long*>(c)[threadIdx.x];
+    __syncthreads();
+}
 
 // A pending insertion: the slot whose key matched, the source of the sequence
 // (a pivot slot and a flip position, or a candidate index when src < 0) and E.
@@ -692,8 +707,7 @@ __device__ void cut_setup(const Params& P) {
 
 // next_piv: the table slots of the pivots the last cut took out of Open for the
 // coming round.  One thread.
-__device__ void round_begin(const Params& P, const int32_t* next_piv) {
-    Ctl* c = P.ctl;
+__device__ void round_begin(const Params& P, const int32_t* next_piv, Ctl* c) {
     if (c->stop) return;
     if (c->n_live == 0 || c->expansions >= P.X || c->u >= P.T_u) {
         // the search ends: pivots taken out for a round that does not run go back
@@ -738,7 +752,7 @@ __device__ void round_begin(const Params& P, const int32_t* next_piv) {
     c->out_count = 0;
 }
 
-__global__ void k_round_begin(Params P) { round_begin(P, P.piv); }
+__global__ void k_round_begin(Params P) { round_begin(P, P.piv, P.ctl); }
 
 // ---------------------------------------------------------------- selection
 // Selects the T smallest live Open entries in key order into flag[].
@@ -822,19 +836,39 @@ struct MidVals {
 };
 
 __global__ __launch_bounds__(kSelThreads) void k_mid_hist(Params P) {
-    Ctl* c = P.ctl;
-    if (c->stop) return;
     __shared__ long long s_cnt[kSelThreads / 64];
     __shared__ int32_t s_min[kSelThreads / 64], s_max[kSelThreads / 64];
     __shared__ MidVals m;
+    __shared__ Ctl cs;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    // the first pivots' counts (in bounds for any count) load with the control block
+    const bool pre = t < P.B;
+    const int32_t pc0 = pre ? P.bcnt[t] : 0, pmn0 = pre ? P.bmin[t] : INT32_MAX, pmx0 = pre ? P.bmax[t] : 0;
+    snap_ctl(cs, P.ctl);
+    const Ctl* c = &cs;
+    Ctl* cg = P.ctl;
+    if (c->stop) return;
     const long long np = c->n_piv;
+    // this workgroup's first kHistItems entries per thread, loaded while the round's
+    // counts are reduced (the list's length needs only the pivot count)
+    const int cur = c->which;
+    const long long n_tot = c->batch_begin + np * (P.L + P.R2);
+    int32_t ev[kHistItems];
+    const long long hbase = (long long)blockIdx.x * blockDim.x * kHistItems + t;
+#pragma unroll
+    for (int k = 0; k < kHistItems; ++k) {
+        const long long i = hbase + (long long)k * blockDim.x;
+        ev[k] = i < n_tot ? P.oE[cur][i] : DEAD;
+    }
     long long cnt = 0;
     int32_t mn = INT32_MAX, mx = 0;
     for (long long b = t; b < np; b += blockDim.x) {
-        cnt += P.bcnt[b];
-        mn = P.bmin[b] < mn ? P.bmin[b] : mn;
-        mx = P.bmax[b] > mx ? P.bmax[b] : mx;
+        const int32_t bc = b == t ? pc0 : P.bcnt[b];
+        const int32_t bn = b == t ? pmn0 : P.bmin[b];
+        const int32_t bx = b == t ? pmx0 : P.bmax[b];
+        cnt += bc;
+        mn = bn < mn ? bn : mn;
+        mx = bx > mx ? bx : mx;
     }
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
     mn = __ockl_wfred_min_i32(mn);
@@ -872,17 +906,17 @@ __global__ __launch_bounds__(kSelThreads) void k_mid_hist(Params P) {
         m.emin = (uint32_t)mn < c->blo ? (uint32_t)mn : c->blo;
         m.emax = (uint32_t)mx > c->bhi ? (uint32_t)mx : c->bhi;
         if (blockIdx.x == 0) {
-            c->n_tot = m.n_tot;
-            c->batch_minE = mn;
-            c->expansions = m.expansions;
-            c->n_live = m.n_live;
-            c->pushes += cnt;
-            c->dups += np * (P.L + P.R2) - cnt;
-            if (mn < c->best_E) c->improved = 1;
-            else c->u += np;
+            cg->n_tot = m.n_tot;
+            cg->batch_minE = mn;
+            cg->expansions = m.expansions;
+            cg->n_live = m.n_live;
+            cg->pushes = c->pushes + cnt;
+            cg->dups = c->dups + np * (P.L + P.R2) - cnt;
+            if (mn < c->best_E) cg->improved = 1;
+            else cg->u = c->u + np;
             cut_setup(P);
-            c->emin = m.emin;
-            c->emax = m.emax;
+            cg->emin = m.emin;
+            cg->emax = m.emax;
         }
     }
     __syncthreads();
@@ -894,16 +928,26 @@ __global__ __launch_bounds__(kSelThreads) void k_mid_hist(Params P) {
     const int nbins = 1 << (hs - ls);   // bins in use
     for (int b = t; b < nbins; b += blockDim.x) h[b] = 0;
     __syncthreads();
-    const int cur = c->which;
     const uint32_t emin = m.emin;
     const uint32_t dmask = (1u << (hs - ls)) - 1u;
-    for (long long i = (long long)blockIdx.x * blockDim.x + t; i < m.n_tot;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int32_t e = P.oE[cur][i];
-        if (e == DEAD) continue;
+    auto add = [&](int32_t e) {
+        if (e == DEAD) return;
         const uint32_t D = ((uint32_t)e - emin) >> 2;
-        if (hs < 32 && (D >> hs) != 0u) continue;
+        if (hs < 32 && (D >> hs) != 0u) return;
         atomicAdd(&h[(D >> ls) & dmask], 1u);
+    };
+#pragma unroll
+    for (int k = 0; k < kHistItems; ++k) add(ev[k]);
+    // longer lists: the rest in passes of kHistItems loads per thread
+    const long long stride = (long long)gridDim.x * blockDim.x * kHistItems;
+    for (long long base = hbase + stride; base < n_tot; base += stride) {
+#pragma unroll
+        for (int k = 0; k < kHistItems; ++k) {
+            const long long i = base + (long long)k * blockDim.x;
+            ev[k] = i < n_tot ? P.oE[cur][i] : DEAD;
+        }
+#pragma unroll
+        for (int k = 0; k < kHistItems; ++k) add(ev[k]);
     }
     __syncthreads();
     for (int b = t; b < nbins; b += blockDim.x)
@@ -986,8 +1030,7 @@ __device__ __forceinline__ bool entry_less(const Params& P, int cur, long long a
 
 // This workgroup's least entry (by key, then sequence) among the round's new
 // entries of the round's least energy, in the classify pass's entry layout.
-__device__ void best_offer(const Params& P) {
-    Ctl* c = P.ctl;
+__device__ void best_offer(const Params& P, const Ctl* c) {
     __shared__ long long best[kSelThreads];
     const int cur = c->which;
     const int32_t target = c->batch_minE;
@@ -1010,13 +1053,13 @@ __device__ void best_offer(const Params& P) {
         __syncthreads();
     }
     if (threadIdx.x == 0 && best[0] >= 0)
-        P.bestc[atomicAdd((unsigned long long*)&c->n_bestc, 1ull)] = (int32_t)best[0];
+        P.bestc[atomicAdd((unsigned long long*)&P.ctl->n_bestc, 1ull)] = (int32_t)best[0];
     __syncthreads();
 }
 
 // The tie select's third workgroup: the least offer becomes the best.
-__device__ void best_take(const Params& P) {
-    Ctl* c = P.ctl;
+__device__ void best_take(const Params& P, const Ctl* c) {
+    Ctl* cg = P.ctl;
     __shared__ long long best[1024];
     const int cur = c->which;
     const long long n = c->n_bestc;
@@ -1038,34 +1081,37 @@ __device__ void best_take(const Params& P) {
     if (b >= 0 && threadIdx.x < (unsigned)P.W)
         P.best_seq[threadIdx.x] = entry_word(P, P.oS[cur][b], b, threadIdx.x);
     if (threadIdx.x == 0 && b >= 0) {
-        c->best_slot = 1;
-        c->best_E = c->batch_minE;
-        c->best_round = (int32_t)c->rounds;
-        c->u = 0;
+        cg->best_slot = 1;
+        cg->best_E = c->batch_minE;
+        cg->best_round = (int32_t)c->rounds;
+        cg->u = 0;
     }
 }
 
 __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
-    Ctl* c = P.ctl;
+    __shared__ Ctl cs;
+    snap_ctl(cs, P.ctl);
+    const Ctl* c = &cs;
+    Ctl* cg = P.ctl;
     if (c->stop) return;
     const int nblk = (int)gridDim.x;
     // a round that improved on the best: every workgroup offers its least (key,
     // sequence) among its new entries at the round's least energy; the tie select
     // takes the least of the offers
-    if (P.best_in_classify && c->improved) best_offer(P);
+    if (P.best_in_classify && c->improved) best_offer(P, c);
     if (!c->sel_enabled) return;
     __shared__ SelCut cut;
     find_cut(P, c, &cut);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        c->c_lt = cut.c_lt;
-        c->prefix = cut.prefix;
-        c->Dt = cut.Dt;
-        c->resolved = cut.resolved;
-        c->hi_shift = cut.hi_shift;
-        c->c_lt2 = cut.c_lt2;
-        c->prefix2 = cut.prefix2;
-        c->Dt2 = cut.Dt2;
-        c->resolved2 = cut.resolved2;
+        cg->c_lt = cut.c_lt;
+        cg->prefix = cut.prefix;
+        cg->Dt = cut.Dt;
+        cg->resolved = cut.resolved;
+        cg->hi_shift = cut.hi_shift;
+        cg->c_lt2 = cut.c_lt2;
+        cg->prefix2 = cut.prefix2;
+        cg->Dt2 = cut.Dt2;
+        cg->resolved2 = cut.resolved2;
     }
     const int cur = c->which;
     const bool all = c->sel_all;
@@ -1134,8 +1180,8 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
             cnt2 += tie2[k] ? 1 : 0;
         }
         long long o, o2;
-        if (dual && !dual_all) block_append2(&c->out_count, cnt, &c->out_count2, cnt2, &o, &o2);   // uniform
-        else o = block_append_n(&c->out_count, cnt);
+        if (dual && !dual_all) block_append2(&cg->out_count, cnt, &cg->out_count2, cnt2, &o, &o2);   // uniform
+        else o = block_append_n(&cg->out_count, cnt);
 #pragma unroll
         for (int k = 0; k < kItems; ++k)
             if (tie[k]) {
@@ -1203,9 +1249,12 @@ constexpr int kTieU = 8;        // candidates loaded ahead per thread in the glo
 // state but the flag words, which they update by atomic ORs of different bits.
 __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
     const int which = blockIdx.x;
-    Ctl* c = P.ctl;
+    __shared__ Ctl cs;
+    snap_ctl(cs, P.ctl);
+    const Ctl* c = &cs;
+    Ctl* cg = P.ctl;
     if (which == 2) {
-        if (!c->stop && P.best_in_classify && c->improved) best_take(P);
+        if (!c->stop && P.best_in_classify && c->improved) best_take(P, c);
         return;
     }
     if (c->stop || !c->sel_enabled) return;
@@ -1233,10 +1282,10 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
     if (unres && (ls > kSubBits || r >= m)) {
         // the whole bin is taken (or its width is out of range: an error the host sees)
         if (t == 0) {
-            if (ls > kSubBits) atomicExch(&c->error, 6);
+            if (ls > kSubBits) atomicExch(&cg->error, 6);
             if (!which) {
-                c->Dt = ((prefix + 1u) << ls) - 1u;
-                c->resolved = 1;
+                cg->Dt = ((prefix + 1u) << ls) - 1u;
+                cg->resolved = 1;
             }
         }
         if (ls > kSubBits) return;
@@ -1273,8 +1322,8 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
             s_v = v;
             s_r = r - cum;
             if (!which) {
-                c->Dt = Dlo + (uint32_t)v;   // the cut's energy, for the next round's bounds
-                c->resolved = 1;
+                cg->Dt = Dlo + (uint32_t)v;   // the cut's energy, for the next round's bounds
+                cg->resolved = 1;
             }
         }
         __syncthreads();
@@ -1339,8 +1388,8 @@ __global__ __launch_bounds__(1024) void k_sel_keys(Params P) {
         __syncthreads();
         const int v = s_v;
         if (t == 0) {
-            if (which) c->zv2 = (uint32_t)v;
-            else c->zv = (uint32_t)v;
+            if (which) cg->zv2 = (uint32_t)v;
+            else cg->zv = (uint32_t)v;
         }
         for (int q0 = t; q0 < m; q0 += kTieU * blockDim.x) {
             unsigned long long z[kTieU];
@@ -2080,7 +2129,10 @@ __global__ __launch_bounds__(1024) void k_best(Params P, int initial) {
 // H).  Each thread handles kItems entries per pass, one atomic per block pass.
 
 __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
-    Ctl* c = P.ctl;
+    __shared__ Ctl cs;
+    snap_ctl(cs, P.ctl);
+    const Ctl* c = &cs;
+    Ctl* cg = P.ctl;
     if (c->stop) return;
     // the classify pass and the tie select have read the histograms: empty them for
     // the next selection
@@ -2138,7 +2190,7 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
                             break;
                         }
                     if (slot[k] < 0) {
-                        atomicExch(&c->error, 2);
+                        atomicExch(&cg->error, 2);
                         keep[k] = false;
                     } else {
                         for (int w = 0; w < H.W; ++w)
@@ -2169,11 +2221,11 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
             const uint64_t pm = __ballot(pv[k]);
             unsigned long long pb = 0;
             if (pm && lane == __ffsll((unsigned long long)pm) - 1)
-                pb = atomicAdd((unsigned long long*)&c->n_pivpos, (unsigned long long)__popcll(pm));
+                pb = atomicAdd((unsigned long long*)&cg->n_pivpos, (unsigned long long)__popcll(pm));
             pb = __shfl(pb, __ffsll((unsigned long long)pm) - 1, 64);
             opk[k] = (long long)pb + __popcll(pm & lt);
         }
-        long long o = block_append_n(&c->survivors, cnt);
+        long long o = block_append_n(&cg->survivors, cnt);
 #pragma unroll
         for (int k = 0; k < kKeepItems; ++k) {
             if (!keep[k]) continue;
@@ -2209,11 +2261,10 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
             ++o;
         }
     }
-    if (claims) atomicAdd((unsigned long long*)&c->claimed, (unsigned long long)claims);
+    if (claims) atomicAdd((unsigned long long*)&cg->claimed, (unsigned long long)claims);
 }
 
-__device__ void round_end(const Params& P, int count_round) {
-    Ctl* c = P.ctl;
+__device__ void round_end(const Params& P, int count_round, Ctl* c) {
     if (c->stop) return;
     if (!c->sel_all) {   // the cut evicted entries
         // (the seeding cut admits the Q smallest candidates: no evictions)
@@ -2231,12 +2282,23 @@ __device__ void round_end(const Params& P, int count_round) {
     if (count_round) c->rounds += 1;
 }
 
-__global__ void k_round_end(Params P, int count_round) { round_end(P, count_round); }
+__global__ void k_round_end(Params P, int count_round) { round_end(P, count_round, P.ctl); }
 
-// The end of a round and the start of the next in one launch.
-__global__ void k_round_next(Params P) {
-    round_end(P, 1);
-    round_begin(P, P.pivn);
+// The end of a round and the start of the next in one launch (one wavefront): the
+// control block is copied to LDS in one go, updated there by one thread and
+// written back whole (no other kernel runs beside this one).
+__global__ __launch_bounds__(64) void k_round_next(Params P) {
+    __shared__ Ctl cs;
+    snap_ctl(cs, P.ctl);
+    if (threadIdx.x == 0) {
+        round_end(P, 1, &cs);
+        round_begin(P, P.pivn, &cs);
+    }
+    __syncthreads();
+    constexpr int n = (int)(sizeof(Ctl) / 8);
+    if (threadIdx.x < (unsigned)n)
+        reinterpret_cast<unsigned long long*>(P.ctl)[threadIdx.x] =
+            reinterpret_cast<const unsigned long long*>(&cs)[threadIdx.x];
 }
 
 __global__ void k_outputs(Params P, uint32_t* best_seq, int32_t* best_E, labs_step2_stats* st,
@@ -2621,7 +2683,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
         }
         select(false, true);
         hipLaunchKernelGGL(k_keep, dim3(kKeepBlocks), tS, 0, st, P);
-        hipLaunchKernelGGL(k_round_next, dim3(1), dim3(1), 0, st, P);
+        hipLaunchKernelGGL(k_round_next, dim3(1), dim3(64), 0, st, P);
         LABS_LAUNCHED("step2 round");
         if ((r + 1) % kCheck == 0) {
             // This batch's flags are copied; the host reads the previous batch's,
