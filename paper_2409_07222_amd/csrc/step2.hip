@@ -1095,6 +1095,16 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
     Ctl* cg = P.ctl;
     if (c->stop) return;
     const int nblk = (int)gridDim.x;
+    // the first pass's energies load while the cut is found
+    const int cur = c->which;
+    const long long n_tot = c->n_tot;
+    const long long base0 = (long long)blockIdx.x * blockDim.x * kItems;
+    int32_t e0[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const long long i = base0 + threadIdx.x + (long long)k * blockDim.x;
+        e0[k] = i < n_tot ? P.oE[cur][i] : DEAD;
+    }
     // a round that improved on the best: every workgroup offers its least (key,
     // sequence) among its new entries at the round's least energy; the tie select
     // takes the least of the offers
@@ -1113,7 +1123,6 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
         cg->Dt2 = cut.Dt2;
         cg->resolved2 = cut.resolved2;
     }
-    const int cur = c->which;
     const bool all = c->sel_all;
     // resolved: the threshold energy Et; otherwise the threshold bin [Dlo, Dhi) of D
     const bool res = cut.resolved;
@@ -1128,7 +1137,6 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
     const uint32_t Et2 = c->emin + (cut.Dt2 << 2);
     const uint32_t D2lo = cut.prefix2 << cut.hi_shift;
     const uint32_t D2hi = (cut.prefix2 + 1u) << cut.hi_shift;
-    const long long n_tot = c->n_tot;
     // top key bytes of the entries tied at a resolved threshold energy
     __shared__ uint32_t zh[2 * kZBins];
     for (int b = threadIdx.x; b < 2 * kZBins; b += blockDim.x) zh[b] = 0;
@@ -1143,7 +1151,7 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_classify(Params P) {
             tie[k] = false;
             tie2[k] = false;
             if (i < n_tot) {
-                const int32_t e = P.oE[cur][i];
+                const int32_t e = base == base0 ? e0[k] : P.oE[cur][i];
                 uint32_t f = 0;
                 if (e != DEAD) {
                     const uint32_t D = ((uint32_t)e - emin) >> 2;
@@ -2154,8 +2162,9 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
         int32_t ev[kKeepItems];
         uint32_t fv[kKeepItems];
         unsigned long long zk[kKeepItems];
+        int tb[kKeepItems];
         int cnt = 0;
-        // every load of the pass first
+        // every load of the pass first (a new entry's tombstone slot too)
 #pragma unroll
         for (int k = 0; k < kKeepItems; ++k) {
             const long long i = base + threadIdx.x + (long long)k * blockDim.x;
@@ -2164,6 +2173,7 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
             fv[k] = in ? P.flag[i] : 0u;
             slot[k] = in ? P.oS[cur][i] : -1;
             zk[k] = in ? P.oZ[cur][i] : 0ull;
+            tb[k] = in && i >= bb ? P.ntomb[i - bb] : -1;
         }
 #pragma unroll
         for (int k = 0; k < kKeepItems; ++k) {
@@ -2177,7 +2187,7 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
             } else if (keep[k]) {
                 const long long j = i - bb;
                 const unsigned long long key = zk[k];
-                const int tomb = P.ntomb[j];
+                const int tomb = tb[k];
                 if (tomb >= 0) {
                     slot[k] = tomb;
                     H.rec[slot[k]].state = ST_OPEN;
