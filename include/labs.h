@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LABS_ABI_VERSION 1
+#define LABS_ABI_VERSION 2
 
 typedef int32_t labs_status;
 enum {
@@ -337,6 +337,8 @@ typedef struct {
     int64_t open_count;      /* Open entries at the end */
     int32_t best_E;
     int32_t best_round;      /* round of the last improvement, -1 if none */
+    int64_t rebuilds;        /* rebuilds of the hash set (evicted tombstones dropped); they
+                                change no result */
 } labs_step2_stats;
 
 typedef struct {

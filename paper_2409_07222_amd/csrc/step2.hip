@@ -89,6 +89,7 @@ constexpr int kGridBlocks = 1024;                    // grid-stride kernels over
 // (two, three per CU at their register use), so that no workgroup waits for a slot.
 constexpr int kClassifyBlocks = 512;
 constexpr int kKeepBlocks = 768;
+constexpr int kCheck = 8;    // rounds between host looks at the control block
 constexpr int kMaxL = 1023;
 constexpr int kPad = 1024;
 constexpr int kSv = kMaxL + 2 * kPad + 2;
@@ -194,6 +195,10 @@ struct Params {
     unsigned long long* candz2[2];
     int32_t* piv;          // [B] table slots of this round's pivots
     int32_t* pivn;         // [B] the next round's (written by the cut; the host alternates the two)
+    // [kCheck][kKeepBlocks]: hash-set slots claimed by each workgroup of the cut in
+    // the rounds of a batch (round r writes row r mod kCheck); the host copies the
+    // rows with the batch's flags and sums them (no atomics on one counter)
+    int32_t* kclaims;
     int32_t* pivE;         // [B] energies of this round's pivots, and of the next round's
     int32_t* pivEn;
     unsigned long long* pivK;   // [B] their Zobrist keys (as stored with their slots)
@@ -2271,7 +2276,16 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
             ++o;
         }
     }
-    if (claims) atomicAdd((unsigned long long*)&cg->claimed, (unsigned long long)claims);
+    // the workgroup's claims: a wave sum, then the waves' sums
+    __shared__ int s_claims[kSelThreads / 64];
+    const int wcl = __ockl_wfred_add_i32((int)claims);
+    if ((threadIdx.x & 63) == 0) s_claims[threadIdx.x >> 6] = wcl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tot += s_claims[k];
+        P.kclaims[(size_t)(c->rounds % kCheck) * kKeepBlocks + blockIdx.x] = tot;
+    }
 }
 
 __device__ void round_end(const Params& P, int count_round, Ctl* c) {
@@ -2312,7 +2326,7 @@ __global__ __launch_bounds__(64) void k_round_next(Params P) {
 }
 
 __global__ void k_outputs(Params P, uint32_t* best_seq, int32_t* best_E, labs_step2_stats* st,
-                          uint32_t* open_seqs, int32_t* open_E, long long open_cap) {
+                          uint32_t* open_seqs, int32_t* open_E, long long open_cap, long long rebuilds) {
     Ctl* c = P.ctl;
     const int W = P.W;
     if (blockIdx.x == 0 && threadIdx.x < (unsigned)W && c->best_slot >= 0)
@@ -2327,6 +2341,7 @@ __global__ void k_outputs(Params P, uint32_t* best_seq, int32_t* best_E, labs_st
         st->open_count = c->n_live;
         st->best_E = c->best_E;
         st->best_round = c->best_round;
+        st->rebuilds = rebuilds;
     }
     if (!open_seqs && !open_E) return;
     const int cur = c->which;
@@ -2457,7 +2472,6 @@ uint64_t next_pow2(uint64_t x) {
     return p;
 }
 
-constexpr int kCheck = 8;    // rounds between host looks at the control block
 
 struct S2Layout {
     uint64_t cap_ht;
@@ -2508,6 +2522,7 @@ S2Layout s2_layout(const labs_step2_cfg& c, long long n_cand) {
     t += align_up(sizeof(int32_t) * kClassifyBlocks, 256);             // best candidates
     t += align_up(sizeof(uint32_t) * kHistWords, 256);                 // select histograms
     t += align_up(sizeof(uint32_t) * 32, 256);                         // best sequence
+    t += align_up(sizeof(int32_t) * kCheck * kKeepBlocks, 256);        // claims per cut workgroup
     t += 2 * align_up(sizeof(Pend) * lo.cap_pend, 256);                // pending, collisions
     lo.total = t + 4096;
     return lo;
@@ -2598,6 +2613,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     P.take_pivots = 0;
     P.ghist = cv.take<uint32_t>((size_t)kHistWords);
     P.best_seq = cv.take<uint32_t>(32);
+    P.kclaims = cv.take<int32_t>((size_t)kCheck * kKeepBlocks);
     P.pend = cv.take<Pend>(lo.cap_pend);
     P.slow = cv.take<Pend>(lo.cap_pend);
     P.cands = cand_seqs;
@@ -2606,6 +2622,7 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     LABS_HIP(hipMemsetAsync(P.H.rec, 0, sizeof(SlotRec) * lo.cap_ht, st));
     LABS_HIP(hipMemsetAsync(P.H.tag, 0, lo.cap_ht, st));
     LABS_HIP(hipMemsetAsync(P.best_seq, 0, sizeof(uint32_t) * 32, st));
+    LABS_HIP(hipMemsetAsync(P.kclaims, 0, sizeof(int32_t) * kCheck * kKeepBlocks, st));
     LABS_HIP(hipMemsetAsync(P.ghist, 0, sizeof(uint32_t) * kHistWords, st));
     const dim3 gS(kGridBlocks), tS(kSelThreads);
     // Selection; rounds take their energy bounds from the control block instead
@@ -2652,11 +2669,13 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     // the next round's pivots out of Open), then the end of the round together
     // with the start of the next.
     hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, st, P);
-    // the control block's flags as copied after every kCheck rounds (pinned, two
-    // batches in turn), and the claims last read
+    // the control block's flags and the cut's claims as copied after every kCheck
+    // rounds (pinned, two batches in turn); claimed = the block's count (set by the
+    // seeding and by a rebuild) + the claims summed since
     struct ChkFlags {
         int32_t stop, error;
         long long claimed;
+        int32_t claims[kCheck * kKeepBlocks];
     };
     struct ChkRes {
         hipStream_t st = nullptr;
@@ -2676,6 +2695,8 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
     hipEvent_t* chk = chk_res.ev;
     const long long BLr = (long long)cfg.batch * (cfg.L + 2 * cfg.T_r);   // claims of one round at most
     long long claimed_seen = n_cand;
+    long long claims_acc = 0;
+    long long n_rebuilds = 0;
     int inflight = -1;
     for (long long r = 0;; ++r) {
         set_round(r);
@@ -2707,6 +2728,8 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
                                     hipMemcpyDeviceToHost, st));
             LABS_HIP(hipMemcpyAsync(&hflags[slot].claimed, &P.ctl->claimed, sizeof(long long),
                                     hipMemcpyDeviceToHost, st));
+            LABS_HIP(hipMemcpyAsync(hflags[slot].claims, P.kclaims, sizeof(int32_t) * kCheck * kKeepBlocks,
+                                    hipMemcpyDeviceToHost, st));
             LABS_HIP(hipEventRecord(chk[slot], st));
             const bool now = (uint64_t)(claimed_seen + 3LL * kCheck * BLr) * 2 >= lo.cap_ht;
             int look;
@@ -2721,16 +2744,18 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
                 continue;
             }
             LABS_HIP(hipEventSynchronize(chk[look]));
-            const ChkFlags f = hflags[look];
+            const ChkFlags& f = hflags[look];
             if (f.error) {
                 set_error("second-step hash set failure (code %d)", f.error);
                 return LABS_E_DEVICE;
             }
             if (f.stop) break;
-            claimed_seen = f.claimed;
-            const long long claimed = f.claimed;
+            for (int k = 0; k < kCheck * kKeepBlocks; ++k) claims_acc += f.claims[k];
+            const long long claimed = f.claimed + claims_acc;
+            claimed_seen = claimed;
             if ((uint64_t)claimed * 2 >= lo.cap_ht) {
                 inflight = -1;   // its claims were counted before the rebuild
+                claims_acc = 0;  // the rebuild recounts the claimed slots
                 Table& dst = tabs[1 - tcur];
                 LABS_HIP(hipMemsetAsync(dst.rec, 0, sizeof(SlotRec) * lo.cap_ht, st));
                 LABS_HIP(hipMemsetAsync(dst.tag, 0, lo.cap_ht, st));
@@ -2741,11 +2766,12 @@ labs_status step2_run(const labs_step2_cfg& cfg, long long n_cand, const uint32_
                 LABS_LAUNCHED("step2 rebuild");
                 tcur = 1 - tcur;
                 P.H = tabs[tcur];
+                ++n_rebuilds;
             }
         }
     }
     hipLaunchKernelGGL(k_outputs, gS, tS, 0, st, P, out.best_seq, out.best_E, out.stats, out.open_seqs,
-                       out.open_E, (long long)out.open_capacity);
+                       out.open_E, (long long)out.open_capacity, n_rebuilds);
     LABS_LAUNCHED("step2 outputs");
     LABS_HIP(hipStreamSynchronize(st));
     return LABS_OK;

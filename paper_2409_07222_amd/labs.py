@@ -72,7 +72,8 @@ class Step2Stats(ctypes.Structure):
     _fields_ = [("expansions", ctypes.c_int64), ("pushes", ctypes.c_int64),
                 ("dup_skips", ctypes.c_int64), ("evictions", ctypes.c_int64),
                 ("rounds", ctypes.c_int64), ("open_count", ctypes.c_int64),
-                ("best_E", ctypes.c_int32), ("best_round", ctypes.c_int32)]
+                ("best_E", ctypes.c_int32), ("best_round", ctypes.c_int32),
+                ("rebuilds", ctypes.c_int64)]
 
 
 class Step2Out(ctypes.Structure):

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared():
         assert hasattr(lib, name), name
     lib.labs_abi_version.restype = ctypes.c_int32
-    assert lib.labs_abi_version() == 1
+    assert lib.labs_abi_version() == 2
     lib.labs_words.restype = ctypes.c_int32
     assert [lib.labs_words(L) for L in (1, 32, 33, 501)] == [1, 1, 2, 16]
 

@@ -58,6 +58,17 @@ def test_step2_parity(lb, orc, L, n, B, Q, X, T_u):
     _run_both(lb, orc, L, cands, B, Q, X, T_u)
 
 
+def test_step2_table_rebuild(lb, orc):
+    """More distinct sequences pass through Open than half of the hash set holds
+    (9,699 in this run against 8,192 of the 16,384 slots sized for L = 33, batch 1,
+    queue 1,600, 1,900 pops): the set is rebuilt without its evicted tombstones,
+    and no result changes."""
+    L, n, B, Q, X = 33, 3, 1, 1600, 1900
+    cands = li.random_pm1(L * 7 + n, n, L)
+    g, _ = _run_both(lb, orc, L, cands, B, Q, X, 1 << 40)
+    assert g["rebuilds"] >= 1, g["rebuilds"]
+
+
 def test_step2_L501(lb, orc):
     L = 501
     cands = li.random_skew(5, 3, L, 16)
