@@ -49,6 +49,7 @@ extern "C" __device__ int __ockl_wfred_min_i32(int);
 extern "C" __device__ unsigned int __ockl_wfred_or_u32(unsigned int);
 extern "C" __device__ int __ockl_wfred_add_i32(int);
 extern "C" __device__ unsigned int __ockl_wfred_max_u32(unsigned int);
+extern "C" __device__ int __ockl_wfred_max_i32(int);
 
 // SplitMix64 (Steele, Lea, Flood 2014): finaliser and the counter form of its
 // stream, output i of the stream started at `key` is mix(key + (i+1)*gamma).

@@ -219,14 +219,25 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
     }
 
     for (int t = t0 + 1; t <= t1; ++t) {
-        // ---- bit planes of C' = (C - 1)/2: for odd L every even-lag C_{2m} is odd
-        // (a sum of L - 2m terms of +-1), so sum_m C F = 2 sum_m C' F + popcount(F)
-        // with one plane fewer
-        uint32_t orv = 0;
+        // ---- bit planes of v = C' + bias, C' = (C - 1)/2: for odd L every even-lag
+        // C_{2m} is odd (a sum of L - 2m terms of +-1), so sum_m C F = 2 sum_m C' F +
+        // popcount(F); bias = -min C' makes every v >= 0, so the planes need only the
+        // bits of max C' - min C' (no sign plane), and sum_m C' F = sum_m v F - bias
+        // popcount(F).  Lags beyond k hold C' = 0 and meet zero window bits.
+        int lmin = Ch[0], lmax = Ch[0];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) orv |= (uint32_t)(Ch[q] ^ (Ch[q] >> 31));
-        orv = __ockl_wfred_or_u32(orv);
-        const int nb = (32 - __clz((int)orv)) + 1;
+        for (int q = 1; q < NQ; ++q) {
+            lmin = min(lmin, Ch[q]);
+            lmax = max(lmax, Ch[q]);
+        }
+        const int cmin = __ockl_wfred_min_i32(lmin);
+        const int cmax = __ockl_wfred_max_i32(lmax);
+        const int bias = -cmin;
+        const uint32_t vmax = (uint32_t)(cmax - cmin);
+        const int nb = vmax ? 32 - __clz((int)vmax) : 0;
+        uint32_t Vq[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) Vq[q] = (uint32_t)(Ch[q] + bias);
 
         // ---- H = H_f + H_b, bit-sliced, then the exact dE, RB slots at a time
         int dlt[R];
@@ -245,7 +256,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
                 for (int r = 0; r < RB; ++r) acc[r] = 0;
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
-                    const uint64_t bal = __ballot((Ch[q] >> jp) & 1);
+                    const uint64_t bal = __ballot((Vq[q] >> jp) & 1u);
                     const uint32_t lo = (uint32_t)bal, hi = (uint32_t)(bal >> 32);
 #pragma unroll
                     for (int r = 0; r < RB; ++r) {
@@ -260,9 +271,8 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
                         for (int r = 0; r < RB; ++r) acc[r] += __popc(hl & B[r][NQ - 1]);
                     }
                 }
-                const int wgt = (jp == nb - 1) ? -(1 << jp) : (1 << jp);
 #pragma unroll
-                for (int r = 0; r < RB; ++r) H[r] += wgt * (int)acc[r];
+                for (int r = 0; r < RB; ++r) H[r] += (int)(acc[r] << jp);
             }
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
@@ -272,7 +282,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
 #pragma unroll
                 for (int w = 0; w < NQ - 1; ++w) pf += __popc(B[r][w]);
                 if (bfull) pf += __popc(B[r][NQ - 1]);
-                H[r] = 2 * H[r] + pf;
+                H[r] = 2 * (H[r] - bias * pf) + pf;
             }
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr) {
