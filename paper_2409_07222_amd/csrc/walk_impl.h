@@ -108,8 +108,11 @@ __device__ inline void store_tables(Lds<NW>& S, int K, int lane, const int32_t* 
 
 // bfull: the last backward word holds a lag (k/2 > 32(NQ-1)); when it does not
 // (k = 64(NQ-1)+1 with NW odd), that word is zero for every slot and is skipped.
+// g0: slot group of F[0].  Slot group g holds positions a >= 1 + 64 g, whose forward
+// windows reach at most (L - a)/2 <= k - 32 g lags: forward words w >= NW - g are zero
+// (the loops are unrolled, so those words and every popcount of them fold away).
 template <int NW, int R>
-__device__ __forceinline__ void build_windows(const Lds<NW>& S, int p, int k, int lane, bool bfull,
+__device__ __forceinline__ void build_windows(const Lds<NW>& S, int p, int k, int lane, bool bfull, int g0,
                                               uint32_t (&F)[R][NW],
                                               uint32_t (&B)[R][(NW + 1) / 2]) {
     constexpr int NQ = (NW + 1) / 2;
@@ -127,7 +130,7 @@ __device__ __forceinline__ void build_windows(const Lds<NW>& S, int p, int k, in
         const uint32_t* VRp = S.VR[pi];
 #pragma unroll
         for (int w = 0; w < NW; ++w)
-            F[r][w] = __builtin_amdgcn_alignbit(Vp[qf + w + 1], Vp[qf + w], hf);
+            F[r][w] = w < NW - (g0 + r) ? __builtin_amdgcn_alignbit(Vp[qf + w + 1], Vp[qf + w], hf) : 0u;
 #pragma unroll
         for (int w = 0; w < NQ - 1; ++w)
             B[r][w] = __builtin_amdgcn_alignbit(VRp[qb + w + 1], VRp[qb + w], hb);
@@ -246,7 +249,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi) {
             uint32_t F[RB][NW], B[RB][NQ];
-            build_windows<NW, RB>(S, p + 64 * RB * gi, k, lane, bfull, F, B);
+            build_windows<NW, RB>(S, p + 64 * RB * gi, k, lane, bfull, RB * gi, F, B);
             int32_t H[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) H[r] = 0;
