@@ -143,6 +143,14 @@ __device__ __forceinline__ void build_windows(const Lds<NW>& S, int p, int k, in
 // RB: fewer window registers, the bit planes re-ballotted once per group).
 // BL: self-avoidance by the walker's Bloom filter (copied into `bl` in LDS for
 // the segment) instead of the tabu tenure.
+// popcount(x) + acc in one instruction: the plane sums chain through the
+// accumulator operand of v_bcnt_u32_b32 instead of separate adds
+__device__ __forceinline__ uint32_t bcnt_add(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
 template <int NW, int R, int RB, bool BL>
 __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>& S, uint32_t* bl) {
     constexpr int NQ = (NW + 1) / 2;
@@ -263,15 +271,17 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
                     const uint32_t lo = (uint32_t)bal, hi = (uint32_t)(bal >> 32);
 #pragma unroll
                     for (int r = 0; r < RB; ++r) {
-                        acc[r] += __popc(lo & F[r][2 * q]);
-                        if (2 * q + 1 < NW) acc[r] += __popc(hi & F[r][2 * q + 1]);
-                        if (2 * q < NQ - 1) acc[r] += __popc(lo & B[r][2 * q]);
-                        if (2 * q + 1 < NQ - 1) acc[r] += __popc(hi & B[r][2 * q + 1]);
+                        // forward words beyond the group's reach are zero (see build_windows)
+                        const int g = RB * gi + r;
+                        if (2 * q < NW - g) acc[r] = bcnt_add(lo & F[r][2 * q], acc[r]);
+                        if (2 * q + 1 < NW - g) acc[r] = bcnt_add(hi & F[r][2 * q + 1], acc[r]);
+                        if (2 * q < NQ - 1) acc[r] = bcnt_add(lo & B[r][2 * q], acc[r]);
+                        if (2 * q + 1 < NQ - 1) acc[r] = bcnt_add(hi & B[r][2 * q + 1], acc[r]);
                     }
                     if ((2 * q == NQ - 1 || 2 * q + 1 == NQ - 1) && bfull) {
                         const uint32_t hl = (2 * q == NQ - 1) ? lo : hi;
 #pragma unroll
-                        for (int r = 0; r < RB; ++r) acc[r] += __popc(hl & B[r][NQ - 1]);
+                        for (int r = 0; r < RB; ++r) acc[r] = bcnt_add(hl & B[r][NQ - 1], acc[r]);
                     }
                 }
 #pragma unroll
