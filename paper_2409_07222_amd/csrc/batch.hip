@@ -41,11 +41,34 @@ Shape shape_of(int L, int p) {
     return s;
 }
 
+// The untuned slot tile of a shape: all R slot groups in one pass, unless that
+// kernel keeps fewer than three waves per SIMD resident and the half tile keeps
+// more (the half tile ballots the planes twice per step, which the extra wave more
+// than pays for there: L = 527, p = 16: 1.10 -> 1.19e11 flip-evals/s; where the full
+// tile already keeps three waves, at L = 387, 451 and 501, the full tile is faster).
+std::map<std::pair<int, int>, int> g_default_rb;   // guarded by g_mu
+
+int default_rb(const Shape& s) {
+    const int half = (s.R + 1) / 2;
+    if (half == s.R) return s.R;
+    WalkKernels full, hk;
+    if (!walk_kernels_lookup(s.NW, s.R, s.R, &full) || !walk_kernels_lookup(s.NW, s.R, half, &hk) ||
+        full.RB != s.R || hk.RB != half)
+        return s.R;
+    int bf = 0, bh = 0;   // resident one-wave workgroups per CU (four SIMDs)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bf, (const void*)full.plain, 64, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&bh, (const void*)hk.plain, 64, 0) != hipSuccess)
+        return s.R;
+    return (bf < 12 && bh > bf) ? half : s.R;
+}
+
 Tile tile_for(const Shape& s) {
     std::lock_guard<std::mutex> g(g_mu);
     auto it = g_tiles.find({s.NW, s.R});
     if (it != g_tiles.end()) return it->second;
-    return Tile{s.R, 2, 0.0};
+    auto d = g_default_rb.find({s.NW, s.R});
+    if (d == g_default_rb.end()) d = g_default_rb.emplace(std::make_pair(s.NW, s.R), default_rb(s)).first;
+    return Tile{d->second, 2, 0.0};
 }
 
 int cu_count() {

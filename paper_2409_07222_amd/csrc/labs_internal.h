@@ -50,6 +50,16 @@ extern "C" __device__ unsigned int __ockl_wfred_or_u32(unsigned int);
 extern "C" __device__ int __ockl_wfred_add_i32(int);
 extern "C" __device__ unsigned int __ockl_wfred_max_u32(unsigned int);
 extern "C" __device__ int __ockl_wfred_max_i32(int);
+extern "C" __device__ int __ockl_wfscan_add_i32(int, bool);
+
+// popcount(x) + acc in one instruction: bit-plane sums chain through the
+// accumulator operand of v_bcnt_u32_b32 (written out, because the compiler splits
+// such chains into separate popcounts and three-way adds)
+__device__ __forceinline__ uint32_t bcnt_add(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
 
 // SplitMix64 (Steele, Lea, Flood 2014): finaliser and the counter form of its
 // stream, output i of the stream started at `key` is mix(key + (i+1)*gamma).

@@ -1843,8 +1843,12 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
             const uint32_t lo = (uint32_t)bal, hi = (uint32_t)(bal >> 32);
 #pragma unroll
             for (int r = 0; r < R2; ++r) {
-                acc[r] += __popc(lo & F[r][2 * q]) + __popc(lo & B[r][2 * q]);
-                if (2 * q + 1 < NW2) acc[r] += __popc(hi & F[r][2 * q + 1]) + __popc(hi & B[r][2 * q + 1]);
+                acc[r] = bcnt_add(lo & F[r][2 * q], acc[r]);
+                acc[r] = bcnt_add(lo & B[r][2 * q], acc[r]);
+                if (2 * q + 1 < NW2) {
+                    acc[r] = bcnt_add(hi & F[r][2 * q + 1], acc[r]);
+                    acc[r] = bcnt_add(hi & B[r][2 * q + 1], acc[r]);
+                }
             }
         }
         const int wgt = (jp == nb - 1) ? -(1 << jp) : (1 << jp);

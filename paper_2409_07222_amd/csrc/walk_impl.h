@@ -23,13 +23,11 @@ struct Lds {
     uint32_t pkbest[32];
 };
 
+// Inclusive prefix sum over the wavefront (the device library's scan: DPP row
+// shifts and broadcasts, no LDS permutes).
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int u = __shfl_up(v, o, 64);
-        if (lane >= o) v += u;
-    }
-    return v;
+    (void)lane;
+    return __ockl_wfscan_add_i32(v, true);
 }
 
 // Fill sv, V, VR from the packed sequence held in S.pk.
@@ -143,14 +141,6 @@ __device__ __forceinline__ void build_windows(const Lds<NW>& S, int p, int k, in
 // RB: fewer window registers, the bit planes re-ballotted once per group).
 // BL: self-avoidance by the walker's Bloom filter (copied into `bl` in LDS for
 // the segment) instead of the tabu tenure.
-// popcount(x) + acc in one instruction: the plane sums chain through the
-// accumulator operand of v_bcnt_u32_b32 instead of separate adds
-__device__ __forceinline__ uint32_t bcnt_add(uint32_t x, uint32_t acc) {
-    uint32_t r;
-    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
-    return r;
-}
-
 template <int NW, int R, int RB, bool BL>
 __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>& S, uint32_t* bl) {
     constexpr int NQ = (NW + 1) / 2;
