@@ -170,6 +170,20 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
     int32_t Ch[NQ];   // (C_{2m} - 1)/2 on valid lags, 0 beyond; kept beside C
 #pragma unroll
     for (int q = 0; q < NQ; ++q) Ch[q] = (64 * q + lane + 1 <= K) ? (C[q] - 1) >> 1 : 0;
+    // +1 digits at even (ones0) and odd (ones1) positions, kept through the walk: a
+    // slot's windows F_a and B_a cover every other position of a's parity, so
+    // together they hold (ones of a's parity) - [s_a = +1] set bits
+    int ones0, ones1;
+    {
+        int c0 = 0, c1 = 0;
+        for (int x = 1 + lane; x <= L; x += 64)
+            if (S.sv[PADL + x] > 0) {
+                if (x & 1) ++c1;
+                else ++c0;
+            }
+        ones0 = __ockl_wfred_add_i32(c0);
+        ones1 = __ockl_wfred_add_i32(c1);
+    }
     int32_t tabu[R];
     uint64_t zr[R];        // Bloom: Zobrist entry of each slot's position
     uint64_t hk = 0;       // Bloom: key of the current sequence
@@ -279,12 +293,9 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
             }
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                int pf = 0;
-#pragma unroll
-                for (int w = 0; w < NW; ++w) pf += __popc(F[r][w]);
-#pragma unroll
-                for (int w = 0; w < NQ - 1; ++w) pf += __popc(B[r][w]);
-                if (bfull) pf += __popc(B[r][NQ - 1]);
+                int a = p + 1 + lane + 64 * (gi * RB + r);
+                if (a > k + 1) a = k + 1;
+                const int pf = ((a & 1) ? ones1 : ones0) - (S.sv[PADL + a] > 0 ? 1 : 0);
                 H[r] = 2 * (H[r] - bias * pf) + pf;
             }
 #pragma unroll
@@ -377,6 +388,11 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
         const int s_as = S.sv[PADL + as];
         const int s_bs = S.sv[PADL + bs];
         const int mps = k + 1 - as;
+        {
+            const int dn = -s_as - (cen ? 0 : s_bs);   // as and bs share a parity (L + 1 is even)
+            if (as & 1) ones1 += dn;
+            else ones0 += dn;
+        }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int m = 64 * q + lane + 1;
