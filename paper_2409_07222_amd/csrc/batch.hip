@@ -454,7 +454,7 @@ labs_status autotune_step1(const int32_t* Ls, int n_L, int p, int walkers, int s
         hipEventCreate(&b);
         labs_status s = LABS_OK;
         for (int rb : rbs)
-            for (int waves : {1, 2, 4, 8}) {
+            for (int waves : {1, 2, 3, 4, 8}) {
                 Tile t{rb, waves, 0};
                 s = batch_walk(&c, 1, &o, ws, bl.total, st, &t, false);   // warm-up
                 if (s != LABS_OK) break;

@@ -496,16 +496,19 @@ __global__ __launch_bounds__(64) void k_walk_bloom(WalkArgs A) {
 // Persistent form: each wavefront takes (configuration, walker) items from a
 // queue until it is empty, so every wavefront exits.
 template <int NW, int R, int RB>
-__global__ __launch_bounds__(64) void k_walk_persistent(const WalkArgs* args, const int2* items,
+__global__ __launch_bounds__(64) void k_walk_persistent(const WalkArgs* __restrict__ args, const int2* items,
                                                         int n_items, unsigned* head) {
     __shared__ Lds<NW> S;
     for (;;) {
         unsigned it = 0;
         if (threadIdx.x == 0) it = atomicAdd(head, 1u);
-        it = __shfl(it, 0, 64);
+        // a wave-uniform item (readfirstlane, not a shuffle), so the item and its
+        // configuration's arguments load into scalar registers as a plain launch's do
+        it = __builtin_amdgcn_readfirstlane(it);
         if (it >= (unsigned)n_items) break;
         const int2 w = items[it];
-        const WalkArgs A = args[w.x];
+        // by reference: the fields load on demand, as from a plain launch's arguments
+        const WalkArgs& A = args[__builtin_amdgcn_readfirstlane(w.x)];
         walk_body<NW, R, RB, false>(A, (int64_t)w.y, S, nullptr);
     }
 }

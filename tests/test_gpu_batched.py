@@ -83,7 +83,7 @@ def test_autotune_and_half_tile_parity(lb, orc, tmp_path):
     assert len(tab["walker_tiles"]) >= 2
     for t in tab["walker_tiles"]:
         assert t["RB"] in (t["R"], (t["R"] + 1) // 2)
-        assert t["waves_per_simd"] in (1, 2, 4, 8)
+        assert t["waves_per_simd"] in (1, 2, 3, 4, 8)
     # force RB = ceil(R/2) for L = 101's class and L = 501's class
     forced = {"walker_tiles": []}
     for L, p in ((101, 8), (501, 16), (131, 1)):
