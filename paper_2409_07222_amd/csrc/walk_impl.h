@@ -479,8 +479,16 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
 }
 
 
+// Waves per SIMD the compiler is held to for a plain walk kernel.  (9, 4, 4) needs
+// 184 VGPRs left free (two waves); held to 168 (three waves) it spills two and runs
+// faster: L = 527, p = 16: 1.24 -> 1.32e11 flip-evals/s.
 template <int NW, int R, int RB>
-__global__ __launch_bounds__(64) void k_walk(WalkArgs A) {
+struct WalkWaves {
+    static constexpr int value = (NW == 9 && R == 4 && RB == 4) ? 3 : 1;
+};
+
+template <int NW, int R, int RB>
+__global__ __launch_bounds__(64, (WalkWaves<NW, R, RB>::value)) void k_walk(WalkArgs A) {
     __shared__ Lds<NW> S;
     walk_body<NW, R, RB, false>(A, blockIdx.x, S, nullptr);
 }
