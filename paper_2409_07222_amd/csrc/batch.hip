@@ -42,10 +42,11 @@ Shape shape_of(int L, int p) {
 }
 
 // The untuned slot tile of a shape: all R slot groups in one pass, unless that
-// kernel keeps fewer than three waves per SIMD resident and the half tile keeps
-// more (the half tile ballots the planes twice per step, which the extra wave more
-// than pays for there: L = 527, p = 16: 1.10 -> 1.19e11 flip-evals/s; where the full
-// tile already keeps three waves, at L = 387, 451 and 501, the full tile is faster).
+// kernel keeps at most three waves per SIMD resident and the half tile keeps more
+// (the half tile ballots the planes twice per step, which the extra wave more than
+// pays for there: L = 409, p = 12, three against four waves: 1.30 -> 1.34e11
+// flip-evals/s; where both keep three, at L = 451, 501 and 527, or the full tile
+// keeps four, at L = 387, the full tile is faster).
 std::map<std::pair<int, int>, int> g_default_rb;   // guarded by g_mu
 
 int default_rb(const Shape& s) {
@@ -59,7 +60,7 @@ int default_rb(const Shape& s) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bf, (const void*)full.plain, 64, 0) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&bh, (const void*)hk.plain, 64, 0) != hipSuccess)
         return s.R;
-    return (bf < 12 && bh > bf) ? half : s.R;
+    return (bf <= 12 && bh > bf) ? half : s.R;
 }
 
 Tile tile_for(const Shape& s) {

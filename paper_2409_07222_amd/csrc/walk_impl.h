@@ -479,12 +479,17 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A, int64_t j, Lds<NW>&
 }
 
 
-// Waves per SIMD the compiler is held to for a plain walk kernel.  (9, 4, 4) needs
-// 184 VGPRs left free (two waves); held to 168 (three waves) it spills two and runs
-// faster: L = 527, p = 16: 1.24 -> 1.32e11 flip-evals/s.
+// Waves per SIMD the compiler is held to for a plain walk kernel, where a kernel
+// left free lands a few VGPRs above an occupancy step and runs faster held below it
+// despite a few spilled registers (flip-evals/s, 8,000 steps):
+//   (9, 4, 4) 184 -> 168 VGPRs, three waves: L = 527, p = 16: 1.24 -> 1.32e11
+//   (7, 3, 3) 137 -> 128 VGPRs, four waves:  L = 387, p = 12: 1.51 -> 1.66e11
+//   (7, 4, 2) 139 -> 128 VGPRs, four waves:  L = 409, p = 12: 1.23 -> 1.34e11
 template <int NW, int R, int RB>
 struct WalkWaves {
-    static constexpr int value = (NW == 9 && R == 4 && RB == 4) ? 3 : 1;
+    static constexpr int value = (NW == 9 && R == 4 && RB == 4)                            ? 3
+                                 : (NW == 7 && ((R == 3 && RB == 3) || (R == 4 && RB == 2))) ? 4
+                                                                                             : 1;
 };
 
 template <int NW, int R, int RB>
