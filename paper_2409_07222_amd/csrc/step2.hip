@@ -457,9 +457,38 @@ __device__ __forceinline__ void push_pending(const Params& P, bool take, const P
 // DEAD when a lower-numbered pivot of the round produces the same sequence
 // (`repeated`) or when H holds its sequence as OPEN or CLOSED; otherwise it is a
 // new entry.  `taken`, `mn` and `mx` accumulate per thread.
-__device__ void stage_neighbour(const Params& P, int cur, long long batch_begin, bool valid, bool repeated,
-                                unsigned long long key, int ps, int flip, int32_t En, int& taken,
-                                int32_t& mn, int32_t& mx, int home_tag = -1) {
+// Words a sequence compare or copy loads together before it uses them (a loop that
+// uses each word as it loads it waits for every load in turn); small, as the
+// registers they take count against every kernel's occupancy.
+constexpr int kWordChunk = 4;
+
+// Whether table slot s holds pivot slot ps's sequence with element `flip` (1-based)
+// flipped.  The pivot's words come from `pkl` (a copy in LDS) when given, else from
+// its table row.
+__device__ __forceinline__ bool flip_equal(const Params& P, uint64_t s, int ps, int flip, const uint32_t* pkl) {
+    const int W = P.H.W;
+    const uint32_t* row = P.H.seq + s * W;
+    const uint32_t* pr = P.H.seq + (size_t)ps * W;
+    const int fw = (flip - 1) >> 5;
+    const uint32_t fm = 1u << (31 - ((flip - 1) & 31));
+    bool eq = true;
+    for (int w0 = 0; w0 < W && eq; w0 += kWordChunk) {
+        uint32_t a[kWordChunk], b[kWordChunk];
+#pragma unroll
+        for (int w = 0; w < kWordChunk; ++w) {
+            a[w] = w0 + w < W ? row[w0 + w] : 0u;
+            b[w] = w0 + w < W ? (pkl ? pkl[w0 + w] : pr[w0 + w]) : 0u;
+        }
+#pragma unroll
+        for (int w = 0; w < kWordChunk; ++w) eq &= (a[w] ^ b[w]) == (w0 + w == fw ? fm : 0u);
+    }
+    return eq;
+}
+
+__device__ __forceinline__ void stage_neighbour(const Params& P, int cur, long long batch_begin, bool valid,
+                                                bool repeated, unsigned long long key, int ps, int flip,
+                                                int32_t En, int& taken, int32_t& mn, int32_t& mx,
+                                                int home_tag = -1, const uint32_t* pkl = nullptr) {
     if (!valid) return;
     const long long j = (long long)blockIdx.x * P.L + (flip - 1);
     int tomb = -1;
@@ -472,15 +501,10 @@ __device__ void stage_neighbour(const Params& P, int cur, long long batch_begin,
             // the home slot's tag may have been loaded ahead by the caller
             const uint8_t ts = (probe == 0 && home_tag >= 0) ? (uint8_t)home_tag : H.tag[s];
             if (ts == 0) break;
-            if (ts != tg || H.rec[s].key != key) continue;
-            bool eq = true;
-            for (int w = 0; w < H.W; ++w)
-                if (H.seq[s * H.W + w] != src_word(P, ps, flip, w)) {
-                    eq = false;
-                    break;
-                }
-            if (!eq) continue;
-            if (H.rec[s].state == ST_EVICTED) tomb = (int)s;
+            if (ts != tg) continue;
+            const SlotRec rc = H.rec[s];   // key and state in one load (no slot changes here)
+            if (rc.key != key || !flip_equal(P, s, ps, flip, pkl)) continue;
+            if (rc.state == ST_EVICTED) tomb = (int)s;
             else take = false;
             break;
         }
@@ -1874,7 +1898,7 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
         const int G = 2 * H[r] - PC[Mf] - PC[Mb];
         const int Q = (L - 1) + 2 * (M - 2 * dis);
         const int32_t En = Ep - 4 * si * G + 4 * Q;
-        stage_neighbour(P, cur, bb, valid, srep[i - 1] != 0, nkey[r], ps, i, En, taken, mn, mx, htag[r]);
+        stage_neighbour(P, cur, bb, valid, srep[i - 1] != 0, nkey[r], ps, i, En, taken, mn, mx, htag[r], pk);
     }
     stage_finish(P, taken, mn, mx);
 }
@@ -2212,8 +2236,25 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
                         atomicExch(&cg->error, 2);
                         keep[k] = false;
                     } else {
-                        for (int w = 0; w < H.W; ++w)
-                            H.seq[(size_t)slot[k] * H.W + w] = new_word(P, j, w);
+                        uint32_t* dst = H.seq + (size_t)slot[k] * H.W;
+                        if (j < c->n_piv * P.L) {
+                            // a flip of a pivot: its row loaded kWordChunk words at a
+                            // time, then stored
+                            const int ji = (int)j, pi = ji / P.L, fl = ji - pi * P.L;
+                            const uint32_t* src = P.pseq + (size_t)pi * H.W;
+                            const int fw = fl >> 5;
+                            const uint32_t fm = 1u << (31 - (fl & 31));
+                            for (int w0 = 0; w0 < H.W; w0 += kWordChunk) {
+                                uint32_t wv[kWordChunk];
+#pragma unroll
+                                for (int w = 0; w < kWordChunk; ++w) wv[w] = w0 + w < H.W ? src[w0 + w] : 0u;
+#pragma unroll
+                                for (int w = 0; w < kWordChunk; ++w)
+                                    if (w0 + w < H.W) dst[w0 + w] = wv[w] ^ (w0 + w == fw ? fm : 0u);
+                            }
+                        } else {
+                            for (int w = 0; w < H.W; ++w) dst[w] = new_word(P, j, w);
+                        }
                         H.rec[slot[k]].E = ev[k];
                         H.rec[slot[k]].state = ST_OPEN;
                         ++claims;
