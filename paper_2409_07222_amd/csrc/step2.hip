@@ -460,7 +460,7 @@ __device__ __forceinline__ void push_pending(const Params& P, bool take, const P
 // Words a sequence compare or copy loads together before it uses them (a loop that
 // uses each word as it loads it waits for every load in turn); small, as the
 // registers they take count against every kernel's occupancy.
-constexpr int kWordChunk = 4;
+constexpr int kWordChunk = 8;
 
 // Whether table slot s holds pivot slot ps's sequence with element `flip` (1-based)
 // flipped.  The pivot's words come from `pkl` (a copy in LDS) when given, else from
