@@ -2076,11 +2076,21 @@ __global__ __launch_bounds__(kRotThreads) void k_rot_stage(Params P) {
             for (uint64_t probe = 0; probe <= H.mask; ++probe, sl = (sl + 1) & H.mask) {
                 const uint8_t ts = H.tag[sl];
                 if (ts == 0) break;
-                if (ts != tg || H.rec[sl].key != key) continue;
+                if (ts != tg) continue;
+                const SlotRec rc = H.rec[sl];   // key and state in one load
+                if (rc.key != key) continue;
+                // the slot's words kWordChunk at a time against the rotation's in LDS
                 bool eq = true;
-                for (int w = 0; w < W && eq; ++w) eq = H.seq[sl * W + w] == rw[q][w];
+                for (int w0 = 0; w0 < W && eq; w0 += kWordChunk) {
+                    uint32_t a[kWordChunk];
+#pragma unroll
+                    for (int w = 0; w < kWordChunk; ++w) a[w] = w0 + w < W ? H.seq[sl * W + w0 + w] : 0u;
+#pragma unroll
+                    for (int w = 0; w < kWordChunk; ++w)
+                        if (w0 + w < W) eq &= a[w] == rw[q][w0 + w];
+                }
                 if (!eq) continue;
-                if (H.rec[sl].state == ST_EVICTED) tomb = (int)sl;
+                if (rc.state == ST_EVICTED) tomb = (int)sl;
                 else take = false;
                 break;
             }
@@ -2253,7 +2263,22 @@ __global__ __launch_bounds__(kSelThreads) void k_keep(Params P) {
                                     if (w0 + w < H.W) dst[w0 + w] = wv[w] ^ (w0 + w == fw ? fm : 0u);
                             }
                         } else {
-                            for (int w = 0; w < H.W; ++w) dst[w] = new_word(P, j, w);
+                            // a rotation of a pivot: its words computed a few at a time,
+                            // every load of a chunk issued before its stores
+                            const long long jr = j - c->n_piv * P.L;
+                            const int pi = (int)(jr / P.R2), q = (int)(jr - (long long)pi * P.R2);
+                            const uint32_t* src = P.pseq + (size_t)pi * H.W;
+                            const int sh = rot_shift(P, q);
+                            constexpr int kc = kWordChunk / 2;   // up to four loads a word
+                            for (int w0 = 0; w0 < H.W; w0 += kc) {
+                                uint32_t wv[kc];
+#pragma unroll
+                                for (int w = 0; w < kc; ++w)
+                                    wv[w] = w0 + w < H.W ? rot_word(src, P.L, H.W, sh, w0 + w) : 0u;
+#pragma unroll
+                                for (int w = 0; w < kc; ++w)
+                                    if (w0 + w < H.W) dst[w0 + w] = wv[w];
+                            }
                         }
                         H.rec[slot[k]].E = ev[k];
                         H.rec[slot[k]].state = ST_OPEN;
