@@ -1716,6 +1716,17 @@ __global__ __launch_bounds__(64) void k_expand_direct(Params P) {
 //   G_i = 2 sum_j w_j (popc(P_j & F_i) + popc(P_j & B_i)) - PC[L-i] - PC[i-1],
 //   Q_i = (L-1) + 2 (M - 2 popc((F_i ^ B_i) & [d <= M])),  M = min(L-i, i-1),
 // PC being the prefix sums of C_d.  C_d itself is (L-d) - 2 popc((V ^ V>>d) & [j < L-d]).
+// Window words that can hold lags in lane group r of the expansion (positions
+// i in [1 + S r, S (r + 1)], S = 64 kExWaves): backward lags reach i - 1 < S (r + 1),
+// forward lags L - i <= 32 NW2 - S r, and the groups before the last hold only
+// valid positions (the last may clamp to i = L, which reaches no forward lag).
+// Words past these are zero for every lane of the group and are skipped.
+constexpr int kExSpanW = 2 * kExWaves;   // 32-bit words per lane group's span
+template <int NW2>
+__device__ constexpr int ex_fwords(int r) { return NW2 - kExSpanW * r > 0 ? NW2 - kExSpanW * r : 0; }
+template <int NW2>
+__device__ constexpr int ex_bwords(int r) { return kExSpanW * (r + 1) < NW2 ? kExSpanW * (r + 1) : NW2; }
+
 template <int NW2, int R2>
 __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
     // The pivot's slot, energy and key (as stored with its slot: lowest bit 1, as
@@ -1850,8 +1861,8 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
         const int sb = N - i + 1, qb = sb >> 5, hb = sb & 31;
 #pragma unroll
         for (int w = 0; w < NW2; ++w) {
-            F[r][w] = __builtin_amdgcn_alignbit(V[qf + w + 1], V[qf + w], hf);
-            B[r][w] = __builtin_amdgcn_alignbit(VR[qb + w + 1], VR[qb + w], hb);
+            F[r][w] = w < ex_fwords<NW2>(r) ? __builtin_amdgcn_alignbit(V[qf + w + 1], V[qf + w], hf) : 0u;
+            B[r][w] = w < ex_bwords<NW2>(r) ? __builtin_amdgcn_alignbit(VR[qb + w + 1], VR[qb + w], hb) : 0u;
         }
     }
     int32_t H[R2];
@@ -1867,12 +1878,10 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
             const uint32_t lo = (uint32_t)bal, hi = (uint32_t)(bal >> 32);
 #pragma unroll
             for (int r = 0; r < R2; ++r) {
-                acc[r] = bcnt_add(lo & F[r][2 * q], acc[r]);
-                acc[r] = bcnt_add(lo & B[r][2 * q], acc[r]);
-                if (2 * q + 1 < NW2) {
-                    acc[r] = bcnt_add(hi & F[r][2 * q + 1], acc[r]);
-                    acc[r] = bcnt_add(hi & B[r][2 * q + 1], acc[r]);
-                }
+                if (2 * q < ex_fwords<NW2>(r)) acc[r] = bcnt_add(lo & F[r][2 * q], acc[r]);
+                if (2 * q < ex_bwords<NW2>(r)) acc[r] = bcnt_add(lo & B[r][2 * q], acc[r]);
+                if (2 * q + 1 < ex_fwords<NW2>(r)) acc[r] = bcnt_add(hi & F[r][2 * q + 1], acc[r]);
+                if (2 * q + 1 < ex_bwords<NW2>(r)) acc[r] = bcnt_add(hi & B[r][2 * q + 1], acc[r]);
             }
         }
         const int wgt = (jp == nb - 1) ? -(1 << jp) : (1 << jp);
@@ -1890,6 +1899,7 @@ __global__ __launch_bounds__(kExThreads) void k_expand(Params P) {
         int dis = 0;
 #pragma unroll
         for (int w = 0; w < NW2; ++w) {
+            if (w >= ex_fwords<NW2>(r) || w >= ex_bwords<NW2>(r)) continue;   // M is below
             const int left = M - 32 * w;
             const uint32_t m = left >= 32 ? 0xffffffffu : (left <= 0 ? 0u : ((1u << left) - 1u));
             dis += __popc((F[r][w] ^ B[r][w]) & m);
