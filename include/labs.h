@@ -240,7 +240,7 @@ labs_status labs_walk_step1_bloom(const labs_step1_cfg* cfg, const labs_bloom* b
  * words of even lags and R = ceil((k+1-p)/64) free positions per lane.  Its tile
  * is RB, the slots a lane scans per pass (R, or ceil(R/2) to free registers for
  * occupancy), and the resident waves per SIMD requested by persistent launches
- * (1, 2, 3, 4 or 8).  Untuned, RB is R unless that kernel keeps fewer than three
+ * (1, 2, 3, 4 or 8).  Untuned, RB is R unless that kernel keeps at most three
  * waves per SIMD resident and the ceil(R/2) kernel keeps more, and persistent
  * launches request 2 waves per SIMD.  labs_autotune_step1 times every candidate tile on the largest
  * length of each class among Ls (host array of n_L odd lengths) with `walkers`
