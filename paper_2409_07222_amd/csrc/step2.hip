@@ -452,11 +452,6 @@ __device__ __forceinline__ void push_pending(const Params& P, bool take, const P
     if (take && o < P.cap_pend) P.pend[o] = pd;
 }
 
-// A generated neighbour (flip position `flip` of the block's pivot, slot ps;
-// energy En; Zobrist key): its Open position is fixed by (pivot, flip).  It is
-// DEAD when a lower-numbered pivot of the round produces the same sequence
-// (`repeated`) or when H holds its sequence as OPEN or CLOSED; otherwise it is a
-// new entry.  `taken`, `mn` and `mx` accumulate per thread.
 // Words a sequence compare or copy loads together before it uses them (a loop that
 // uses each word as it loads it waits for every load in turn); small, as the
 // registers they take count against every kernel's occupancy.
@@ -485,6 +480,13 @@ __device__ __forceinline__ bool flip_equal(const Params& P, uint64_t s, int ps, 
     return eq;
 }
 
+// A generated neighbour (flip position `flip` of the block's pivot, slot ps;
+// energy En; Zobrist key): its Open position is fixed by (pivot, flip).  It is
+// DEAD when a lower-numbered pivot of the round produces the same sequence
+// (`repeated`) or when H holds its sequence as OPEN or CLOSED; otherwise it is a
+// new entry.  `taken`, `mn` and `mx` accumulate per thread; `home_tag` is the home
+// slot's tag when the caller loaded it ahead (else -1), `pkl` the pivot's words in
+// LDS when the caller holds them (else null).
 __device__ __forceinline__ void stage_neighbour(const Params& P, int cur, long long batch_begin, bool valid,
                                                 bool repeated, unsigned long long key, int ps, int flip,
                                                 int32_t En, int& taken, int32_t& mn, int32_t& mx,
