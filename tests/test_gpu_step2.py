@@ -58,6 +58,18 @@ def test_step2_parity(lb, orc, L, n, B, Q, X, T_u):
     _run_both(lb, orc, L, cands, B, Q, X, T_u)
 
 
+@pytest.mark.parametrize("L", [257, 385, 386, 512, 513, 545, 546, 641])
+def test_step2_expansion_shapes(lb, orc, L):
+    """Each bit-sliced expansion kernel at the ends of its length range: 257 (two
+    lane groups of 256 positions, the first full), 385 / 386 (12 / 16 lag words),
+    512 / 513 (two / three groups), 545 / 546 (17 / 20 words) and 641 (the
+    longest before the direct expansion).  A group's window words past the lags its
+    positions reach are skipped, so these lengths put the last reachable word at
+    every boundary the skip depends on."""
+    cands = li.random_pm1(L * 7 + 2, 2, L)
+    _run_both(lb, orc, L, cands, 4, 200, 16 if L > 400 else 24, 1 << 40)
+
+
 def test_step2_table_rebuild(lb, orc):
     """More distinct sequences pass through Open than half of the hash set holds
     (9,699 in this run against 8,192 of the 16,384 slots sized for L = 33, batch 1,
@@ -140,6 +152,7 @@ def test_step2_zero_budget(lb, orc):
     (33, 5, 3, 64, 150, 12, 1),                # dynamic depth stop
     (101, 6, 64, 3000, 1500, 300, 8),
     (200, 2, 32, 500, 400, 1 << 40, 32),       # the largest T_r
+    (527, 2, 4, 200, 16, 1 << 40, 4),          # three lane groups of the bit-sliced expansion
     (701, 2, 4, 200, 16, 1 << 40, 4),          # direct expansion
     (1023, 2, 2, 100, 8, 1 << 40, 32),
     (5, 5, 3, 6, 40, 1 << 40, 1),              # exhausted space with rotations
