@@ -114,6 +114,8 @@ def test_walk_cfg1_trajectories(lb, orc):
     (143, 2, 200, 14, 28, 4),     # k = 71: seven lags in the last word
     (259, 8, 100, 25, 50, 2),     # k = 129: five words, one lag in the last
     (527, 16, 20, 52, 105, 2),    # k = 263: nine words, four slot groups
+    (409, 12, 30, 40, 81, 2),     # k = 204: seven words, four slot groups (the half tile, held to four waves)
+    (449, 12, 30, 44, 89, 2),     # k = 224: seven full words, four slot groups
 ])
 def test_walk_shapes(lb, orc, L, p, steps, lo, hi, n):
     _compare_walk(lb, orc, L, p, steps, lo, hi, 7 + L, n)
